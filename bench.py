@@ -1,0 +1,261 @@
+"""Benchmark of the plain wedge-sampling path on one MI355X.
+
+Workload: Graph500 R-MAT, scale 24, edge factor 16 (a, b, c, d = 0.57, 0.19,
+0.19, 0.05), seed 7, ids relabelled by a seeded bijection; degree bins with
+tau = omega = 2; eps = delta = 1e-3, so k = 3,800,452 Hoeffding samples per
+bin and for the global stream.  Synthetic, generated on the host, uploaded to
+HBM before timing.
+
+One step = the whole path on that edge list: wedge_build_csr (degrees and
+sorted adjacency), wedge_bin_counts (bins and sampling index),
+wedge_sample_close (samples and exact closure tests), wedge_estimate
+(FP64 summary), including the two small host reads the path needs (m, and
+the per-bin wedge counts that decide which bins are sampled).
+
+Prints one JSON line.  value = closure checks per second of the whole step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "closure checks/s + s per M edges at fixed CI; learned-CV vs plain samples"
+PEAK_HBM_GBS = 8000.0
+# bytes the sampler must read per sample besides its search: vlist[v] (4),
+# rowptr[v] (8), the two neighbour ids (8), rowptr of both endpoints and
+# their successors (32); plus 4 bytes per adjacency word the search reads.
+BYTES_PER_SAMPLE = 52
+BYTES_PER_PROBE = 4
+PMC_FILE = os.path.join(ROOT, "profiles", "sample_close_rmat_s24_counters.json")
+SAMPLER_SRC = os.path.join(ROOT, "paper_1301_5887_amd", "csrc", "sample.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sampler_hash() -> str:
+    h = hashlib.sha256()
+    for p in (SAMPLER_SRC, os.path.join(ROOT, "paper_1301_5887_amd", "csrc", "rng.hpp")):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--edgefactor", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--delta", type=float, default=1e-3)
+    ap.add_argument("--max-bins", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-samples-per-bin", type=int, default=1 << 17)
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="after timing, run one device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1301_5887_amd import wedge as W
+    from paper_1301_5887_amd.synth import gen
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    n, src, dst = gen.rmat_graph500(args.scale, args.edgefactor, args.seed)
+    log(f"[bench] generated R-MAT s{args.scale} ef{args.edgefactor}: n={n} m_in={len(src)} "
+        f"in {time.time() - t0:.1f}s")
+    d_src = torch.from_numpy(src.view(np.int32)).cuda()
+    d_dst = torch.from_numpy(dst.view(np.int32)).cuda()
+    m_in = len(src)
+    B = args.max_bins
+    k = W.hoeffding_k(args.eps, args.delta)
+    dev = d_src.device
+    lib = W.lib()
+    stream = torch.cuda.current_stream()
+
+    # all buffers allocated once, outside the timed region
+    ws = W.Workspace(dev)
+    ws.get(max(int(lib.wedge_build_csr_workspace(m_in, n)), int(lib.wedge_bin_counts_workspace(n))))
+    rowptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(2 * m_in, dtype=torch.int32, device=dev)
+    info = torch.empty(2, dtype=torch.int64, device=dev)
+    n_b = torch.empty(B, dtype=torch.int64, device=dev)
+    p_b = torch.empty(B, dtype=torch.int64, device=dev)
+    index = W._empty_bytes(int(lib.wedge_index_bytes(n, m_in, B)), dev)
+    q = torch.empty((B + 1) * 4, dtype=torch.int64, device=dev)
+    probe = torch.empty(1, dtype=torch.int64, device=dev)
+    h_info = torch.empty(2, dtype=torch.int64, pin_memory=True)
+    h_nb = torch.empty(B, dtype=torch.int64, pin_memory=True)
+    h_pb = torch.empty(B, dtype=torch.int64, pin_memory=True)
+    h_q = torch.empty((B + 1) * 4, dtype=torch.int64, pin_memory=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+
+    def step():
+        wbuf = ws.buf
+        ev[0].record(stream)
+        W._check(lib.wedge_build_csr(W._ptr(d_src), W._ptr(d_dst), m_in, n, W._ptr(rowptr),
+                                     W._ptr(col), W._ptr(info), W._ptr(wbuf), wbuf.numel(),
+                                     W._stream()))
+        ev[1].record(stream)
+        h_info.copy_(info)
+        m = int(h_info[0])
+        W._check(lib.wedge_bin_counts(W._ptr(rowptr), n, m, 2, 2, B, W._ptr(n_b), W._ptr(p_b),
+                                      W._ptr(index), index.numel(), W._ptr(wbuf), wbuf.numel(),
+                                      W._stream()))
+        ev[2].record(stream)
+        h_nb.copy_(n_b)
+        h_pb.copy_(p_b)
+        pb = h_pb.numpy().view(np.uint64)
+        hk = W.k_for_bins(pb, k)
+        kg = k if int(pb.sum()) > 0 else 0
+        ev[3].record(stream)
+        W._check(lib.wedge_sample_close(W._ptr(rowptr), W._ptr(col), n, m, W._ptr(index), B,
+                                        hk.ctypes.data_as(W._vp), kg, args.seed, 0, W._ptr(q),
+                                        W._ptr(probe), None, 0, W._stream()))
+        ev[4].record(stream)
+        h_q.copy_(q)
+        bi = W.BinIndex(n=n, m=m, tau=2, omega=2, max_bins=B, n_b=n_b, p_b=p_b, index=index,
+                        h_n_b=h_nb.numpy().view(np.uint64).copy(), h_p_b=pb.copy())
+        est = W.estimate(bi, h_q.numpy().view(np.uint64).copy(), hk, kg, args.delta)
+        torch.cuda.synchronize()
+        times = {"build_csr": ev[0].elapsed_time(ev[1]), "bin_counts": ev[1].elapsed_time(ev[2]),
+                 "sample_close": ev[3].elapsed_time(ev[4])}
+        return m, hk, kg, est, times
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup step {i} done")
+    torch.cuda.synchronize()
+    phase = {"build_csr": [], "bin_counts": [], "sample_close": []}
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        m, hk, kg, est, times = step()
+        for kx, vx in times.items():
+            phase[kx].append(vx)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    log(f"[bench] timed {args.steps} steps in {t_total:.3f}s")
+    ms_step = 1000.0 * t_total / args.steps
+    K = int(hk.sum()) + kg
+    probes = int(W.to_host_u64(probe)[0])
+    avg = {kx: float(np.mean(vx)) for kx, vx in phase.items()}
+
+    # roofline of the sampler (dominant kernel of the hot path)
+    alg_bytes = BYTES_PER_SAMPLE * K + BYTES_PER_PROBE * probes
+    achieved = alg_bytes / (avg["sample_close"] / 1000.0) / 1e9
+    traffic = None
+    if os.path.exists(PMC_FILE):
+        with open(PMC_FILE) as f:
+            pmc = json.load(f)
+        if pmc.get("sampler_hash") == sampler_hash() and pmc.get("workload_K") == K:
+            traffic = pmc.get("hbm_bytes_per_launch")
+    roofline = {"kernel": "k_sample_close", "bound": "hbm", "achieved": round(achieved, 2),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 5),
+                "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
+                "probe_loads": probes}
+
+    if args.calibrate_copy_gib > 0:
+        nbytes = int(args.calibrate_copy_gib * (1 << 30))
+        a = torch.empty(nbytes // 4, dtype=torch.int32, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {nbytes} bytes done")
+        del a, b
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(src, dst, n, B, hk, kg, args, W, torch)
+
+    out = {
+        "metric": METRIC,
+        "value": K / (ms_step / 1000.0),
+        "unit": "closure checks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {args.scale}, edgefactor {args.edgefactor}, "
+                               f"Graph500 (0.57,0.19,0.19,0.05), seed {args.seed}; "
+                               f"tau=omega=2; eps=delta={args.eps:g}",
+                   "n": n, "m": int(m), "m_in": m_in, "k_per_bin": k,
+                   "bins_sampled": int((hk > 0).sum()), "k_global": kg, "closure_checks": K},
+        "s_per_M_edges": (ms_step / 1000.0) / (m / 1e6),
+        "s_per_M_edges_without_csr": ((ms_step - avg["build_csr"]) / 1000.0) / (m / 1e6),
+        "sample_close_checks_per_s": K / (avg["sample_close"] / 1000.0),
+        "phase_ms": {kx: round(vx, 4) for kx, vx in avg.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "estimates": {"c": est.glob["c"], "c_global": est.glob["c_global"], "t": est.glob["t"],
+                      "t_global": est.glob["t_global"], "eps": est.glob["eps_global"]},
+        "paper_context": "Hadoop, 32 nodes: 225 s + 0.33 s per million edges",
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(src, dst, n, B, hk, kg, args, W, torch):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    the first `cpu_samples_per_bin` samples of every sampled bin and of the
+    global stream, all host threads.  Its class counts are compared with the
+    GPU's over the same sample range."""
+    from oracle import oracle as O
+
+    t0 = time.time()
+    og = O.build_graph(src, dst, n)
+    log(f"[bench] oracle graph built in {time.time() - t0:.1f}s")
+    ks = np.minimum(hk, np.uint64(args.cpu_samples_per_bin)).astype(np.uint64)
+    kgs = min(kg, args.cpu_samples_per_bin)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t1 = time.perf_counter()
+    s = O.sample(og, 2, 2, B, ks, kgs, args.seed, nthreads=threads)
+    dt = time.perf_counter() - t1
+    Ks = int(ks.sum()) + kgs
+    # the GPU on the same sample range
+    g = W.Csr(n=n, m=og.m, rowptr=None, col=None)
+    match = None
+    try:
+        d_src = torch.from_numpy(src.view(np.int32)).cuda()
+        d_dst = torch.from_numpy(dst.view(np.int32)).cuda()
+        g = W.build_csr(d_src, d_dst, n)
+        bi = W.bin_counts(g, 2, 2, B)
+        so = W.sample_close(g, bi, ks, kgs, args.seed)
+        qg = W.to_host_u64(so.q).reshape(B + 1, 4)
+        match = bool((qg == s.q).all())
+    finally:
+        pass
+    log(f"[bench] oracle sampled {Ks} wedges in {dt:.2f}s ({threads} threads), match={match}")
+    return {"value": Ks / dt, "unit": "closure checks/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {args.cpu_samples_per_bin} samples of each of "
+                      f"{int((ks > 0).sum())} bins and of the global stream ({Ks} checks) "
+                      f"on the same R-MAT scale-{args.scale} graph; oracle graph set-up "
+                      f"{time.time() - t0 - dt:.1f}s not timed",
+            "gpu_counts_match": match}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/* wedge.h -- C ABI of libwedge: wedge sampling of triangle statistics on an
+ * MI355X (gfx950).
+ *
+ * Method: Kolda, Pinar, Plantenga, Seshadhri, Task, "Counting Triangles in
+ * Massive Graphs with MapReduce" (arXiv 1301.5887).  The calls follow the
+ * paper's statement of the problem: an undirected edge list in no particular
+ * order with no meaning given to self-loops or repeats (Sec. 4.1, Sec. 5.1),
+ * degree bins set by (tau, omega) (Sec. 4.2), k samples per bin set by
+ * (eps, delta) (Sec. 3.1), and per-bin and global clustering coefficients and
+ * triangle counts as output (Alg. phase4c, Eq. global_est).
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* or documented "device" are device (HBM) pointers;
+ *    pointers named h_* are host pointers.  The caller owns and allocates
+ *    every buffer (sizes come from the *_workspace / *_bytes queries); the
+ *    library allocates nothing.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *    enqueued asynchronously on it; no call synchronises except
+ *    wedge_index_status, which says so.
+ *  - Return value: WEDGE_OK (0) or a negative wedge_status.  Arguments are
+ *    validated on the host before anything is enqueued; on error nothing is
+ *    enqueued, outputs are untouched and wedge_last_error() returns a message
+ *    (thread-local).  Conditions only the device can see (an edge id >= n,
+ *    a degree whose bin is >= max_bins) are reported in device-side counters
+ *    documented per call.
+ *  - Vertex ids are uint32 (n < 2^32); edge offsets are uint64.
+ */
+#ifndef WEDGE_H
+#define WEDGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WEDGE_OK = 0,
+  WEDGE_EINVAL = -1,     /* null or misaligned pointer, inconsistent arguments */
+  WEDGE_ERANGE = -2,     /* a size or parameter outside the supported range */
+  WEDGE_EWORKSPACE = -3, /* workspace or output buffer smaller than required */
+  WEDGE_EHIP = -4,       /* a HIP runtime call or kernel launch failed */
+  WEDGE_ENOTSUP = -5     /* no usable gfx950 device */
+} wedge_status;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* wedge_last_error(void);
+
+/* Version of this ABI (incremented on any incompatible change). */
+int wedge_abi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Degree binning, Sec. 4.2 (Eqs. binlodeg, binid), integer form.
+ * BinLoDeg(b) = b for b <= tau, else tau + sum_{j<b-tau} omega^j (saturating
+ * at 2^64-1); BinId(d) = max{ b : BinLoDeg(b) <= d } for d >= 1.  With
+ * tau = omega = 2 the bins are {1},{2},{3,4},{5..8},...  Requires tau >= 1
+ * and integer omega >= 2.  Host-only helpers.
+ * ---------------------------------------------------------------------- */
+uint64_t wedge_bin_lo_deg(uint32_t b, uint32_t tau, uint64_t omega);
+uint32_t wedge_bin_id(uint64_t d, uint32_t tau, uint64_t omega);
+
+/* Thm. Hoeffding: k = ceil(0.5 * eps^-2 * ln(2/delta)) samples give
+ * |c_hat - c| < eps with probability >= 1 - delta.  Returns 0 unless
+ * 0 < eps and 0 < delta < 1.  Host-only. */
+uint64_t wedge_hoeffding_k(double eps, double delta);
+
+/* ------------------------------------------------------------------------
+ * wedge_build_csr -- degree per vertex and adjacency (Alg. phase1a and the
+ * input convention of Sec. 4.1: undirected, self-loops and repeats ignored).
+ *
+ * In:  d_src[m_in], d_dst[m_in]  device uint32 edge endpoints, any order.
+ * Out: d_rowptr[n+1]  device uint64; row v of the adjacency is
+ *                     d_col[d_rowptr[v] .. d_rowptr[v+1]), so the degree is
+ *                     d_rowptr[v+1] - d_rowptr[v].
+ *      d_col[2*m_in]  device uint32 capacity; the first 2m entries hold every
+ *                     neighbour of every vertex once, each row ascending.
+ *      d_info[2]      device uint64: [0] = m, the number of distinct
+ *                     undirected non-loop edges; [1] = number of input edges
+ *                     rejected because an endpoint was >= n (they are
+ *                     dropped; the caller decides whether that is an error).
+ * Workspace: wedge_build_csr_workspace(m_in, n) bytes of device memory,
+ * 256-byte aligned, contents ignored on entry.
+ * Errors: EINVAL (null/misaligned pointer), ERANGE (n == 0, m_in >= 2^40),
+ *         EWORKSPACE, EHIP.
+ * ---------------------------------------------------------------------- */
+size_t wedge_build_csr_workspace(uint64_t m_in, uint32_t n);
+int wedge_build_csr(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint32_t n,
+                    uint64_t* d_rowptr, uint32_t* d_col, uint64_t* d_info, void* d_workspace,
+                    size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * wedge_bin_counts -- wedges per vertex and per bin (Alg. phase1b, Sec. 2.1:
+ * p_v = d_v (d_v - 1) / 2, degree-0 vertices ignored) and the sampling index
+ * that draws a centre with probability p_v / p_b (Sec. 3.2).
+ *
+ * In:  d_rowptr[n+1] as produced by wedge_build_csr; m = d_info[0] (sizes
+ *      the index; pass the same n, m, max_bins to wedge_sample_close).
+ * Out: d_n_b[max_bins], d_p_b[max_bins]  device uint64: vertices and wedges
+ *                     per bin (bins 0 and 1 never hold wedges).
+ *      d_index        device blob of wedge_index_bytes(n, m, max_bins) bytes
+ *                     (256-byte aligned): the centres ordered by
+ *                     (degree, id), the table of distinct degrees with their
+ *                     cumulative wedge counts, and per-bin ranges.  Opaque;
+ *                     only wedge_sample_close and wedge_index_status read it.
+ * Workspace: wedge_bin_counts_workspace(n) bytes.
+ * Device-side condition: a degree whose bin is >= max_bins is counted in the
+ * index's overflow counter (read it with wedge_index_status); those vertices
+ * are left out of every bin.
+ * Errors: EINVAL, ERANGE (tau == 0, omega < 2, max_bins == 0 or > 4096),
+ *         EWORKSPACE, EHIP.
+ * ---------------------------------------------------------------------- */
+size_t wedge_index_bytes(uint32_t n, uint64_t m, uint32_t max_bins);
+size_t wedge_bin_counts_workspace(uint32_t n);
+int wedge_bin_counts(const uint64_t* d_rowptr, uint32_t n, uint64_t m, uint32_t tau,
+                     uint64_t omega, uint32_t max_bins, uint64_t* d_n_b, uint64_t* d_p_b,
+                     void* d_index, size_t index_bytes, void* d_workspace,
+                     size_t workspace_bytes, void* stream);
+
+/* Synchronises `stream`, then reads the index header: number of distinct
+ * degrees, vertices whose bin was >= max_bins, samples requested from a bin
+ * without wedges by wedge_sample_close (skipped), and sampler workgroups that
+ * found the index built for a different n, m or max_bins (skipped).  Any
+ * out-pointer may be NULL. */
+int wedge_index_status(const void* d_index, uint32_t* h_num_classes, uint64_t* h_overflow,
+                       uint64_t* h_empty_bin_samples, uint64_t* h_mismatch, void* stream);
+
+/* ------------------------------------------------------------------------
+ * wedge_sample_close -- uniform wedge sampling per bin and exact closure
+ * tests (Thms. cd-est and td-est; Alg. phase2c Sampling; Alg. phase3b;
+ * Alg. phase4c classes).
+ *
+ * For every bin b < max_bins with h_k[b] > 0, samples s = 0..h_k[b]-1 are
+ * drawn from Philox4x64-10 with key (seed, 1) and counter
+ * (s, b, graph_id, r), r = retry round of the uniform-below draw:
+ *   w = U(word 0, p_b) picks the centre v (centres of the bin in
+ *       (degree, id) order, each taking p_v consecutive values of w);
+ *   o = U(word 1, d(d-1)) picks the ordered neighbour pair
+ *       i = o / (d-1), j = r + [r >= i] with r = o mod (d-1), neighbours
+ *       numbered in ascending id order;
+ *   the wedge (a, v, c) is closed iff {a, c} is an edge;
+ *   class = 0 if open, else 1 + [BinId(d_a) = b] + [BinId(d_c) = b].
+ * U(x, N) is Lemire's nearly-divisionless uniform integer on [0, N): when
+ * the low product word falls below 2^64 mod N the draw moves to the same
+ * word of retry round r+1.
+ * A global stream of k_global samples draws from all wedges (counter word 1
+ * = 0xFFFFFFFF); its closed wedges have class 3, open ones class 0.
+ *
+ * In:  d_rowptr, d_col of the graph, its n and m, and d_index built by
+ *      wedge_bin_counts with the same n, m and max_bins; h_k[max_bins] host
+ *      sample counts (0 for bins without wedges).
+ * Out: d_q[(max_bins+1)*4]  device uint64, overwritten: d_q[4b + c] = number
+ *                     of samples of bin b in class c; row max_bins is the
+ *                     global stream.
+ *      d_probe_loads  nullable device uint64[1], overwritten: total number of
+ *                     adjacency words read by the closure searches.
+ *      d_dump         nullable device wedge_sample_rec[(max_bins+1) *
+ *                     dump_per_bin]: record s of row r at r*dump_per_bin + s
+ *                     for s < dump_per_bin; other records untouched.
+ * Samples requested from a bin whose p_b is 0 are skipped and counted in the
+ * index header (wedge_index_status).
+ * Errors: EINVAL, ERANGE (a k above 2^48, max_bins mismatch), EHIP.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t v;   /* centre */
+  uint32_t a;   /* endpoint N(v)[i] */
+  uint32_t c;   /* endpoint N(v)[j] */
+  uint32_t cls; /* 0 open, 1..3 closed with cls vertices in the bin */
+} wedge_sample_rec;
+
+int wedge_sample_close(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
+                       const void* d_index, uint32_t max_bins, const uint64_t* h_k,
+                       uint64_t k_global, uint64_t seed, uint32_t graph_id, uint64_t* d_q,
+                       uint64_t* d_probe_loads, wedge_sample_rec* d_dump, uint64_t dump_per_bin,
+                       void* stream);
+
+/* Same computation with explicit launch shape: `lanes_in_flight` samples per
+ * lane carried through the gather chain together (1, 2, 4 or 8) and
+ * `samples_per_tile` samples per workgroup (rounded up to a multiple of
+ * 256 * lanes_in_flight).  Results are identical for every shape; only the
+ * speed differs.  Used by the autotuner. */
+int wedge_sample_close_tuned(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
+                             uint64_t m, const void* d_index, uint32_t max_bins,
+                             const uint64_t* h_k, uint64_t k_global, uint64_t seed,
+                             uint32_t graph_id, uint64_t* d_q, uint64_t* d_probe_loads,
+                             wedge_sample_rec* d_dump, uint64_t dump_per_bin,
+                             int lanes_in_flight, uint64_t samples_per_tile, void* stream);
+
+/* ------------------------------------------------------------------------
+ * wedge_estimate -- Alg. phase4c summary and Eq. global_est, host FP64, in
+ * this order (no FMA contraction):
+ *   c_b = (q1+q2+q3) / k_b;   t_b = (p_b * (6 q1 + 3 q2 + 2 q3)) / (6 k_b)
+ *   eps_b = sqrt(ln(2/delta) / (2 k_b))
+ *   c = (sum over b ascending of p_b c_b) / p,  t = c p / 3,  p = sum_b p_b
+ *   global stream: c_G = q_G3 / k_G,  t_G = c_G p / 3
+ * Bins with k_b = 0 get c = t = eps = 0 and valid = 0.
+ * In: h_n_b, h_p_b, h_k [max_bins]; h_q[(max_bins+1)*4] as from
+ *     wedge_sample_close.  Out: h_bins[max_bins], *h_global.
+ * Errors: EINVAL (null pointer, delta outside (0,1)).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t bin;
+  uint32_t valid;    /* 1 if the bin was sampled */
+  uint64_t lo_deg;   /* BinLoDeg(bin) */
+  uint64_t n_b, p_b, k_b;
+  uint64_t q[4];
+  double c;          /* estimated closed fraction of the bin's wedges */
+  double t;          /* estimated triangles with a vertex in the bin */
+  double eps;        /* Hoeffding half-width of c at confidence 1 - delta */
+} wedge_bin_estimate;
+
+typedef struct {
+  uint64_t p;        /* total wedges */
+  uint64_t k_global;
+  uint64_t q_global[4];
+  double c;          /* sum_b (p_b/p) c_b */
+  double t;          /* c p / 3 */
+  double c_global;   /* global stream */
+  double t_global;
+  double eps_global;
+  double t_bins_sum; /* sum_b t_b */
+} wedge_global_estimate;
+
+int wedge_estimate(const uint64_t* h_n_b, const uint64_t* h_p_b, const uint64_t* h_q,
+                   const uint64_t* h_k, uint32_t max_bins, uint32_t tau, uint64_t omega,
+                   uint64_t k_global, double delta, wedge_bin_estimate* h_bins,
+                   wedge_global_estimate* h_global);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WEDGE_H */

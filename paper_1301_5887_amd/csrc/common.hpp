@@ -1,0 +1,100 @@
+// Shared host/device helpers of libwedge: status plumbing, launch checks and
+// the index layout that wedge_bin_counts writes and wedge_sample_close reads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/wedge.h"
+
+namespace wedge {
+
+// Thread-local last-error message; set_error returns the status so callers
+// can `return set_error(...)`.
+int set_error(int status, const char* fmt, ...);
+void clear_error();
+
+#define WEDGE_HIP_TRY(expr)                                                        \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      return ::wedge::set_error(WEDGE_EHIP, "%s failed: %s (%s:%d)", #expr,       \
+                                hipGetErrorString(_e), __FILE__, __LINE__);        \
+  } while (0)
+
+#define WEDGE_LAUNCH_CHECK(what)                                                   \
+  do {                                                                             \
+    hipError_t _e = hipGetLastError();                                             \
+    if (_e != hipSuccess)                                                          \
+      return ::wedge::set_error(WEDGE_EHIP, "launch of %s failed: %s", what,       \
+                                hipGetErrorString(_e));                            \
+  } while (0)
+
+inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Number of significant bits of x (0 for x == 0).
+inline int bit_width(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
+
+// ---------------------------------------------------------------- the index
+// Device blob written by wedge_bin_counts.  All sections 256-byte aligned.
+struct IndexHeader {
+  uint32_t n;
+  uint32_t max_bins;
+  uint32_t num_classes;   // distinct degrees present (degree 0 included)
+  uint32_t tau;
+  uint64_t omega;
+  uint64_t class_cap;
+  uint64_t overflow;      // vertices whose bin is >= max_bins
+  uint64_t empty_bin_samples;  // samples asked of a bin with p_b = 0
+  uint64_t mismatch;      // sampler launches whose n / max_bins / m disagree
+  uint64_t pad[25];
+};
+static_assert(sizeof(IndexHeader) == 256, "header is one 256-byte line");
+
+// One row per bin b < max_bins plus row max_bins for the global stream.
+struct BinMeta {
+  uint64_t lo_deg;     // BinLoDeg(b); row max_bins: 2 (all d >= 2)
+  uint64_t hi_deg;     // BinLoDeg(b+1), exclusive; row max_bins: 2^64-1
+  uint64_t n_b;
+  uint64_t p_b;        // wedges in the bin
+  uint64_t cumw_base;  // wedges of all classes before cls_lo
+  uint32_t cls_lo;     // classes of the bin: [cls_lo, cls_hi)
+  uint32_t cls_hi;
+  uint64_t pad[2];
+};
+static_assert(sizeof(BinMeta) == 64, "bin row is 64 bytes");
+
+struct IndexView {
+  IndexHeader* hdr;
+  BinMeta* bins;      // [max_bins + 1]
+  uint32_t* vlist;    // [n] vertices ordered by (degree, id)
+  uint32_t* cls_deg;  // [class_cap] degree of class j (ascending)
+  uint32_t* cls_start;// [class_cap] first position of class j in vlist
+  uint64_t* cls_cumw; // [class_cap] inclusive prefix of count_j * C(d_j, 2)
+};
+
+// Upper bound on the number of distinct degrees of a simple graph with n
+// vertices and m edges: distinct d_1 < ... < d_C sum to at most 2m, so
+// C(C-1)/2 <= 2m; one more for degree 0.
+uint64_t class_capacity(uint32_t n, uint64_t m);
+size_t index_bytes(uint32_t n, uint64_t m, uint32_t max_bins);
+IndexView index_view(void* base, uint32_t n, uint64_t m, uint32_t max_bins);
+
+// Saturating BinLoDeg (host and device).
+__host__ __device__ inline uint64_t bin_lo_deg(uint32_t b, uint32_t tau, uint64_t omega) {
+  if (b <= tau) return b;
+  uint64_t lo = tau, term = 1;
+  for (uint32_t j = 0; j + tau < b; ++j) {
+    uint64_t nlo = lo + term;
+    if (nlo < lo) return ~0ULL;
+    lo = nlo;
+    uint64_t hi = __builtin_mul_overflow(term, omega, &term) ? 1 : 0;
+    if (hi) term = ~0ULL;
+  }
+  return lo;
+}
+
+}  // namespace wedge

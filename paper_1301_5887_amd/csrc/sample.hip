@@ -1,0 +1,394 @@
+// wedge_sample_close: uniform wedge samples per degree bin and exact closure
+// tests (Thm. cd-est / td-est; centre-then-pair construction of Sec. 3.2;
+// pair law of the Sampling procedure of Alg. phase2c; exact edge match of
+// Alg. phase3b; classes q0..q3 of Alg. phase4c).
+//
+// Work layout: every workgroup takes one tile of consecutive sample indices
+// of one bin.  It stages the bin's cumulative-wedge table (one entry per
+// distinct degree, or every S-th entry when the bin has more than the LDS
+// holds) in LDS, then each lane carries U independent samples through the
+// dependent gather chain
+//     Philox -> centre class (LDS search) -> vlist -> rowptr[v] -> col (a, c)
+//            -> rowptr[a], rowptr[c] -> binary search in the shorter row,
+// issuing the loads of its U samples back to back so that U x (waves per CU)
+// chains are in flight per CU.  Class counts are reduced per wave with
+// shuffles, per workgroup in LDS, and added to the bin's four uint64
+// counters with one atomic each: integer sums, so the result does not depend
+// on tiling or scheduling.
+#include "common.hpp"
+#include "rng.hpp"
+#include "scan.hpp"
+
+namespace wedge {
+
+constexpr int kSampWG = 256;
+constexpr int kLdsClasses = 1024;
+constexpr int kMaxTasks = 64;
+constexpr uint32_t kGlobalWord = 0xFFFFFFFFu;
+
+struct Task {
+  uint32_t row;    // row of q / dump: bin id, or max_bins for the global stream
+  uint32_t bword;  // Philox counter word 1: bin id, or 0xFFFFFFFF
+  uint64_t k;      // samples
+  uint64_t tile_begin;
+};
+
+struct SampleArgs {
+  const uint64_t* rowptr;
+  const uint32_t* col;
+  IndexView ix;
+  uint64_t seed;
+  uint64_t spt;  // samples per tile
+  uint64_t dump_per_bin;
+  uint64_t* q;
+  uint64_t* probe_loads;
+  wedge_sample_rec* dump;
+  uint64_t class_cap;
+  uint32_t n;
+  uint32_t max_bins;
+  uint32_t graph_id;
+  uint32_t ntask;
+  Task task[kMaxTasks];
+};
+
+template <int U>
+__global__ __launch_bounds__(kSampWG) void k_sample_close(const SampleArgs A) {
+  __shared__ uint64_t s_cumw[kLdsClasses];
+  __shared__ uint32_t s_deg[kLdsClasses];
+  __shared__ uint32_t s_start[kLdsClasses];
+  __shared__ unsigned long long s_red[5];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const uint64_t tile = blockIdx.x;
+  int e = 0;
+  for (int i = 1; i < (int)A.ntask; ++i)
+    if (A.task[i].tile_begin <= tile) e = i;
+  const uint32_t row = A.task[e].row;
+  const uint64_t bword = A.task[e].bword;
+  const uint64_t s0 = (tile - A.task[e].tile_begin) * A.spt;
+  const uint64_t s1 = min(s0 + A.spt, A.task[e].k);
+  if (s0 >= s1) return;
+  {
+    // the index must have been built for this graph and bin count
+    const IndexHeader* H = A.ix.hdr;
+    if (H->n != A.n || H->max_bins != A.max_bins || H->class_cap != A.class_cap) {
+      if (tid == 0) atomicAdd((unsigned long long*)&A.ix.hdr->mismatch, 1ULL);
+      return;
+    }
+  }
+  const BinMeta M = A.ix.bins[row];
+  if (M.p_b == 0) {
+    if (tid == 0) atomicAdd((unsigned long long*)&A.ix.hdr->empty_bin_samples, s1 - s0);
+    return;
+  }
+  const bool global = (bword == kGlobalWord);
+  const uint32_t ncls = M.cls_hi - M.cls_lo;
+  const uint32_t S = (ncls + kLdsClasses - 1) / kLdsClasses;  // classes per staged group
+  const uint32_t ngroups = (ncls + S - 1) / S;
+  for (uint32_t i = tid; i < ngroups; i += kSampWG) {
+    const uint32_t last = min((i + 1) * S, ncls) - 1;
+    s_cumw[i] = A.ix.cls_cumw[M.cls_lo + last];
+    if (S == 1) {
+      s_deg[i] = A.ix.cls_deg[M.cls_lo + i];
+      s_start[i] = A.ix.cls_start[M.cls_lo + i];
+    }
+  }
+  if (tid < 5) s_red[tid] = 0;
+  __syncthreads();
+
+  const uint64_t seed = A.seed, g = A.graph_id;
+  const uint64_t* __restrict__ rowptr = A.rowptr;
+  const uint32_t* __restrict__ col = A.col;
+  uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;
+  uint64_t probes = 0;
+
+  for (uint64_t base = s0; base < s1; base += (uint64_t)kSampWG * U) {
+    uint64_t s[U], W[U], x1[U], d[U], vi[U], rp[U], lo[U], len[U];
+    uint32_t v[U], a[U], c[U], key[U];
+    uint64_t ia[U], ic[U];
+    bool act[U], found[U];
+    // 1. random words and the centre's wedge index
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s[u] = base + (uint64_t)u * kSampWG + tid;
+      act[u] = s[u] < s1;
+      W[u] = 0;
+      x1[u] = 0;
+      if (act[u]) {
+        const U64x4 o = philox4x64_10(s[u], bword, g, 0, seed, kDomainSample);
+        W[u] = M.cumw_base + below_from(o.w[0], M.p_b, seed, s[u], bword, g, 0);
+        x1[u] = o.w[1];
+      }
+    }
+    // 2. class of the centre: first staged group whose cumulative count
+    //    exceeds W, then (when groups hold several classes) the class inside
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t l = 0, h = ngroups;
+      while (l < h) {
+        const uint32_t mid = (l + h) >> 1;
+        if (s_cumw[mid] > W[u]) h = mid; else l = mid + 1;
+      }
+      uint64_t dd, st, cprev;
+      if (S == 1) {
+        dd = s_deg[l];
+        st = s_start[l];
+        cprev = l > 0 ? s_cumw[l - 1] : M.cumw_base;
+      } else {
+        uint32_t jl = l * S, jh = min((l + 1) * S, ncls);
+        while (jl < jh) {
+          const uint32_t mid = (jl + jh) >> 1;
+          if (A.ix.cls_cumw[M.cls_lo + mid] > W[u]) jh = mid; else jl = mid + 1;
+        }
+        const uint64_t j = (uint64_t)M.cls_lo + jl;
+        dd = A.ix.cls_deg[j];
+        st = A.ix.cls_start[j];
+        cprev = j > 0 ? A.ix.cls_cumw[j - 1] : 0;
+      }
+      d[u] = act[u] ? dd : 2;
+      const uint64_t pv = d[u] * (d[u] - 1) / 2;
+      vi[u] = st + (W[u] - cprev) / pv;
+      if (vi[u] >= A.n) vi[u] = A.n - 1;  // unreachable for a consistent index
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = act[u] ? A.ix.vlist[vi[u]] : 0;
+    // 3. ordered pair of distinct neighbours, numbered in ascending id order
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ia[u] = ic[u] = 0;
+      if (act[u]) {
+        const uint64_t dm1 = d[u] - 1;
+        const uint64_t o = below_from(x1[u], d[u] * dm1, seed, s[u], bword, g, 1);
+        const uint64_t i = o / dm1;
+        const uint64_t r = o - i * dm1;
+        ia[u] = i;
+        ic[u] = r + (r >= i ? 1 : 0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) rp[u] = act[u] ? rowptr[v[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = act[u] ? col[rp[u] + ia[u]] : 0;
+      c[u] = act[u] ? col[rp[u] + ic[u]] : 0;
+    }
+    // 4. closure: search the endpoint in the shorter of the two rows
+    uint64_t da[U], dc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint64_t ra0 = 0, ra1 = 0, rc0 = 0, rc1 = 0;
+      if (act[u]) {
+        ra0 = rowptr[a[u]];
+        ra1 = rowptr[a[u] + 1];
+        rc0 = rowptr[c[u]];
+        rc1 = rowptr[c[u] + 1];
+      }
+      da[u] = ra1 - ra0;
+      dc[u] = rc1 - rc0;
+      const bool in_a = da[u] <= dc[u];
+      lo[u] = in_a ? ra0 : rc0;
+      len[u] = act[u] ? (in_a ? da[u] : dc[u]) : 0;
+      key[u] = in_a ? c[u] : a[u];
+      found[u] = false;
+    }
+    bool more = true;
+    while (more) {
+      uint32_t x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (len[u] > 0) x[u] = col[lo[u] + (len[u] >> 1)];
+      more = false;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (len[u] > 0) {
+          ++probes;
+          const uint64_t h = len[u] >> 1;
+          if (x[u] == key[u]) {
+            found[u] = true;
+            len[u] = 0;
+          } else if (x[u] < key[u]) {
+            lo[u] += h + 1;
+            len[u] -= h + 1;
+          } else {
+            len[u] = h;
+          }
+          more |= len[u] > 0;
+        }
+      }
+    }
+    // 5. class and tallies
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!act[u]) continue;
+      uint32_t cls = 0;
+      if (found[u]) {
+        cls = global ? 3u
+                     : 1u + (M.lo_deg <= da[u] && da[u] < M.hi_deg ? 1u : 0u) +
+                           (M.lo_deg <= dc[u] && dc[u] < M.hi_deg ? 1u : 0u);
+      }
+      cnt0 += cls == 0;
+      cnt1 += cls == 1;
+      cnt2 += cls == 2;
+      cnt3 += cls == 3;
+      if (A.dump && s[u] < A.dump_per_bin) {
+        wedge_sample_rec rec;
+        rec.v = v[u];
+        rec.a = a[u];
+        rec.c = c[u];
+        rec.cls = cls;
+        A.dump[(uint64_t)row * A.dump_per_bin + s[u]] = rec;
+      }
+    }
+  }
+  unsigned long long r0 = wave_sum<unsigned long long>(cnt0);
+  unsigned long long r1 = wave_sum<unsigned long long>(cnt1);
+  unsigned long long r2 = wave_sum<unsigned long long>(cnt2);
+  unsigned long long r3 = wave_sum<unsigned long long>(cnt3);
+  unsigned long long r4 = wave_sum<unsigned long long>(probes);
+  if (lane == 0) {
+    atomicAdd(&s_red[0], r0);
+    atomicAdd(&s_red[1], r1);
+    atomicAdd(&s_red[2], r2);
+    atomicAdd(&s_red[3], r3);
+    atomicAdd(&s_red[4], r4);
+  }
+  __syncthreads();
+  if (tid < 4) {
+    if (s_red[tid]) atomicAdd((unsigned long long*)&A.q[(uint64_t)row * 4 + tid], s_red[tid]);
+  } else if (tid == 4 && A.probe_loads) {
+    atomicAdd((unsigned long long*)A.probe_loads, s_red[4]);
+  }
+}
+
+// Samples in flight per lane and samples per tile; chosen by the caller
+// (autotuner) or by the default below.
+struct SampleTuning {
+  int U;
+  uint64_t spt;
+};
+
+static SampleTuning default_tuning(uint64_t total) {
+  SampleTuning t;
+  t.U = 4;
+  // about 16 tiles per CU of the 256 on the chip, within [1024, 16384]
+  uint64_t spt = total / (256 * 16);
+  const uint64_t unit = (uint64_t)kSampWG * t.U;
+  spt = (spt / unit) * unit;
+  if (spt < unit) spt = unit;
+  if (spt > 16384) spt = 16384;
+  t.spt = spt;
+  return t;
+}
+
+static int launch_tasks(SampleArgs& A, int U, hipStream_t st) {
+  uint64_t tiles = 0;
+  for (uint32_t i = 0; i < A.ntask; ++i) {
+    A.task[i].tile_begin = tiles;
+    tiles += ceil_div(A.task[i].k, A.spt);
+  }
+  if (tiles == 0) return WEDGE_OK;
+  if (tiles > 0x7FFFFFFFULL) return set_error(WEDGE_ERANGE, "wedge_sample_close: too many tiles");
+  switch (U) {
+    case 1: k_sample_close<1><<<(unsigned)tiles, kSampWG, 0, st>>>(A); break;
+    case 2: k_sample_close<2><<<(unsigned)tiles, kSampWG, 0, st>>>(A); break;
+    case 8: k_sample_close<8><<<(unsigned)tiles, kSampWG, 0, st>>>(A); break;
+    default: k_sample_close<4><<<(unsigned)tiles, kSampWG, 0, st>>>(A); break;
+  }
+  WEDGE_LAUNCH_CHECK("k_sample_close");
+  return WEDGE_OK;
+}
+
+int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
+                      const void* d_index, uint32_t max_bins, const uint64_t* h_k,
+                      uint64_t k_global, uint64_t seed, uint32_t graph_id, uint64_t* d_q,
+                      uint64_t* d_probe_loads, wedge_sample_rec* d_dump, uint64_t dump_per_bin,
+                      const SampleTuning* tuning, hipStream_t st) {
+  if (n == 0) return set_error(WEDGE_ERANGE, "wedge_sample_close: n must be >= 1");
+  if (max_bins == 0 || max_bins > 4096)
+    return set_error(WEDGE_ERANGE, "wedge_sample_close: max_bins must be in [1, 4096]");
+  if (!d_rowptr || !d_index || !d_q || !h_k)
+    return set_error(WEDGE_EINVAL, "wedge_sample_close: null pointer");
+  if (!aligned(d_rowptr, 8) || !aligned(d_index, 256) || !aligned(d_q, 8) ||
+      !aligned(d_col, 4) || !aligned(d_probe_loads, 8) || !aligned(d_dump, 16))
+    return set_error(WEDGE_EINVAL, "wedge_sample_close: misaligned pointer");
+  uint64_t total = k_global;
+  for (uint32_t b = 0; b < max_bins; ++b) {
+    if (h_k[b] > (1ULL << 48))
+      return set_error(WEDGE_ERANGE, "wedge_sample_close: k[%u] above 2^48", b);
+    total += h_k[b];
+  }
+  if (k_global > (1ULL << 48)) return set_error(WEDGE_ERANGE, "wedge_sample_close: k_global above 2^48");
+  if (total > 0 && (m == 0 || !d_col))
+    return set_error(WEDGE_EINVAL, "wedge_sample_close: samples requested of a graph without edges");
+  if (d_dump && dump_per_bin == 0) d_dump = nullptr;
+  int rc;
+  if ((rc = fill<uint64_t>(d_q, ((uint64_t)max_bins + 1) * 4, 0, st))) return rc;
+  if (d_probe_loads && (rc = fill<uint64_t>(d_probe_loads, 1, 0, st))) return rc;
+  SampleTuning t = tuning ? *tuning : default_tuning(total);
+  if (t.U != 1 && t.U != 2 && t.U != 4 && t.U != 8) t.U = 4;
+  {
+    const uint64_t unit = (uint64_t)kSampWG * t.U;
+    if (t.spt < unit) t.spt = unit;
+    t.spt = ceil_div(t.spt, unit) * unit;
+  }
+  SampleArgs A;
+  A.rowptr = d_rowptr;
+  A.col = d_col;
+  A.ix = index_view(const_cast<void*>(d_index), n, m, max_bins);
+  A.seed = seed;
+  A.spt = t.spt;
+  A.dump_per_bin = dump_per_bin;
+  A.q = d_q;
+  A.probe_loads = d_probe_loads;
+  A.dump = d_dump;
+  A.graph_id = graph_id;
+  A.n = n;
+  A.max_bins = max_bins;
+  A.class_cap = class_capacity(n, m);
+  A.ntask = 0;
+  for (uint32_t b = 0; b <= max_bins; ++b) {
+    const bool glob = (b == max_bins);
+    const uint64_t k = glob ? k_global : h_k[b];
+    if (k == 0) continue;
+    Task& T = A.task[A.ntask++];
+    T.row = b;
+    T.bword = glob ? kGlobalWord : b;
+    T.k = k;
+    if (A.ntask == kMaxTasks) {
+      if ((rc = launch_tasks(A, t.U, st))) return rc;
+      A.ntask = 0;
+    }
+  }
+  if (A.ntask > 0 && (rc = launch_tasks(A, t.U, st))) return rc;
+  return WEDGE_OK;
+}
+
+}  // namespace wedge
+
+using namespace wedge;
+
+extern "C" int wedge_sample_close(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
+                                  uint64_t m, const void* d_index, uint32_t max_bins,
+                                  const uint64_t* h_k, uint64_t k_global, uint64_t seed,
+                                  uint32_t graph_id, uint64_t* d_q, uint64_t* d_probe_loads,
+                                  wedge_sample_rec* d_dump, uint64_t dump_per_bin, void* stream) {
+  clear_error();
+  return sample_close_impl(d_rowptr, d_col, n, m, d_index, max_bins, h_k, k_global, seed,
+                           graph_id, d_q, d_probe_loads, d_dump, dump_per_bin, nullptr,
+                           (hipStream_t)stream);
+}
+
+extern "C" int wedge_sample_close_tuned(const uint64_t* d_rowptr, const uint32_t* d_col,
+                                        uint32_t n, uint64_t m, const void* d_index,
+                                        uint32_t max_bins, const uint64_t* h_k, uint64_t k_global,
+                                        uint64_t seed, uint32_t graph_id, uint64_t* d_q,
+                                        uint64_t* d_probe_loads, wedge_sample_rec* d_dump,
+                                        uint64_t dump_per_bin, int lanes_in_flight,
+                                        uint64_t samples_per_tile, void* stream) {
+  clear_error();
+  SampleTuning t{lanes_in_flight, samples_per_tile};
+  return sample_close_impl(d_rowptr, d_col, n, m, d_index, max_bins, h_k, k_global, seed,
+                           graph_id, d_q, d_probe_loads, d_dump, dump_per_bin, &t,
+                           (hipStream_t)stream);
+}

@@ -1,0 +1,348 @@
+"""Thin Python binding of libwedge (ctypes).
+
+Argument marshalling only: every step runs in the HIP kernels behind the C
+ABI of ``include/wedge.h``.  PyTorch supplies device memory and the stream.
+There is no CPU fallback: if ``libwedge.so`` is missing or no GPU is
+present, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwedge.so")
+
+_c_u64 = ctypes.c_uint64
+_c_u32 = ctypes.c_uint32
+_vp = ctypes.c_void_p
+
+
+class WedgeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libwedge status {status}: {message}")
+        self.status = status
+
+
+class WedgeSampleRec(ctypes.Structure):
+    _fields_ = [("v", ctypes.c_uint32), ("a", ctypes.c_uint32), ("c", ctypes.c_uint32),
+                ("cls", ctypes.c_uint32)]
+
+
+class WedgeBinEstimate(ctypes.Structure):
+    _fields_ = [("bin", ctypes.c_uint32), ("valid", ctypes.c_uint32), ("lo_deg", _c_u64),
+                ("n_b", _c_u64), ("p_b", _c_u64), ("k_b", _c_u64), ("q", _c_u64 * 4),
+                ("c", ctypes.c_double), ("t", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+class WedgeGlobalEstimate(ctypes.Structure):
+    _fields_ = [("p", _c_u64), ("k_global", _c_u64), ("q_global", _c_u64 * 4),
+                ("c", ctypes.c_double), ("t", ctypes.c_double), ("c_global", ctypes.c_double),
+                ("t_global", ctypes.c_double), ("eps_global", ctypes.c_double),
+                ("t_bins_sum", ctypes.c_double)]
+
+
+# name -> (restype, argtypes); the C-ABI surface declared in include/wedge.h
+SIGNATURES = {
+    "wedge_last_error": (ctypes.c_char_p, []),
+    "wedge_abi_version": (ctypes.c_int, []),
+    "wedge_bin_lo_deg": (_c_u64, [_c_u32, _c_u32, _c_u64]),
+    "wedge_bin_id": (_c_u32, [_c_u64, _c_u32, _c_u64]),
+    "wedge_hoeffding_k": (_c_u64, [ctypes.c_double, ctypes.c_double]),
+    "wedge_build_csr_workspace": (ctypes.c_size_t, [_c_u64, _c_u32]),
+    "wedge_build_csr": (ctypes.c_int, [_vp, _vp, _c_u64, _c_u32, _vp, _vp, _vp, _vp,
+                                       ctypes.c_size_t, _vp]),
+    "wedge_index_bytes": (ctypes.c_size_t, [_c_u32, _c_u64, _c_u32]),
+    "wedge_bin_counts_workspace": (ctypes.c_size_t, [_c_u32]),
+    "wedge_bin_counts": (ctypes.c_int, [_vp, _c_u32, _c_u64, _c_u32, _c_u64, _c_u32, _vp, _vp,
+                                        _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp]),
+    "wedge_index_status": (ctypes.c_int, [_vp, ctypes.POINTER(_c_u32), ctypes.POINTER(_c_u64),
+                                          ctypes.POINTER(_c_u64), ctypes.POINTER(_c_u64), _vp]),
+    "wedge_sample_close": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _vp, _c_u64,
+                                          _c_u64, _c_u32, _vp, _vp, _vp, _c_u64, _vp]),
+    "wedge_sample_close_tuned": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _vp,
+                                                _c_u64, _c_u64, _c_u32, _vp, _vp, _vp, _c_u64,
+                                                ctypes.c_int, _c_u64, _vp]),
+    "wedge_estimate": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_u32, _c_u32, _c_u64, _c_u64,
+                                      ctypes.c_double, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libwedge.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise WedgeError(rc, lib().wedge_last_error().decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_gpu(*tensors):
+    if not torch.cuda.is_available():
+        raise RuntimeError("libwedge needs a GPU (no CPU fallback)")
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensor arguments must live on the GPU")
+
+
+def _u64_tensor(x: torch.Tensor):
+    # torch has no uint64 arithmetic on ROCm for every op; keep int64 storage
+    # (same bits) and reinterpret on the host.
+    return x
+
+
+def _empty_bytes(nbytes: int, device) -> torch.Tensor:
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def to_host_u64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64).copy()
+
+
+# --------------------------------------------------------------- host helpers
+def hoeffding_k(eps: float, delta: float) -> int:
+    return int(lib().wedge_hoeffding_k(eps, delta))
+
+
+def bin_lo_deg(b: int, tau: int, omega: int) -> int:
+    return int(lib().wedge_bin_lo_deg(b, tau, omega))
+
+
+def bin_id(d: int, tau: int, omega: int) -> int:
+    return int(lib().wedge_bin_id(d, tau, omega))
+
+
+# ---------------------------------------------------------------- the path
+@dataclass
+class Csr:
+    n: int
+    m: int
+    rowptr: torch.Tensor   # int64 storage of uint64 [n+1]
+    col: torch.Tensor      # int32 storage of uint32 [>= 2m]
+    rejected: int = 0
+
+
+class Workspace:
+    """Grow-only device scratch reused across calls."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = _empty_bytes(nbytes, self.device)
+        return self.buf
+
+
+def build_csr(src: torch.Tensor, dst: torch.Tensor, n: int, ws: Workspace | None = None,
+              stream=None, sync: bool = True, out: tuple | None = None):
+    """wedge_build_csr.  Returns a Csr (syncs to read m unless sync=False,
+    in which case m is None and info is returned in .rejected as a tensor)."""
+    _require_gpu(src, dst)
+    assert src.dtype == torch.int32 and dst.dtype == torch.int32 and src.numel() == dst.numel()
+    m_in = src.numel()
+    dev = src.device
+    need = int(lib().wedge_build_csr_workspace(m_in, n))
+    wbuf = (ws or Workspace(dev)).get(need)
+    if out is None:
+        rowptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(max(2 * m_in, 1), dtype=torch.int32, device=dev)
+        info = torch.empty(2, dtype=torch.int64, device=dev)
+    else:
+        rowptr, col, info = out
+    _check(lib().wedge_build_csr(_ptr(src), _ptr(dst), m_in, n, _ptr(rowptr), _ptr(col),
+                                 _ptr(info), _ptr(wbuf), wbuf.numel(), _stream(stream)))
+    if not sync:
+        return rowptr, col, info
+    h = to_host_u64(info)
+    return Csr(n=n, m=int(h[0]), rowptr=rowptr, col=col, rejected=int(h[1]))
+
+
+@dataclass
+class BinIndex:
+    n: int
+    m: int
+    tau: int
+    omega: int
+    max_bins: int
+    n_b: torch.Tensor
+    p_b: torch.Tensor
+    index: torch.Tensor
+    h_n_b: np.ndarray | None = None
+    h_p_b: np.ndarray | None = None
+
+
+def bin_counts(g: Csr, tau: int = 2, omega: int = 2, max_bins: int = 64,
+               ws: Workspace | None = None, stream=None, read: bool = True) -> BinIndex:
+    """wedge_bin_counts; with read=True also copies n_b, p_b to the host and
+    checks the overflow counter."""
+    _require_gpu(g.rowptr)
+    dev = g.rowptr.device
+    n_b = torch.empty(max_bins, dtype=torch.int64, device=dev)
+    p_b = torch.empty(max_bins, dtype=torch.int64, device=dev)
+    ib = int(lib().wedge_index_bytes(g.n, g.m, max_bins))
+    index = _empty_bytes(ib, dev)
+    need = int(lib().wedge_bin_counts_workspace(g.n))
+    wbuf = (ws or Workspace(dev)).get(need)
+    _check(lib().wedge_bin_counts(_ptr(g.rowptr), g.n, g.m, tau, omega, max_bins, _ptr(n_b),
+                                  _ptr(p_b), _ptr(index), index.numel(), _ptr(wbuf),
+                                  wbuf.numel(), _stream(stream)))
+    bi = BinIndex(n=g.n, m=g.m, tau=tau, omega=omega, max_bins=max_bins, n_b=n_b, p_b=p_b,
+                  index=index)
+    if read:
+        st = index_status(bi, stream)
+        if st["overflow"]:
+            raise WedgeError(-2, f"{st['overflow']} vertices have a bin >= max_bins={max_bins}")
+        bi.h_n_b = to_host_u64(n_b)
+        bi.h_p_b = to_host_u64(p_b)
+    return bi
+
+
+def index_status(bi: BinIndex, stream=None) -> dict:
+    nc = _c_u32(0)
+    ov, eb, mm = _c_u64(0), _c_u64(0), _c_u64(0)
+    _check(lib().wedge_index_status(_ptr(bi.index), ctypes.byref(nc), ctypes.byref(ov),
+                                    ctypes.byref(eb), ctypes.byref(mm), _stream(stream)))
+    return {"num_classes": nc.value, "overflow": ov.value, "empty_bin_samples": eb.value,
+            "mismatch": mm.value}
+
+
+def k_for_bins(h_p_b: np.ndarray, k: int) -> np.ndarray:
+    """k samples for every bin with wedges (Thm. cd-est), 0 for the rest."""
+    return np.where(np.asarray(h_p_b, dtype=np.uint64) > 0, np.uint64(k),
+                    np.uint64(0)).astype(np.uint64)
+
+
+@dataclass
+class SampleOut:
+    q: torch.Tensor                  # int64 storage [(max_bins+1)*4]
+    probe_loads: torch.Tensor
+    dump: torch.Tensor | None        # int32 [(max_bins+1)*dump_per_bin, 4]
+    h_k: np.ndarray
+    k_global: int
+
+
+def sample_close(g: Csr, bi: BinIndex, h_k: np.ndarray, k_global: int, seed: int,
+                 graph_id: int = 0, dump_per_bin: int = 0, stream=None,
+                 lanes_in_flight: int | None = None, samples_per_tile: int | None = None,
+                 out: SampleOut | None = None) -> SampleOut:
+    """wedge_sample_close (asynchronous)."""
+    _require_gpu(g.rowptr, g.col, bi.index)
+    dev = g.rowptr.device
+    hk = np.ascontiguousarray(h_k, dtype=np.uint64)
+    assert hk.shape[0] == bi.max_bins
+    rows = bi.max_bins + 1
+    if out is None:
+        q = torch.empty(rows * 4, dtype=torch.int64, device=dev)
+        probe = torch.empty(1, dtype=torch.int64, device=dev)
+        dump = (torch.zeros((rows * dump_per_bin, 4), dtype=torch.int32, device=dev)
+                if dump_per_bin > 0 else None)
+        out = SampleOut(q=q, probe_loads=probe, dump=dump, h_k=hk, k_global=k_global)
+    else:
+        out.h_k, out.k_global = hk, k_global
+    hk_p = hk.ctypes.data_as(ctypes.c_void_p)
+    if lanes_in_flight is None and samples_per_tile is None:
+        rc = lib().wedge_sample_close(_ptr(g.rowptr), _ptr(g.col), g.n, g.m, _ptr(bi.index),
+                                      bi.max_bins, hk_p, k_global, seed, graph_id, _ptr(out.q),
+                                      _ptr(out.probe_loads), _ptr(out.dump), dump_per_bin,
+                                      _stream(stream))
+    else:
+        rc = lib().wedge_sample_close_tuned(_ptr(g.rowptr), _ptr(g.col), g.n, g.m,
+                                            _ptr(bi.index), bi.max_bins, hk_p, k_global, seed,
+                                            graph_id, _ptr(out.q), _ptr(out.probe_loads),
+                                            _ptr(out.dump), dump_per_bin,
+                                            int(lanes_in_flight or 4),
+                                            int(samples_per_tile or 4096), _stream(stream))
+    _check(rc)
+    return out
+
+
+@dataclass
+class Estimates:
+    bins: list = field(default_factory=list)     # per bin: dict
+    glob: dict = field(default_factory=dict)
+    q: np.ndarray | None = None
+
+
+def estimate(bi: BinIndex, q: np.ndarray, h_k: np.ndarray, k_global: int,
+             delta: float) -> Estimates:
+    """wedge_estimate (host FP64 inside the library)."""
+    B = bi.max_bins
+    qq = np.ascontiguousarray(q, dtype=np.uint64).reshape(-1)
+    hk = np.ascontiguousarray(h_k, dtype=np.uint64)
+    nb = np.ascontiguousarray(bi.h_n_b, dtype=np.uint64)
+    pb = np.ascontiguousarray(bi.h_p_b, dtype=np.uint64)
+    eb = (WedgeBinEstimate * B)()
+    eg = WedgeGlobalEstimate()
+    _check(lib().wedge_estimate(nb.ctypes.data_as(_vp), pb.ctypes.data_as(_vp),
+                                qq.ctypes.data_as(_vp), hk.ctypes.data_as(_vp), B, bi.tau,
+                                bi.omega, k_global, delta, ctypes.cast(eb, _vp),
+                                ctypes.byref(eg)))
+    out = Estimates(q=qq.reshape(B + 1, 4))
+    for e in eb:
+        out.bins.append({"bin": e.bin, "valid": e.valid, "lo_deg": e.lo_deg, "n_b": e.n_b,
+                         "p_b": e.p_b, "k_b": e.k_b, "q": list(e.q), "c": e.c, "t": e.t,
+                         "eps": e.eps})
+    out.glob = {"p": eg.p, "k_global": eg.k_global, "q_global": list(eg.q_global), "c": eg.c,
+                "t": eg.t, "c_global": eg.c_global, "t_global": eg.t_global,
+                "eps_global": eg.eps_global, "t_bins_sum": eg.t_bins_sum}
+    return out
+
+
+@dataclass
+class PlainResult:
+    csr: Csr
+    bins: BinIndex
+    samples: SampleOut
+    est: Estimates
+
+
+def run_plain(src: torch.Tensor, dst: torch.Tensor, n: int, *, tau: int = 2, omega: int = 2,
+              max_bins: int = 64, k: int | None = None, k_global: int | None = None,
+              eps: float = 1e-3, delta: float = 1e-3, seed: int = 1, graph_id: int = 0,
+              dump_per_bin: int = 0, ws: Workspace | None = None, stream=None) -> PlainResult:
+    """The whole plain path: build_csr -> bin_counts -> sample_close -> estimate.
+    k (per bin) and k_global default to the Hoeffding size for (eps, delta)."""
+    ws = ws or Workspace(src.device)
+    kk = hoeffding_k(eps, delta) if k is None else int(k)
+    kg = kk if k_global is None else int(k_global)
+    g = build_csr(src, dst, n, ws=ws, stream=stream)
+    bi = bin_counts(g, tau, omega, max_bins, ws=ws, stream=stream)
+    hk = k_for_bins(bi.h_p_b, kk)
+    if int(bi.h_p_b.sum()) == 0:
+        kg = 0   # no wedges at all: nothing for the global stream to draw
+    so = sample_close(g, bi, hk, kg, seed, graph_id=graph_id, dump_per_bin=dump_per_bin,
+                      stream=stream)
+    q = to_host_u64(so.q)
+    est = estimate(bi, q, hk, kg, delta)
+    return PlainResult(csr=g, bins=bi, samples=so, est=est)

@@ -1,0 +1,169 @@
+"""The C-ABI library loads, exports every declared symbol, validates its
+arguments on the host, and its host-only helpers match the oracle.  No
+device work is launched here."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1301_5887_amd import wedge as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wedge.h")
+
+EOK, EINVAL, ERANGE, EWORKSPACE = 0, -1, -2, -3
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wedge_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for core in ("wedge_build_csr", "wedge_bin_counts", "wedge_sample_close", "wedge_estimate"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = W.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", W.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\s[TW]\s+(\w+)$", out, flags=re.M))
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(L, name)
+    # the binding's signature table covers the header exactly
+    assert set(W.SIGNATURES) == set(declared_functions())
+
+
+def test_abi_version():
+    assert W.lib().wedge_abi_version() == 1
+
+
+FAKE = ctypes.c_void_p(1 << 20)   # never dereferenced: validation fails first
+FAKE2 = ctypes.c_void_p(2 << 20)
+
+
+def test_build_csr_validation():
+    L = W.lib()
+    ws = L.wedge_build_csr_workspace(100, 10)
+    assert ws > 0
+    rc = L.wedge_build_csr(FAKE, FAKE, 100, 0, FAKE, FAKE, FAKE, FAKE, ws, None)
+    assert rc == ERANGE and b"n must be" in L.wedge_last_error()
+    rc = L.wedge_build_csr(FAKE, FAKE, 100, 10, None, FAKE, FAKE, FAKE, ws, None)
+    assert rc == EINVAL
+    rc = L.wedge_build_csr(None, FAKE, 100, 10, FAKE, FAKE, FAKE, FAKE, ws, None)
+    assert rc == EINVAL
+    rc = L.wedge_build_csr(FAKE, FAKE, 100, 10, ctypes.c_void_p((1 << 20) + 4), FAKE, FAKE, FAKE,
+                           ws, None)
+    assert rc == EINVAL and b"misaligned" in L.wedge_last_error()
+    rc = L.wedge_build_csr(FAKE, FAKE, 100, 10, FAKE, FAKE, FAKE, FAKE, ws - 1, None)
+    assert rc == EWORKSPACE
+    rc = L.wedge_build_csr(FAKE, FAKE, 1 << 40, 10, FAKE, FAKE, FAKE, FAKE, ws, None)
+    assert rc == ERANGE
+
+
+def test_bin_counts_validation():
+    L = W.lib()
+    n, m, B = 1000, 5000, 64
+    ib = L.wedge_index_bytes(n, m, B)
+    ws = L.wedge_bin_counts_workspace(n)
+    args = lambda tau=2, omega=2, B=B, ib=ib, ws=ws: (FAKE, n, m, tau, omega, B, FAKE, FAKE,  # noqa
+                                                      FAKE2, ib, FAKE, ws, None)
+    assert L.wedge_bin_counts(*args(tau=0)) == ERANGE
+    assert L.wedge_bin_counts(*args(omega=1)) == ERANGE
+    assert L.wedge_bin_counts(*args(B=0)) == ERANGE
+    assert L.wedge_bin_counts(*args(B=5000)) == ERANGE
+    assert L.wedge_bin_counts(*args(ib=ib - 1)) == EWORKSPACE
+    assert L.wedge_bin_counts(*args(ws=ws - 1)) == EWORKSPACE
+
+
+def test_sample_close_validation():
+    L = W.lib()
+    k = np.zeros(8, dtype=np.uint64)
+    kp = k.ctypes.data_as(ctypes.c_void_p)
+    rc = L.wedge_sample_close(FAKE, FAKE, 10, 20, FAKE2, 0, kp, 0, 1, 0, FAKE, None, None, 0,
+                              None)
+    assert rc == ERANGE
+    rc = L.wedge_sample_close(FAKE, FAKE, 10, 20, FAKE2, 8, None, 0, 1, 0, FAKE, None, None, 0,
+                              None)
+    assert rc == EINVAL
+    k[3] = (1 << 48) + 1
+    rc = L.wedge_sample_close(FAKE, FAKE, 10, 20, FAKE2, 8, kp, 0, 1, 0, FAKE, None, None, 0,
+                              None)
+    assert rc == ERANGE
+    k[3] = 5
+    rc = L.wedge_sample_close(FAKE, None, 10, 0, FAKE2, 8, kp, 0, 1, 0, FAKE, None, None, 0,
+                              None)
+    assert rc == EINVAL and b"without edges" in L.wedge_last_error()
+
+
+def test_estimate_validation():
+    L = W.lib()
+    z = np.zeros(40, dtype=np.uint64).ctypes.data_as(ctypes.c_void_p)
+    eb = (W.WedgeBinEstimate * 4)()
+    eg = W.WedgeGlobalEstimate()
+    assert L.wedge_estimate(z, z, z, z, 4, 2, 2, 0, 0.0, ctypes.cast(eb, ctypes.c_void_p),
+                            ctypes.byref(eg)) == EINVAL
+    assert L.wedge_estimate(None, z, z, z, 4, 2, 2, 0, 0.1, ctypes.cast(eb, ctypes.c_void_p),
+                            ctypes.byref(eg)) == EINVAL
+
+
+def test_host_helpers_match_oracle():
+    for eps, delta in [(1e-3, 1e-3), (0.05, 1e-3), (0.01, 0.05), (0.2, 0.5)]:
+        assert W.hoeffding_k(eps, delta) == O.hoeffding_k(eps, delta)
+    assert W.hoeffding_k(1e-3, 1e-3) == 3_800_452
+    assert W.hoeffding_k(0.0, 0.1) == 0 and W.hoeffding_k(0.1, 1.0) == 0
+    for tau, omega in [(2, 2), (1, 2), (1, 3), (1, 10), (4, 7), (1, 10**7), (500, 2)]:
+        for b in range(0, 80):
+            assert W.bin_lo_deg(b, tau, omega) == O.bin_lo_deg(b, tau, omega)
+        for d in list(range(1, 1200)) + [2**31, 2**32 - 1, 10**12, 2**63]:
+            assert W.bin_id(d, tau, omega) == O.bin_id(d, tau, omega), (tau, omega, d)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_estimate_matches_oracle_bitwise(seed):
+    rng = np.random.default_rng(seed)
+    B = 40
+    p_b = rng.integers(0, 10**13, B, dtype=np.uint64)
+    p_b[rng.random(B) < 0.3] = 0
+    n_b = rng.integers(0, 10**7, B, dtype=np.uint64)
+    k = np.where(p_b > 0, np.uint64(3_800_452), np.uint64(0)).astype(np.uint64)
+    q = np.zeros((B + 1, 4), dtype=np.uint64)
+    for b in range(B):
+        if k[b]:
+            cuts = np.sort(rng.integers(0, int(k[b]) + 1, 3))
+            q[b] = [cuts[0], cuts[1] - cuts[0], cuts[2] - cuts[1], int(k[b]) - cuts[2]]
+    q[B] = [3_000_000, 0, 0, 800_452]
+    delta = 1e-3
+    class BI:  # noqa: N801 - minimal stand-in for the binding's BinIndex
+        pass
+    bi = BI()
+    bi.max_bins, bi.tau, bi.omega, bi.h_n_b, bi.h_p_b = B, 2, 2, n_b, p_b
+    est = W.estimate(bi, q, k, 3_800_452, delta)
+    per_bin, glob = O.estimate(p_b, q, k, 3_800_452, delta)
+    for b in range(B):
+        e = est.bins[b]
+        assert e["c"] == per_bin[b, 0] and e["t"] == per_bin[b, 1] and e["eps"] == per_bin[b, 2]
+        assert e["valid"] == per_bin[b, 3]
+        assert e["lo_deg"] == O.bin_lo_deg(b, 2, 2)
+    assert est.glob["c"] == glob[0] and est.glob["t"] == glob[1]
+    assert est.glob["c_global"] == glob[2] and est.glob["t_global"] == glob[3]
+    assert est.glob["eps_global"] == glob[4] and est.glob["t_bins_sum"] == glob[5]
+    assert math.isclose(est.glob["p"], float(p_b.sum()))
+
+
+def test_no_cpu_fallback_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    t = torch.zeros(4, dtype=torch.int32)
+    with pytest.raises(RuntimeError):
+        W.build_csr(t, t, 4)

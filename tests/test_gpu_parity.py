@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer outputs (CSR, bin table, centre order, every dumped sample, class
+counts) must be bit-identical; FP64 estimates agree to 1e-12 relative
+(they are computed by the same formulas in the same order, so in practice
+they are identical).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1301_5887_amd import wedge as W
+from paper_1301_5887_amd.synth import gen
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def index_vlist(bi, n):
+    """Centre order stored in the index: header (256 B), bin rows
+    ((max_bins+1) x 64 B, padded to 256 B), then vlist[n]."""
+    off = 256 + ((bi.max_bins + 1) * 64 + 255) // 256 * 256
+    raw = bi.index[off:off + 4 * n].cpu().numpy().view(np.uint32)
+    return raw.copy()
+
+
+def run_both(src, dst, n, tau=2, omega=2, B=40, k=1000, kg=None, seed=7, dpb=None,
+             lanes=None, spt=None, graph_id=0):
+    kg = k if kg is None else kg
+    dpb = max(k, kg) if dpb is None else dpb
+    print(f"[parity] n={n} m_in={len(src)} tau={tau} omega={omega} B={B} k={k} kg={kg} "
+          f"seed={seed} lanes={lanes} spt={spt}", flush=True)
+    ws = W.Workspace()
+    g = W.build_csr(dev(src), dev(dst), n, ws=ws)
+    bi = W.bin_counts(g, tau, omega, B, ws=ws)
+    hk = W.k_for_bins(bi.h_p_b, k)
+    if int(bi.h_p_b.sum()) == 0:
+        kg = 0   # no wedges at all: nothing for the global stream to draw
+    so = W.sample_close(g, bi, hk, kg, seed, graph_id=graph_id, dump_per_bin=dpb,
+                        lanes_in_flight=lanes, samples_per_tile=spt)
+    torch.cuda.synchronize()
+    st = W.index_status(bi)
+    assert st["mismatch"] == 0 and st["empty_bin_samples"] == 0 and st["overflow"] == 0
+    q = W.to_host_u64(so.q).reshape(B + 1, 4)
+    dump = so.dump.cpu().numpy().view(np.uint32).reshape(B + 1, dpb, 4) if dpb else None
+    og = O.build_graph(src, dst, n)
+    return dict(g=g, bi=bi, hk=hk, kg=kg, q=q, dump=dump, so=so, og=og, seed=seed, tau=tau,
+                omega=omega, B=B, dpb=dpb, graph_id=graph_id)
+
+
+def check_all(r, check_dump=True):
+    g, bi, og, B = r["g"], r["bi"], r["og"], r["B"]
+    tau, omega = r["tau"], r["omega"]
+    # a1: CSR
+    assert g.m == og.m
+    rp = W.to_host_u64(g.rowptr)
+    assert (rp == og.rowptr).all()
+    col = g.col[: 2 * g.m].cpu().numpy().view(np.uint32)
+    assert (col == og.col).all()
+    # a2: bins and centre order
+    n_b, p_b = O.bins(og, tau, omega, B)
+    assert (bi.h_n_b == n_b).all() and (bi.h_p_b == p_b).all()
+    order = O.center_order(og)
+    vl = index_vlist(bi, og.n)
+    assert (vl[og.n - order.shape[0]:] == order).all()
+    # a3-a5: samples and class counts
+    assert ((r["hk"] > 0) == (p_b > 0)).all()
+    dpb = r["dpb"] if check_dump else 0
+    s = O.sample(og, tau, omega, B, r["hk"], r["kg"], r["seed"], graph_id=r["graph_id"],
+                 dump_per_bin=dpb)
+    assert (r["q"] == s.q).all(), (r["q"], s.q)
+    if check_dump and dpb:
+        for row in range(B + 1):
+            kk = r["kg"] if row == B else int(r["hk"][row])
+            lim = min(kk, dpb)
+            if lim == 0:
+                continue
+            gd = r["dump"][row, :lim]
+            assert (gd[:, 0] == s.v[row, :lim]).all(), row
+            assert (gd[:, 1] == s.a[row, :lim]).all(), row
+            assert (gd[:, 2] == s.c[row, :lim]).all(), row
+            assert (gd[:, 3] == s.cls[row, :lim]).all(), row
+    # a6: estimates
+    est = W.estimate(bi, r["q"], r["hk"], r["kg"], 1e-3)
+    per_bin, glob = O.estimate(p_b, s.q, r["hk"], r["kg"], 1e-3)
+    for b in range(B):
+        for key, j in (("c", 0), ("t", 1), ("eps", 2)):
+            assert abs(est.bins[b][key] - per_bin[b, j]) <= REL * max(1.0, abs(per_bin[b, j]))
+    for key, j in (("c", 0), ("t", 1), ("c_global", 2), ("t_global", 3)):
+        assert abs(est.glob[key] - glob[j]) <= REL * max(1.0, abs(glob[j]))
+    return s
+
+
+def test_worked_example():
+    e = np.array([[1, 2], [1, 3], [2, 4], [3, 4], [3, 5], [4, 5], [4, 6]], dtype=np.uint32)
+    r = run_both(e[:, 0], e[:, 1], 7, tau=2, omega=2, B=8, k=3000, seed=5)
+    check_all(r)
+    # singleton bins of the paper's figure
+    r = run_both(e[:, 0], e[:, 1], 7, tau=4, omega=2, B=8, k=2000, seed=6)
+    check_all(r)
+
+
+def test_chung_lu_small_workload_full_dump():
+    """n = 10^4 heavy-tailed Chung-Lu, k = 10^5 per bin and global: every
+    sample compared."""
+    n, src, dst = gen.chung_lu_c1(1)
+    r = run_both(src, dst, n, tau=2, omega=2, B=40, k=100_000, seed=1)
+    check_all(r)
+
+
+def test_rmat_scale14_ragged_k():
+    n, src, dst = gen.rmat_graph500(14, 16, seed=7)
+    r = run_both(src, dst, n, tau=2, omega=2, B=40, k=12_345, kg=7_777, seed=3)
+    check_all(r)
+
+
+def test_two_level_class_search():
+    """One bin holding > 1024 distinct degrees: the staged table keeps every
+    2nd class and the final step searches HBM."""
+    L = 1100
+    src, dst = [], []
+    for i in range(1, L + 1):           # left vertex L+i-1 joins right 0..i-1
+        src.extend([L + i - 1] * i)
+        dst.extend(range(i))
+    src = np.array(src, dtype=np.uint32)
+    dst = np.array(dst, dtype=np.uint32)
+    n = 2 * L
+    # add a few triangles among the right side so some wedges close
+    extra = np.array([[0, 1], [1, 2], [0, 2], [5, 9], [9, 11]], dtype=np.uint32)
+    src = np.concatenate([src, extra[:, 0]])
+    dst = np.concatenate([dst, extra[:, 1]])
+    r = run_both(src, dst, n, tau=1, omega=10**7, B=4, k=50_000, seed=9)
+    st = W.index_status(r["bi"])
+    assert st["num_classes"] > 1024
+    check_all(r)
+
+
+@pytest.mark.parametrize("lanes,spt", [(1, 256), (2, 1000), (4, 4096), (8, 2048 * 9), (4, 10**6)])
+def test_launch_shape_invariance(lanes, spt):
+    n, src, dst = gen.rmat_graph500(12, 8, seed=5)
+    r = run_both(src, dst, n, B=30, k=20_001, seed=4, lanes=lanes, spt=spt, dpb=512)
+    check_all(r)
+
+
+def test_many_bins_chunked_launches():
+    """Singleton bins (tau >= max degree, Sec. 4.2): more than 64 sampled
+    bins, so the sampler launches in chunks."""
+    n = 3000
+    src, dst, _ = gen.chung_lu(n, 2.0, 2, 400, 30_000, seed=2)
+    r = run_both(src, dst, n, tau=2000, omega=2, B=2100, k=500, seed=12, dpb=64)
+    assert int((r["hk"] > 0).sum()) > 64
+    check_all(r)
+
+
+def test_degenerate_graphs():
+    # only self-loops and repeats: m = 0, nothing to sample
+    src = np.array([0, 1, 1, 2, 2], dtype=np.uint32)
+    r = run_both(src, src, 3, B=8, k=100, dpb=8)
+    assert r["g"].m == 0 and r["q"].sum() == 0
+    check_all(r)
+    # one edge: no wedges
+    r = run_both(np.array([0], np.uint32), np.array([1], np.uint32), 2, B=8, k=100, dpb=8)
+    assert r["bi"].h_p_b.sum() == 0 and r["q"].sum() == 0
+    # star: every wedge open
+    s = 50
+    r = run_both(np.zeros(s, np.uint32), np.arange(1, s + 1, dtype=np.uint32), s + 1, B=10,
+                 k=999, seed=3)
+    check_all(r)
+    assert r["q"][:, 1:].sum() == 0
+    # complete graph: every wedge closed, one bin -> class 3
+    n = 12
+    e = np.array([(i, j) for i in range(n) for j in range(i + 1, n)], dtype=np.uint32)
+    r = run_both(e[:, 0], e[:, 1], n, tau=1, omega=1000, B=4, k=4096, seed=8)
+    check_all(r)
+    assert r["q"][2].tolist() == [0, 0, 0, 4096] and r["q"][4].tolist() == [0, 0, 0, 4096]
+
+
+def test_rejected_ids_and_duplicates():
+    rng = np.random.default_rng(3)
+    n = 500
+    src = rng.integers(0, n + 20, 6000).astype(np.uint32)
+    dst = rng.integers(0, n + 20, 6000).astype(np.uint32)
+    src[:100] = dst[:100]                  # self-loops
+    src[100:300], dst[100:300] = src[300:500], dst[300:500]   # repeats
+    bad = int(((src >= n) | (dst >= n)).sum())
+    r = run_both(src, dst, n, B=20, k=3000, seed=2)
+    assert r["g"].rejected == bad == r["og"].rejected
+    check_all(r)
+
+
+def test_graph_id_and_seed_select_streams():
+    n, src, dst = gen.rmat_graph500(11, 8, seed=1)
+    r1 = run_both(src, dst, n, B=30, k=5000, seed=3, graph_id=0, dpb=64)
+    r2 = run_both(src, dst, n, B=30, k=5000, seed=3, graph_id=5, dpb=64)
+    check_all(r2)
+    assert not (r1["dump"] == r2["dump"]).all()
+
+
+def test_deterministic_repeat():
+    n, src, dst = gen.rmat_graph500(13, 16, seed=2)
+    a = run_both(src, dst, n, B=30, k=40_000, seed=1, dpb=0)
+    b = run_both(src, dst, n, B=30, k=40_000, seed=1, dpb=0)
+    assert (a["q"] == b["q"]).all()
+    assert W.to_host_u64(a["so"].probe_loads)[0] == W.to_host_u64(b["so"].probe_loads)[0]
