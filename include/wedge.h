@@ -226,6 +226,97 @@ int wedge_estimate(const uint64_t* h_n_b, const uint64_t* h_p_b, const uint64_t*
                    uint64_t k_global, double delta, wedge_bin_estimate* h_bins,
                    wedge_global_estimate* h_global);
 
+
+/* ------------------------------------------------------------------------
+ * Batched form: many graphs of uneven size and all their degree bins, with
+ * no host round trip between the steps (so the whole pipeline can be
+ * captured into a HIP graph), one persistent sampler grid for every
+ * (graph, bin) of the batch, and launch shapes chosen by an autotuner.
+ *
+ * Graph g owns input edges [edge_off[g], edge_off[g+1]) of d_src/d_dst with
+ * ids local to the graph (0 <= id < n_g, others rejected), and the global
+ * vertex ids [vert_off[g], vert_off[g+1]) with n_g = vert_off[g+1] -
+ * vert_off[g] >= 1.  Every graph is sampled as by wedge_sample_close with
+ * graph_id = g: bins with wedges get k_per_bin samples, the graph's global
+ * stream k_global (0 when the graph has no wedges).  Sampled vertex ids are
+ * global; the class counts of graph g equal those of the single-graph path
+ * on graph g alone, bit for bit.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t num_graphs;     /* G >= 1 */
+  uint32_t max_bins;       /* bins per graph, 1..4096 */
+  uint32_t tau;            /* >= 1 */
+  uint32_t max_n;          /* largest n_g; must be <= 2^(32 - bits(G-1)) */
+  uint64_t omega;          /* integer >= 2 */
+  uint64_t k_per_bin;      /* samples per bin with wedges, <= 2^48 */
+  uint64_t k_global;       /* samples of each graph's global stream, <= 2^48 */
+  uint64_t seed;           /* Philox key word 0 */
+  uint64_t total_edges;    /* sum of the graphs' input edges, < 2^40 */
+  uint64_t total_vertices; /* sum of n_g, < 2^32 */
+} wedge_batch_desc;
+
+/* Launch shape of the sampler: samples carried together per lane (1, 2, 4
+ * or 8), samples per tile (rounded up to a multiple of 256 * lanes) and
+ * workgroups of the persistent grid (0 = 2048).  Every shape gives the same
+ * counts. */
+typedef struct {
+  int lanes_in_flight;
+  uint32_t samples_per_tile;
+  uint32_t workgroups;
+} wedge_launch_shape;
+
+/* Device workspace for a batch (0 if the descriptor is invalid).  It holds
+ * the block-diagonal CSR, the index, the task table and scratch, and keeps
+ * them between wedge_batch_prepare and wedge_batch_sample. */
+size_t wedge_batch_workspace_bytes(const wedge_batch_desc* d);
+
+/* Degrees, adjacency, bins and index of every graph (Alg. phase1a/1b).
+ * In: d_src, d_dst [total_edges]; d_edge_off [G+1] (uint64, device);
+ * d_vert_off [G+1] (uint32, device).  Out: d_n_b, d_p_b [G * max_bins]. */
+int wedge_batch_prepare(const wedge_batch_desc* d, const uint32_t* d_src, const uint32_t* d_dst,
+                        const uint64_t* d_edge_off, const uint32_t* d_vert_off, uint64_t* d_n_b,
+                        uint64_t* d_p_b, void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* Samples and closure tests of every (graph, bin) of a prepared batch in one
+ * persistent launch (Thms. cd-est/td-est, Alg. phase3b, Alg. phase4c), then
+ * per-graph FP64 estimates on the device.  shape may be NULL (default).
+ * Out: d_q [G * (max_bins+1) * 4] (row g*(max_bins+1) + b; row
+ * g*(max_bins+1) + max_bins = global stream of g); d_probe_loads (nullable)
+ * as in wedge_sample_close; d_est_glob (nullable) [G * 6] = c, t, c_G, t_G,
+ * eps_G, sum_b t_b; d_est_bins (nullable) [G * max_bins * 3] = c_b, t_b,
+ * eps_b, in the order and formulas of wedge_estimate. */
+int wedge_batch_sample(const wedge_batch_desc* d, const wedge_launch_shape* shape, double delta,
+                       uint64_t* d_q, uint64_t* d_probe_loads, double* d_est_glob,
+                       double* d_est_bins, void* d_workspace, size_t workspace_bytes,
+                       void* stream);
+
+/* wedge_batch_prepare followed by wedge_batch_sample. */
+int wedge_batch_run(const wedge_batch_desc* d, const uint32_t* d_src, const uint32_t* d_dst,
+                    const uint64_t* d_edge_off, const uint32_t* d_vert_off,
+                    const wedge_launch_shape* shape, double delta, uint64_t* d_n_b,
+                    uint64_t* d_p_b, uint64_t* d_q, double* d_est_glob, double* d_est_bins,
+                    void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* Captures wedge_batch_run with these arguments into a HIP graph (on a
+ * private stream) and instantiates it; *h_graph receives an opaque handle.
+ * Replays read and write the same buffers. */
+int wedge_batch_graph_create(const wedge_batch_desc* d, const uint32_t* d_src,
+                             const uint32_t* d_dst, const uint64_t* d_edge_off,
+                             const uint32_t* d_vert_off, const wedge_launch_shape* shape,
+                             double delta, uint64_t* d_n_b, uint64_t* d_p_b, uint64_t* d_q,
+                             double* d_est_glob, double* d_est_bins, void* d_workspace,
+                             size_t workspace_bytes, void** h_graph);
+int wedge_batch_graph_launch(void* h_graph, void* stream);
+int wedge_batch_graph_destroy(void* h_graph);
+
+/* Autotuner of the batch sampler: runs every candidate shape `reps` times
+ * on a prepared batch (synchronising), keeps the median time in h_ms[c],
+ * checks that every candidate's counts equal candidate 0's (else EINVAL),
+ * and sets *h_best to the fastest.  d_q_ref, d_q_try: [G*(max_bins+1)*4]. */
+int wedge_batch_autotune(const wedge_batch_desc* d, const wedge_launch_shape* cands, int ncand,
+                         int reps, uint64_t* d_q_ref, uint64_t* d_q_try, void* d_workspace,
+                         size_t workspace_bytes, float* h_ms, int* h_best, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

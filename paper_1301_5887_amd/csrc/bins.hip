@@ -3,11 +3,13 @@
 // integer form, Sec. 4.2), and the index the sampler uses to draw a centre
 // with probability p_v / p_b (Sec. 3.2).
 //
-// The index orders vertices by (degree, id) with a stable radix sort of the
-// keys d<<32|v over the degree digits only.  Because BinId is monotone in
-// the degree, each bin is then one contiguous run, and within it vertices of
-// equal degree form a "class" of equally likely centres: the sampler stores
-// one cumulative wedge count per distinct degree instead of one per vertex.
+// The index orders vertices by (graph, degree, id) with a stable radix sort
+// of the keys g<<gshift | d<<32 | v over the degree and graph digits only.
+// Because BinId is monotone in the degree, each bin of each graph is then
+// one contiguous run, and within it vertices of equal degree form a "class"
+// of equally likely centres: the sampler keeps one cumulative wedge count per
+// (graph, distinct degree) instead of one per vertex.  A single graph is the
+// case G = 1 (no graph digits).
 #include <math.h>
 
 #include "common.hpp"
@@ -16,27 +18,29 @@
 
 namespace wedge {
 
-uint64_t class_capacity(uint32_t n, uint64_t m) {
-  // c distinct positive degrees sum to >= 1 + 2 + ... + c = c(c+1)/2, and
-  // all degrees sum to 2m; degree 0 may add one more class.
-  uint64_t c = (uint64_t)((sqrt(1.0 + 16.0 * (double)m) - 1.0) / 2.0);
-  while ((c + 1) * (c + 2) / 2 <= 2 * m) ++c;
-  while (c > 0 && c * (c + 1) / 2 > 2 * m) --c;
-  uint64_t cap = c + 2;
-  if (cap > (uint64_t)n) cap = n;
+uint64_t class_capacity(uint64_t n_total, uint64_t m_total, uint32_t G) {
+  // In one graph, c distinct positive degrees sum to >= c(c+1)/2 and to
+  // <= 2 m_g, so c_g <= sqrt(4 m_g); summed over G graphs (Cauchy-Schwarz)
+  // sum_g c_g <= sqrt(4 G M).  Degree 0 and one guard entry add 2 per graph.
+  const double s = sqrt(4.0 * (double)G * (double)m_total);
+  uint64_t c = (uint64_t)s + 1;
+  while (c > 0 && (double)(c - 1) * (double)(c - 1) > 4.0 * (double)G * (double)m_total) --c;
+  uint64_t cap = c + 2 * (uint64_t)G + 2;
+  if (cap > n_total) cap = n_total;
   return cap ? cap : 1;
 }
 
-static size_t index_layout(uint32_t n, uint64_t m, uint32_t max_bins, IndexView* v, void* base) {
-  const uint64_t cap = class_capacity(n, m);
+static size_t index_layout(uint64_t n_total, uint64_t m_total, uint32_t G, uint32_t max_bins,
+                           IndexView* v, void* base) {
+  const uint64_t cap = class_capacity(n_total, m_total, G);
   char* c = (char*)base;
   size_t off = 0;
   if (v) v->hdr = (IndexHeader*)(c + off);
   off += sizeof(IndexHeader);
   if (v) v->bins = (BinMeta*)(c + off);
-  off += round_up(sizeof(BinMeta) * ((size_t)max_bins + 1), 256);
+  off += round_up(sizeof(BinMeta) * (size_t)G * ((size_t)max_bins + 1), 256);
   if (v) v->vlist = (uint32_t*)(c + off);
-  off += round_up((size_t)n * 4, 256);
+  off += round_up((size_t)n_total * 4, 256);
   if (v) v->cls_deg = (uint32_t*)(c + off);
   off += round_up(cap * 4, 256);
   if (v) v->cls_start = (uint32_t*)(c + off);
@@ -46,13 +50,14 @@ static size_t index_layout(uint32_t n, uint64_t m, uint32_t max_bins, IndexView*
   return off;
 }
 
-size_t index_bytes(uint32_t n, uint64_t m, uint32_t max_bins) {
-  return index_layout(n, m, max_bins, nullptr, nullptr);
+size_t index_bytes(uint64_t n_total, uint64_t m_total, uint32_t G, uint32_t max_bins) {
+  return index_layout(n_total, m_total, G, max_bins, nullptr, nullptr);
 }
 
-IndexView index_view(void* base, uint32_t n, uint64_t m, uint32_t max_bins) {
+IndexView index_view(void* base, uint64_t n_total, uint64_t m_total, uint32_t G,
+                     uint32_t max_bins) {
   IndexView v;
-  index_layout(n, m, max_bins, &v, base);
+  index_layout(n_total, m_total, G, max_bins, &v, base);
   return v;
 }
 
@@ -73,13 +78,16 @@ __device__ inline uint32_t bin_of(uint64_t d, uint32_t tau, uint64_t omega, uint
 }
 
 __global__ void k_deg_keys(const uint64_t* __restrict__ rowptr, uint32_t n,
-                           uint64_t* __restrict__ keys) {
+                           const uint32_t* __restrict__ voff, uint32_t G, int gshift,
+                           uint64_t dmask, uint64_t* __restrict__ keys) {
   uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; v < n; v += stride) {
     uint64_t d = rowptr[v + 1] - rowptr[v];
-    if (d > 0xFFFFFFFFULL) d = 0xFFFFFFFFULL;
-    keys[v] = (d << 32) | v;
+    if (d > dmask) d = dmask;
+    uint64_t key = (d << 32) | v;
+    if (G > 1) key |= (uint64_t)graph_of(voff, G, (uint32_t)v) << gshift;
+    keys[v] = key;
   }
 }
 
@@ -94,13 +102,14 @@ struct ClassApply {
   const uint64_t* k;
   uint64_t N;
   uint64_t cap;
+  uint64_t dmask;
   IndexView ix;
   __device__ void operator()(uint64_t i, uint64_t prefix, uint64_t first) const {
     const uint64_t x = k[i];
     ix.vlist[i] = (uint32_t)x;
     if (first) {
       if (prefix < cap) {
-        ix.cls_deg[prefix] = (uint32_t)(x >> 32);
+        ix.cls_deg[prefix] = (uint32_t)((x >> 32) & dmask);
         ix.cls_start[prefix] = (uint32_t)i;
       } else {
         atomicAdd((unsigned long long*)&ix.hdr->overflow, 1ULL);
@@ -113,8 +122,8 @@ struct ClassApply {
   }
 };
 
-// wedges of class j: (vertices of degree d_j) * C(d_j, 2)
-__device__ inline uint64_t class_wedges(const IndexView& ix, uint32_t n, uint32_t C, uint64_t j) {
+// wedges of class j: (vertices in the class) * C(d_j, 2)
+__device__ inline uint64_t class_wedges(const IndexView& ix, uint64_t n, uint32_t C, uint64_t j) {
   const uint64_t d = ix.cls_deg[j];
   const uint64_t end = (j + 1 < C) ? ix.cls_start[j + 1] : n;
   const uint64_t cnt = end - ix.cls_start[j];
@@ -123,7 +132,7 @@ __device__ inline uint64_t class_wedges(const IndexView& ix, uint32_t n, uint32_
 
 struct WedgeLoad {
   IndexView ix;
-  uint32_t n;
+  uint64_t n;
   __device__ uint64_t operator()(uint64_t j) const {
     const uint32_t C = ix.hdr->num_classes;
     return j < C ? class_wedges(ix, n, C, j) : 0;
@@ -137,73 +146,90 @@ struct CumwApply {
   }
 };
 
-// One thread per class: add its vertices and wedges to its bin, and record
-// the first class of every bin it starts (first_cls[b] = first class whose
-// bin is >= b; first_cls[max_bins] also counts bins beyond the table).
-__global__ void k_bin_accumulate(IndexView ix, uint32_t n, uint64_t cap, uint32_t tau,
-                                 uint64_t omega, uint32_t max_bins, uint64_t* __restrict__ n_b,
-                                 uint64_t* __restrict__ p_b, uint32_t* __restrict__ first_cls) {
+// Slot of (graph g, bin b) in the fill table: G * (max_bins + 1) slots,
+// slot b = max_bins of a graph standing for "bins >= max_bins".
+__device__ inline uint64_t slot_of(uint32_t g, uint32_t b, uint32_t max_bins) {
+  return (uint64_t)g * (max_bins + 1) + b;
+}
+
+// One thread per class: add its vertices and wedges to its (graph, bin), and
+// record the first class of every slot it starts: first_cls[s] = first
+// class whose slot is >= s.
+__global__ void k_bin_accumulate(IndexView ix, uint64_t n, uint32_t tau, uint64_t omega,
+                                 uint32_t max_bins, const uint32_t* __restrict__ voff, uint32_t G,
+                                 uint64_t* __restrict__ n_b, uint64_t* __restrict__ p_b,
+                                 uint32_t* __restrict__ first_cls) {
   const uint32_t C = ix.hdr->num_classes;
+  const uint64_t nslots = (uint64_t)G * (max_bins + 1);
   uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; j < C; j += stride) {
     const uint64_t d = ix.cls_deg[j];
     const uint64_t end = (j + 1 < C) ? ix.cls_start[j + 1] : n;
     const uint64_t cnt = end - ix.cls_start[j];
+    const uint32_t g = graph_of(voff, G, ix.vlist[ix.cls_start[j]]);
     const uint32_t b = d == 0 ? 0 : bin_of(d, tau, omega, max_bins);
     if (d > 0) {
       if (b >= max_bins) {
         atomicAdd((unsigned long long*)&ix.hdr->overflow, (unsigned long long)cnt);
       } else {
-        atomicAdd((unsigned long long*)&n_b[b], (unsigned long long)cnt);
-        atomicAdd((unsigned long long*)&p_b[b], (unsigned long long)class_wedges(ix, n, C, j));
+        atomicAdd((unsigned long long*)&n_b[(uint64_t)g * max_bins + b], (unsigned long long)cnt);
+        atomicAdd((unsigned long long*)&p_b[(uint64_t)g * max_bins + b],
+                  (unsigned long long)class_wedges(ix, n, C, j));
       }
     }
-    int64_t bprev = -1;
+    const uint64_t s = slot_of(g, b, max_bins);
+    int64_t sprev = -1;
     if (j > 0) {
       const uint64_t dp = ix.cls_deg[j - 1];
-      bprev = dp == 0 ? 0 : bin_of(dp, tau, omega, max_bins);
+      const uint32_t gp = graph_of(voff, G, ix.vlist[ix.cls_start[j - 1]]);
+      sprev = (int64_t)slot_of(gp, dp == 0 ? 0 : bin_of(dp, tau, omega, max_bins), max_bins);
     }
-    for (int64_t bb = bprev + 1; bb <= (int64_t)b; ++bb) first_cls[bb] = (uint32_t)j;
+    for (int64_t t = sprev + 1; t <= (int64_t)s; ++t) first_cls[t] = (uint32_t)j;
     if (j == C - 1)
-      for (uint32_t bb = b + 1; bb <= max_bins; ++bb) first_cls[bb] = C;
+      for (uint64_t t = s + 1; t <= nslots; ++t) first_cls[t] = C;
   }
 }
 
-__global__ void k_bin_finalize(IndexView ix, uint32_t n, uint64_t cap, uint32_t tau,
-                               uint64_t omega, uint32_t max_bins, const uint64_t* __restrict__ n_b,
-                               const uint64_t* __restrict__ p_b,
+// One thread per (graph, row): rows b < max_bins are the bins, row max_bins
+// the graph's global stream (every vertex of the graph with d >= 2).
+__global__ void k_bin_finalize(IndexView ix, uint64_t n, uint64_t cap, uint32_t tau,
+                               uint64_t omega, uint32_t max_bins, uint32_t G,
+                               const uint64_t* __restrict__ n_b, const uint64_t* __restrict__ p_b,
                                const uint32_t* __restrict__ first_cls) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b > max_bins) return;
-  const uint32_t C = ix.hdr->num_classes;
+  const uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t rows = (uint64_t)G * (max_bins + 1);
+  if (f >= rows) return;
+  const uint32_t g = (uint32_t)(f / (max_bins + 1));
+  const uint32_t b = (uint32_t)(f % (max_bins + 1));
   BinMeta mt;
   mt.pad[0] = mt.pad[1] = 0;
   if (b < max_bins) {
     mt.lo_deg = bin_lo_deg(b, tau, omega);
     mt.hi_deg = bin_lo_deg(b + 1, tau, omega);
-    mt.n_b = n_b[b];
-    mt.p_b = p_b[b];
-    mt.cls_lo = first_cls[b];
-    mt.cls_hi = first_cls[b + 1];
+    mt.n_b = n_b[(uint64_t)g * max_bins + b];
+    mt.p_b = p_b[(uint64_t)g * max_bins + b];
+    mt.cls_lo = first_cls[slot_of(g, b, max_bins)];
+    mt.cls_hi = first_cls[slot_of(g, b + 1, max_bins)];
     mt.cumw_base = mt.cls_lo > 0 ? ix.cls_cumw[mt.cls_lo - 1] : 0;
   } else {
-    // global stream: one bin of every vertex with d >= 2
     mt.lo_deg = 2;
     mt.hi_deg = ~0ULL;
     mt.n_b = 0;
-    mt.p_b = C > 0 ? ix.cls_cumw[C - 1] : 0;
-    mt.cls_lo = 0;
-    mt.cls_hi = C;
-    mt.cumw_base = 0;
+    mt.cls_lo = first_cls[slot_of(g, 0, max_bins)];
+    mt.cls_hi = first_cls[slot_of(g + 1, 0, max_bins)];
+    mt.cumw_base = mt.cls_lo > 0 ? ix.cls_cumw[mt.cls_lo - 1] : 0;
+    const uint64_t top = mt.cls_hi > 0 ? ix.cls_cumw[mt.cls_hi - 1] : 0;
+    mt.p_b = mt.cls_hi > mt.cls_lo ? top - mt.cumw_base : 0;
   }
-  ix.bins[b] = mt;
-  if (b == 0) {
-    ix.hdr->n = n;
+  ix.bins[f] = mt;
+  if (f == 0) {
+    ix.hdr->n = (uint32_t)n;
     ix.hdr->max_bins = max_bins;
     ix.hdr->tau = tau;
     ix.hdr->omega = omega;
     ix.hdr->class_cap = cap;
+    ix.hdr->num_graphs = G;
   }
 }
 
@@ -215,7 +241,8 @@ struct BinsWorkspace {
   void* radix;
 };
 
-static size_t bins_layout(uint32_t n, BinsWorkspace* w, void* base) {
+static size_t bins_layout(uint64_t n, uint32_t G, uint32_t max_bins, BinsWorkspace* w,
+                          void* base) {
   char* c = (char*)base;
   size_t off = 0;
   const size_t keys = round_up((size_t)(n ? n : 1) * 8, 256);
@@ -224,12 +251,67 @@ static size_t bins_layout(uint32_t n, BinsWorkspace* w, void* base) {
   if (w) w->keys_b = (uint64_t*)(c + off);
   off += keys;
   if (w) w->scan_ws = (uint64_t*)(c + off);
-  off += round_up(scan_ws_elems((uint64_t)n + 1) * 8, 256);
+  off += round_up(scan_ws_elems(n + 1) * 8, 256);
   if (w) w->first_cls = (uint32_t*)(c + off);
-  off += round_up(4 * (4096 + 2), 256);
+  off += round_up(4 * ((size_t)G * ((size_t)max_bins + 1) + 2), 256);
   if (w) w->radix = (void*)(c + off);
   off += radix_scratch_bytes(n);
   return off;
+}
+
+size_t bins_workspace_bytes(uint64_t n_total, uint32_t G, uint32_t max_bins) {
+  return bins_layout(n_total, G, max_bins, nullptr, nullptr);
+}
+
+int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uint32_t* d_voff,
+               uint32_t G, uint32_t max_n, uint32_t tau, uint64_t omega, uint32_t max_bins,
+               uint64_t* d_n_b, uint64_t* d_p_b, void* d_index, void* d_workspace,
+               hipStream_t st) {
+  BinsWorkspace w;
+  bins_layout(n, G, max_bins, &w, d_workspace);
+  IndexView ix = index_view(d_index, n, m_total, G, max_bins);
+  const uint64_t cap = class_capacity(n, m_total, G);
+  const int gbits = G > 1 ? bit_width((uint64_t)G - 1) : 0;
+  const int gshift = 64 - gbits;
+  const uint64_t dmask = (gbits > 0) ? ((1ULL << (32 - gbits)) - 1) : 0xFFFFFFFFULL;
+  int rc;
+  if ((rc = fill<uint64_t>((uint64_t*)ix.hdr, sizeof(IndexHeader) / 8, 0, st))) return rc;
+  if ((rc = fill<uint64_t>(d_n_b, (uint64_t)G * max_bins, 0, st))) return rc;
+  if ((rc = fill<uint64_t>(d_p_b, (uint64_t)G * max_bins, 0, st))) return rc;
+  {
+    uint64_t blocks = ceil_div(n, 256);
+    if (blocks > 65536) blocks = 65536;
+    k_deg_keys<<<(unsigned)blocks, 256, 0, st>>>(d_rowptr, (uint32_t)n, d_voff, G, gshift, dmask,
+                                                 w.keys_a);
+    WEDGE_LAUNCH_CHECK("k_deg_keys");
+  }
+  // sort by the degree digits, then by the graph digits; ids stay ascending
+  uint64_t dbound = (uint64_t)(max_n ? max_n : 1) - 1;
+  if (m_total < dbound) dbound = m_total;
+  int shifts[16];
+  int np = 0;
+  for (int s = 0; s < bit_width(dbound); s += 8) shifts[np++] = 32 + s;
+  for (int s = 0; s < gbits; s += 8) shifts[np++] = gshift + s;
+  uint64_t* sorted = nullptr;
+  rc = radix_sort(w.keys_a, w.keys_b, n, shifts, np, radix_scratch(w.radix, n), st, &sorted);
+  if (rc) return rc;
+  rc = scan_apply<uint64_t>(ClassLoad{sorted}, ClassApply{sorted, n, cap, dmask, ix}, n,
+                            w.scan_ws, st);
+  if (rc) return rc;
+  rc = scan_apply<uint64_t>(WedgeLoad{ix, n}, CumwApply{ix}, cap, w.scan_ws, st);
+  if (rc) return rc;
+  {
+    uint64_t blocks = ceil_div(cap, 256);
+    if (blocks > 4096) blocks = 4096;
+    k_bin_accumulate<<<(unsigned)blocks, 256, 0, st>>>(ix, n, tau, omega, max_bins, d_voff, G,
+                                                       d_n_b, d_p_b, w.first_cls);
+    WEDGE_LAUNCH_CHECK("k_bin_accumulate");
+  }
+  const uint64_t rows = (uint64_t)G * (max_bins + 1);
+  k_bin_finalize<<<(unsigned)ceil_div(rows, 256), 256, 0, st>>>(ix, n, cap, tau, omega, max_bins,
+                                                                G, d_n_b, d_p_b, w.first_cls);
+  WEDGE_LAUNCH_CHECK("k_bin_finalize");
+  return WEDGE_OK;
 }
 
 }  // namespace wedge
@@ -237,10 +319,12 @@ static size_t bins_layout(uint32_t n, BinsWorkspace* w, void* base) {
 using namespace wedge;
 
 extern "C" size_t wedge_index_bytes(uint32_t n, uint64_t m, uint32_t max_bins) {
-  return index_bytes(n, m, max_bins);
+  return index_bytes(n, m, 1, max_bins);
 }
 
-extern "C" size_t wedge_bin_counts_workspace(uint32_t n) { return bins_layout(n, nullptr, nullptr); }
+extern "C" size_t wedge_bin_counts_workspace(uint32_t n) {
+  return bins_workspace_bytes(n, 1, 4096);
+}
 
 extern "C" int wedge_bin_counts(const uint64_t* d_rowptr, uint32_t n, uint64_t m, uint32_t tau,
                                 uint64_t omega, uint32_t max_bins, uint64_t* d_n_b,
@@ -257,51 +341,14 @@ extern "C" int wedge_bin_counts(const uint64_t* d_rowptr, uint32_t n, uint64_t m
   if (!aligned(d_rowptr, 8) || !aligned(d_n_b, 8) || !aligned(d_p_b, 8) ||
       !aligned(d_index, 256) || !aligned(d_workspace, 256))
     return set_error(WEDGE_EINVAL, "wedge_bin_counts: misaligned pointer");
-  if (index_bytes_given < index_bytes(n, m, max_bins))
+  if (index_bytes_given < index_bytes(n, m, 1, max_bins))
     return set_error(WEDGE_EWORKSPACE, "wedge_bin_counts: index %zu < %zu bytes",
-                     index_bytes_given, index_bytes(n, m, max_bins));
+                     index_bytes_given, index_bytes(n, m, 1, max_bins));
   if (workspace_bytes < wedge_bin_counts_workspace(n))
     return set_error(WEDGE_EWORKSPACE, "wedge_bin_counts: workspace %zu < %zu bytes",
                      workspace_bytes, wedge_bin_counts_workspace(n));
-  hipStream_t st = (hipStream_t)stream;
-  BinsWorkspace w;
-  bins_layout(n, &w, d_workspace);
-  IndexView ix = index_view(d_index, n, m, max_bins);
-  const uint64_t cap = class_capacity(n, m);
-  int rc;
-  if ((rc = fill<uint64_t>((uint64_t*)ix.hdr, sizeof(IndexHeader) / 8, 0, st))) return rc;
-  if ((rc = fill<uint64_t>(d_n_b, max_bins, 0, st))) return rc;
-  if ((rc = fill<uint64_t>(d_p_b, max_bins, 0, st))) return rc;
-  {
-    uint64_t blocks = ceil_div(n, 256);
-    if (blocks > 65536) blocks = 65536;
-    k_deg_keys<<<(unsigned)blocks, 256, 0, st>>>(d_rowptr, n, w.keys_a);
-    WEDGE_LAUNCH_CHECK("k_deg_keys");
-  }
-  // sort by the degree digits only; ids stay ascending within a degree
-  uint64_t dbound = (uint64_t)n - 1;
-  if (m < dbound) dbound = m;
-  int shifts[8];
-  int np = 0;
-  for (int s = 0; s < bit_width(dbound); s += 8) shifts[np++] = 32 + s;
-  uint64_t* sorted = nullptr;
-  rc = radix_sort(w.keys_a, w.keys_b, n, shifts, np, radix_scratch(w.radix, n), st, &sorted);
-  if (rc) return rc;
-  rc = scan_apply<uint64_t>(ClassLoad{sorted}, ClassApply{sorted, n, cap, ix}, n, w.scan_ws, st);
-  if (rc) return rc;
-  rc = scan_apply<uint64_t>(WedgeLoad{ix, n}, CumwApply{ix}, cap, w.scan_ws, st);
-  if (rc) return rc;
-  {
-    uint64_t blocks = ceil_div(cap, 256);
-    if (blocks > 4096) blocks = 4096;
-    k_bin_accumulate<<<(unsigned)blocks, 256, 0, st>>>(ix, n, cap, tau, omega, max_bins, d_n_b,
-                                                       d_p_b, w.first_cls);
-    WEDGE_LAUNCH_CHECK("k_bin_accumulate");
-  }
-  k_bin_finalize<<<(unsigned)ceil_div(max_bins + 1, 256), 256, 0, st>>>(
-      ix, n, cap, tau, omega, max_bins, d_n_b, d_p_b, w.first_cls);
-  WEDGE_LAUNCH_CHECK("k_bin_finalize");
-  return WEDGE_OK;
+  return bins_build(d_rowptr, n, m, nullptr, 1, n, tau, omega, max_bins, d_n_b, d_p_b, d_index,
+                    d_workspace, (hipStream_t)stream);
 }
 
 extern "C" int wedge_index_status(const void* d_index, uint32_t* h_num_classes,

@@ -50,7 +50,9 @@ struct IndexHeader {
   uint64_t overflow;      // vertices whose bin is >= max_bins
   uint64_t empty_bin_samples;  // samples asked of a bin with p_b = 0
   uint64_t mismatch;      // sampler launches whose n / max_bins / m disagree
-  uint64_t pad[25];
+  uint32_t num_graphs;
+  uint32_t pad32;
+  uint64_t pad[24];
 };
 static_assert(sizeof(IndexHeader) == 256, "header is one 256-byte line");
 
@@ -76,12 +78,41 @@ struct IndexView {
   uint64_t* cls_cumw; // [class_cap] inclusive prefix of count_j * C(d_j, 2)
 };
 
-// Upper bound on the number of distinct degrees of a simple graph with n
-// vertices and m edges: distinct d_1 < ... < d_C sum to at most 2m, so
-// C(C-1)/2 <= 2m; one more for degree 0.
-uint64_t class_capacity(uint32_t n, uint64_t m);
-size_t index_bytes(uint32_t n, uint64_t m, uint32_t max_bins);
-IndexView index_view(void* base, uint32_t n, uint64_t m, uint32_t max_bins);
+// Upper bound on the number of distinct (graph, degree) pairs of G simple
+// graphs with n_total vertices and m_total edges in all.
+uint64_t class_capacity(uint64_t n_total, uint64_t m_total, uint32_t G);
+size_t index_bytes(uint64_t n_total, uint64_t m_total, uint32_t G, uint32_t max_bins);
+IndexView index_view(void* base, uint64_t n_total, uint64_t m_total, uint32_t G,
+                     uint32_t max_bins);
+
+// Sampling index of G graphs whose vertices are the consecutive global id
+// ranges [voff[g], voff[g+1]) of one block-diagonal CSR (d_voff may be null
+// when G == 1); degrees must be < 2^(32 - bits(G-1)).  Rows of the index:
+// G x (max_bins + 1), row max_bins of a graph being its global stream.
+size_t bins_workspace_bytes(uint64_t n_total, uint32_t G, uint32_t max_bins);
+int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uint32_t* d_voff,
+               uint32_t G, uint32_t max_n, uint32_t tau, uint64_t omega, uint32_t max_bins,
+               uint64_t* d_n_b, uint64_t* d_p_b, void* d_index, void* d_workspace,
+               hipStream_t st);
+
+// Block-diagonal CSR of G graphs (G == 1: d_eoff, d_voff may be null):
+// edges [eoff[g], eoff[g+1]) of the input carry local ids of graph g, whose
+// global ids are voff[g] + local.
+size_t csr_workspace_bytes(uint64_t m_in);
+int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint32_t n,
+              const uint64_t* d_eoff, const uint32_t* d_voff, uint32_t G, uint64_t* d_rowptr,
+              uint32_t* d_col, uint64_t* d_info, void* d_workspace, hipStream_t st);
+
+// Graph of global vertex v: last g with voff[g] <= v (voff[0] = 0).
+__device__ inline uint32_t graph_of(const uint32_t* __restrict__ voff, uint32_t G, uint32_t v) {
+  if (G <= 1) return 0;
+  uint32_t lo = 0, hi = G;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (voff[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
 
 // Saturating BinLoDeg (host and device).
 __host__ __device__ inline uint64_t bin_lo_deg(uint32_t b, uint32_t tau, uint64_t omega) {

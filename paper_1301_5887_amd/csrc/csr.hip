@@ -15,16 +15,39 @@
 
 namespace wedge {
 
+// Graph of edge i of a batch: last g with eoff[g] <= i.
+__device__ inline uint32_t graph_of_edge(const uint64_t* __restrict__ eoff, uint32_t G,
+                                         uint64_t i) {
+  uint32_t lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (eoff[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Edge i -> the keys u<<32|w and w<<32|u in global ids.  In a batch (G > 1)
+// ids are local to their graph and are shifted by the graph's vertex offset.
 __global__ void k_canon_keys(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
-                             uint64_t m_in, uint32_t n, uint64_t* __restrict__ keys,
-                             unsigned long long* __restrict__ rejected) {
+                             uint64_t m_in, uint32_t n, const uint64_t* __restrict__ eoff,
+                             const uint32_t* __restrict__ voff, uint32_t G,
+                             uint64_t* __restrict__ keys, unsigned long long* __restrict__ rejected) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; i < m_in; i += stride) {
     uint64_t u = src[i], w = dst[i];
-    if (u >= n || w >= n) {
+    uint64_t base = 0, lim = n;
+    if (G > 1) {
+      const uint32_t g = graph_of_edge(eoff, G, i);
+      base = voff[g];
+      lim = voff[g + 1] - base;
+    }
+    if (u >= lim || w >= lim) {
       atomicAdd(rejected, 1ULL);
       u = w = 0;
+    } else {
+      u += base;
+      w += base;
     }
     ulonglong2 kv;
     kv.x = (u << 32) | w;
@@ -98,13 +121,44 @@ static size_t csr_layout(uint64_t m_in, CsrWorkspace* w, void* base) {
   return off;
 }
 
+size_t csr_workspace_bytes(uint64_t m_in) { return csr_layout(m_in, nullptr, nullptr); }
+
+int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint32_t n,
+              const uint64_t* d_eoff, const uint32_t* d_voff, uint32_t G, uint64_t* d_rowptr,
+              uint32_t* d_col, uint64_t* d_info, void* d_workspace, hipStream_t st) {
+  CsrWorkspace w;
+  csr_layout(m_in, &w, d_workspace);
+  const uint64_t N = 2 * m_in;
+  int rc = fill<uint64_t>(d_info, 2, 0, st);
+  if (rc) return rc;
+  if (N == 0) return fill<uint64_t>(d_rowptr, (uint64_t)n + 1, 0, st);
+  {
+    uint64_t blocks = ceil_div(m_in, 256);
+    if (blocks > 1u << 20) blocks = 1u << 20;
+    k_canon_keys<<<(unsigned)blocks, 256, 0, st>>>(d_src, d_dst, m_in, n, d_eoff, d_voff, G,
+                                                   w.keys_a, (unsigned long long*)(d_info + 1));
+    WEDGE_LAUNCH_CHECK("k_canon_keys");
+  }
+  // digits of dst (bits 0..nb) then of src (bits 32..32+nb)
+  int shifts[16];
+  int np = 0;
+  const int nb = bit_width((uint64_t)n - 1);
+  for (int s = 0; s < nb; s += 8) shifts[np++] = s;
+  for (int s = 0; s < nb; s += 8) shifts[np++] = 32 + s;
+  uint64_t* sorted = nullptr;
+  rc = radix_sort(w.keys_a, w.keys_b, N, shifts, np, radix_scratch(w.radix, N), st, &sorted);
+  if (rc) return rc;
+  return scan_apply<uint64_t>(DedupLoad{sorted}, DedupApply{sorted, N, n, d_col, d_rowptr, d_info},
+                              N, w.scan_ws, st);
+}
+
 }  // namespace wedge
 
 using namespace wedge;
 
 extern "C" size_t wedge_build_csr_workspace(uint64_t m_in, uint32_t n) {
   (void)n;
-  return csr_layout(m_in, nullptr, nullptr);
+  return csr_workspace_bytes(m_in);
 }
 
 extern "C" int wedge_build_csr(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in,
@@ -120,38 +174,10 @@ extern "C" int wedge_build_csr(const uint32_t* d_src, const uint32_t* d_dst, uin
   if (!aligned(d_rowptr, 8) || !aligned(d_info, 8) || !aligned(d_workspace, 256) ||
       !aligned(d_src, 4) || !aligned(d_dst, 4) || !aligned(d_col, 4))
     return set_error(WEDGE_EINVAL, "wedge_build_csr: misaligned pointer");
-  const size_t need = wedge_build_csr_workspace(m_in, n);
+  const size_t need = csr_workspace_bytes(m_in);
   if (workspace_bytes < need)
     return set_error(WEDGE_EWORKSPACE, "wedge_build_csr: workspace %zu < %zu bytes",
                      workspace_bytes, need);
-  hipStream_t st = (hipStream_t)stream;
-  CsrWorkspace w;
-  csr_layout(m_in, &w, d_workspace);
-  const uint64_t N = 2 * m_in;
-
-  int rc = fill<uint64_t>(d_info, 2, 0, st);
-  if (rc) return rc;
-  if (N == 0) {
-    return fill<uint64_t>(d_rowptr, (uint64_t)n + 1, 0, st);
-  }
-  {
-    uint64_t blocks = ceil_div(m_in, 256);
-    if (blocks > 1u << 20) blocks = 1u << 20;
-    k_canon_keys<<<(unsigned)blocks, 256, 0, st>>>(d_src, d_dst, m_in, n, w.keys_a,
-                                                   (unsigned long long*)(d_info + 1));
-    WEDGE_LAUNCH_CHECK("k_canon_keys");
-  }
-  // digits of dst (bits 0..nb) then of src (bits 32..32+nb)
-  int shifts[16];
-  int np = 0;
-  const int nb = bit_width((uint64_t)n - 1);
-  for (int s = 0; s < nb; s += 8) shifts[np++] = s;
-  for (int s = 0; s < nb; s += 8) shifts[np++] = 32 + s;
-  uint64_t* sorted = nullptr;
-  rc = radix_sort(w.keys_a, w.keys_b, N, shifts, np, radix_scratch(w.radix, N), st, &sorted);
-  if (rc) return rc;
-  rc = scan_apply<uint64_t>(DedupLoad{sorted},
-                            DedupApply{sorted, N, n, d_col, d_rowptr, d_info},
-                            N, w.scan_ws, st);
-  return rc;
+  return csr_build(d_src, d_dst, m_in, n, nullptr, nullptr, 1, d_rowptr, d_col, d_info,
+                   d_workspace, (hipStream_t)stream);
 }

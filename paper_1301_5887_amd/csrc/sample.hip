@@ -3,81 +3,47 @@
 // pair law of the Sampling procedure of Alg. phase2c; exact edge match of
 // Alg. phase3b; classes q0..q3 of Alg. phase4c).
 //
-// Work layout: every workgroup takes one tile of consecutive sample indices
-// of one bin.  It stages the bin's cumulative-wedge table (one entry per
-// distinct degree, or every S-th entry when the bin has more than the LDS
-// holds) in LDS, then each lane carries U independent samples through the
-// dependent gather chain
+// Work layout: a workgroup takes one tile of consecutive sample indices of
+// one (graph, bin) row.  It stages the row's cumulative-wedge table (one
+// entry per distinct degree, or every S-th entry when the row has more than
+// the LDS holds) in LDS, then each lane carries U independent samples
+// through the dependent gather chain
 //     Philox -> centre class (LDS search) -> vlist -> rowptr[v] -> col (a, c)
 //            -> rowptr[a], rowptr[c] -> binary search in the shorter row,
 // issuing the loads of its U samples back to back so that U x (waves per CU)
 // chains are in flight per CU.  Class counts are reduced per wave with
-// shuffles, per workgroup in LDS, and added to the bin's four uint64
+// shuffles, per workgroup in LDS, and added to the row's four uint64
 // counters with one atomic each: integer sums, so the result does not depend
 // on tiling or scheduling.
+//
+// Two launch forms share the tile routine: a grid of tiles with the task
+// table in the kernel arguments (one graph), and a persistent grid that
+// pulls tiles of every (graph, bin) row of a batch from a device work queue.
 #include "common.hpp"
 #include "rng.hpp"
+#include "sample.hpp"
 #include "scan.hpp"
 
 namespace wedge {
 
-constexpr int kSampWG = 256;
 constexpr int kLdsClasses = 1024;
-constexpr int kMaxTasks = 64;
 constexpr uint32_t kGlobalWord = 0xFFFFFFFFu;
 
-struct Task {
-  uint32_t row;    // row of q / dump: bin id, or max_bins for the global stream
-  uint32_t bword;  // Philox counter word 1: bin id, or 0xFFFFFFFF
-  uint64_t k;      // samples
-  uint64_t tile_begin;
+struct TileSmem {
+  uint64_t cumw[kLdsClasses];
+  uint32_t deg[kLdsClasses];
+  uint32_t start[kLdsClasses];
+  unsigned long long red[5];
+  uint64_t item[2];
 };
 
-struct SampleArgs {
-  const uint64_t* rowptr;
-  const uint32_t* col;
-  IndexView ix;
-  uint64_t seed;
-  uint64_t spt;  // samples per tile
-  uint64_t dump_per_bin;
-  uint64_t* q;
-  uint64_t* probe_loads;
-  wedge_sample_rec* dump;
-  uint64_t class_cap;
-  uint32_t n;
-  uint32_t max_bins;
-  uint32_t graph_id;
-  uint32_t ntask;
-  Task task[kMaxTasks];
-};
-
+// One tile: samples [s0, s1) of index row f (graph g, bin word bword).
 template <int U>
-__global__ __launch_bounds__(kSampWG) void k_sample_close(const SampleArgs A) {
-  __shared__ uint64_t s_cumw[kLdsClasses];
-  __shared__ uint32_t s_deg[kLdsClasses];
-  __shared__ uint32_t s_start[kLdsClasses];
-  __shared__ unsigned long long s_red[5];
-
+__device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint32_t bword,
+                            uint64_t gword, uint64_t s0, uint64_t s1) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const uint64_t tile = blockIdx.x;
-  int e = 0;
-  for (int i = 1; i < (int)A.ntask; ++i)
-    if (A.task[i].tile_begin <= tile) e = i;
-  const uint32_t row = A.task[e].row;
-  const uint64_t bword = A.task[e].bword;
-  const uint64_t s0 = (tile - A.task[e].tile_begin) * A.spt;
-  const uint64_t s1 = min(s0 + A.spt, A.task[e].k);
-  if (s0 >= s1) return;
-  {
-    // the index must have been built for this graph and bin count
-    const IndexHeader* H = A.ix.hdr;
-    if (H->n != A.n || H->max_bins != A.max_bins || H->class_cap != A.class_cap) {
-      if (tid == 0) atomicAdd((unsigned long long*)&A.ix.hdr->mismatch, 1ULL);
-      return;
-    }
-  }
-  const BinMeta M = A.ix.bins[row];
+  const BinMeta M = A.ix.bins[f];
   if (M.p_b == 0) {
     if (tid == 0) atomicAdd((unsigned long long*)&A.ix.hdr->empty_bin_samples, s1 - s0);
     return;
@@ -88,16 +54,17 @@ __global__ __launch_bounds__(kSampWG) void k_sample_close(const SampleArgs A) {
   const uint32_t ngroups = (ncls + S - 1) / S;
   for (uint32_t i = tid; i < ngroups; i += kSampWG) {
     const uint32_t last = min((i + 1) * S, ncls) - 1;
-    s_cumw[i] = A.ix.cls_cumw[M.cls_lo + last];
+    sm.cumw[i] = A.ix.cls_cumw[M.cls_lo + last];
     if (S == 1) {
-      s_deg[i] = A.ix.cls_deg[M.cls_lo + i];
-      s_start[i] = A.ix.cls_start[M.cls_lo + i];
+      sm.deg[i] = A.ix.cls_deg[M.cls_lo + i];
+      sm.start[i] = A.ix.cls_start[M.cls_lo + i];
     }
   }
-  if (tid < 5) s_red[tid] = 0;
+  if (tid < 5) sm.red[tid] = 0;
   __syncthreads();
 
-  const uint64_t seed = A.seed, g = A.graph_id;
+  const uint64_t seed = A.seed;
+  const uint64_t bw = bword;
   const uint64_t* __restrict__ rowptr = A.rowptr;
   const uint32_t* __restrict__ col = A.col;
   uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;
@@ -116,8 +83,8 @@ __global__ __launch_bounds__(kSampWG) void k_sample_close(const SampleArgs A) {
       W[u] = 0;
       x1[u] = 0;
       if (act[u]) {
-        const U64x4 o = philox4x64_10(s[u], bword, g, 0, seed, kDomainSample);
-        W[u] = M.cumw_base + below_from(o.w[0], M.p_b, seed, s[u], bword, g, 0);
+        const U64x4 o = philox4x64_10(s[u], bw, gword, 0, seed, kDomainSample);
+        W[u] = M.cumw_base + below_from(o.w[0], M.p_b, seed, s[u], bw, gword, 0);
         x1[u] = o.w[1];
       }
     }
@@ -128,13 +95,13 @@ __global__ __launch_bounds__(kSampWG) void k_sample_close(const SampleArgs A) {
       uint32_t l = 0, h = ngroups;
       while (l < h) {
         const uint32_t mid = (l + h) >> 1;
-        if (s_cumw[mid] > W[u]) h = mid; else l = mid + 1;
+        if (sm.cumw[mid] > W[u]) h = mid; else l = mid + 1;
       }
       uint64_t dd, st, cprev;
       if (S == 1) {
-        dd = s_deg[l];
-        st = s_start[l];
-        cprev = l > 0 ? s_cumw[l - 1] : M.cumw_base;
+        dd = sm.deg[l];
+        st = sm.start[l];
+        cprev = l > 0 ? sm.cumw[l - 1] : M.cumw_base;
       } else {
         uint32_t jl = l * S, jh = min((l + 1) * S, ncls);
         while (jl < jh) {
@@ -159,7 +126,7 @@ __global__ __launch_bounds__(kSampWG) void k_sample_close(const SampleArgs A) {
       ia[u] = ic[u] = 0;
       if (act[u]) {
         const uint64_t dm1 = d[u] - 1;
-        const uint64_t o = below_from(x1[u], d[u] * dm1, seed, s[u], bword, g, 1);
+        const uint64_t o = below_from(x1[u], d[u] * dm1, seed, s[u], bw, gword, 1);
         const uint64_t i = o / dm1;
         const uint64_t r = o - i * dm1;
         ia[u] = i;
@@ -237,7 +204,7 @@ __global__ __launch_bounds__(kSampWG) void k_sample_close(const SampleArgs A) {
         rec.a = a[u];
         rec.c = c[u];
         rec.cls = cls;
-        A.dump[(uint64_t)row * A.dump_per_bin + s[u]] = rec;
+        A.dump[f * A.dump_per_bin + s[u]] = rec;
       }
     }
   }
@@ -247,28 +214,91 @@ __global__ __launch_bounds__(kSampWG) void k_sample_close(const SampleArgs A) {
   unsigned long long r3 = wave_sum<unsigned long long>(cnt3);
   unsigned long long r4 = wave_sum<unsigned long long>(probes);
   if (lane == 0) {
-    atomicAdd(&s_red[0], r0);
-    atomicAdd(&s_red[1], r1);
-    atomicAdd(&s_red[2], r2);
-    atomicAdd(&s_red[3], r3);
-    atomicAdd(&s_red[4], r4);
+    atomicAdd(&sm.red[0], r0);
+    atomicAdd(&sm.red[1], r1);
+    atomicAdd(&sm.red[2], r2);
+    atomicAdd(&sm.red[3], r3);
+    atomicAdd(&sm.red[4], r4);
   }
   __syncthreads();
   if (tid < 4) {
-    if (s_red[tid]) atomicAdd((unsigned long long*)&A.q[(uint64_t)row * 4 + tid], s_red[tid]);
+    if (sm.red[tid]) atomicAdd((unsigned long long*)&A.q[f * 4 + tid], sm.red[tid]);
   } else if (tid == 4 && A.probe_loads) {
-    atomicAdd((unsigned long long*)A.probe_loads, s_red[4]);
+    atomicAdd((unsigned long long*)A.probe_loads, sm.red[4]);
+  }
+  __syncthreads();  // the shared table and tallies are reused by the next tile
+}
+
+__device__ inline bool header_ok(const SamplerCtx& A) {
+  const IndexHeader* H = A.ix.hdr;
+  return H->n == A.n && H->max_bins == A.max_bins && H->class_cap == A.class_cap &&
+         H->num_graphs == A.num_graphs;
+}
+
+template <int U>
+__global__ __launch_bounds__(kSampWG) void k_sample_close(const SamplerCtx A, const TaskTable T) {
+  __shared__ TileSmem sm;
+  const uint64_t tile = blockIdx.x;
+  int e = 0;
+  for (int i = 1; i < (int)T.ntask; ++i)
+    if (T.task[i].tile_begin <= tile) e = i;
+  const uint64_t s0 = (tile - T.task[e].tile_begin) * A.spt;
+  const uint64_t s1 = min(s0 + A.spt, T.task[e].k);
+  if (s0 >= s1) return;
+  if (!header_ok(A)) {
+    if (threadIdx.x == 0) atomicAdd((unsigned long long*)&A.ix.hdr->mismatch, 1ULL);
+    return;
+  }
+  sample_tile<U>(A, sm, T.task[e].row, T.task[e].bword, T.graph_word, s0, s1);
+}
+
+// Persistent form: tiles of all (graph, row) pairs of a batch come from a
+// ticket counter; tile_begin[f] is the exclusive prefix of the tile counts
+// of rows f (tile_begin[nrows] = total).  Every workgroup leaves the loop
+// once the ticket passes the total.
+template <int U>
+__global__ __launch_bounds__(kSampWG) void k_sample_persistent(const SamplerCtx A,
+                                                               const uint64_t* __restrict__ task_k,
+                                                               const uint64_t* __restrict__ tile_begin,
+                                                               uint64_t nrows,
+                                                               unsigned long long* ticket) {
+  __shared__ TileSmem sm;
+  if (!header_ok(A)) {
+    if (threadIdx.x == 0) atomicAdd((unsigned long long*)&A.ix.hdr->mismatch, 1ULL);
+    return;
+  }
+  const uint64_t total = tile_begin[nrows];
+  const uint32_t rows_per_graph = A.max_bins + 1;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const uint64_t t = atomicAdd(ticket, 1ULL);
+      uint64_t f = 0;
+      if (t < total) {
+        uint64_t lo = 0, hi = nrows;  // last f with tile_begin[f] <= t
+        while (hi - lo > 1) {
+          const uint64_t mid = (lo + hi) >> 1;
+          if (tile_begin[mid] <= t) lo = mid; else hi = mid;
+        }
+        f = lo;
+      }
+      sm.item[0] = t;
+      sm.item[1] = f;
+    }
+    __syncthreads();
+    const uint64_t t = sm.item[0];
+    const uint64_t f = sm.item[1];
+    __syncthreads();
+    if (t >= total) break;
+    const uint64_t s0 = (t - tile_begin[f]) * A.spt;
+    const uint64_t s1 = min(s0 + A.spt, task_k[f]);
+    if (s0 >= s1) continue;
+    const uint32_t g = (uint32_t)(f / rows_per_graph);
+    const uint32_t row = (uint32_t)(f % rows_per_graph);
+    sample_tile<U>(A, sm, f, row == A.max_bins ? kGlobalWord : row, g, s0, s1);
   }
 }
 
-// Samples in flight per lane and samples per tile; chosen by the caller
-// (autotuner) or by the default below.
-struct SampleTuning {
-  int U;
-  uint64_t spt;
-};
-
-static SampleTuning default_tuning(uint64_t total) {
+SampleTuning default_tuning(uint64_t total) {
   SampleTuning t;
   t.U = 4;
   // about 16 tiles per CU of the 256 on the chip, within [1024, 16384]
@@ -278,24 +308,49 @@ static SampleTuning default_tuning(uint64_t total) {
   if (spt < unit) spt = unit;
   if (spt > 16384) spt = 16384;
   t.spt = spt;
+  t.workgroups = 256 * 8;
   return t;
 }
 
-static int launch_tasks(SampleArgs& A, int U, hipStream_t st) {
+void normalise(SampleTuning& t) {
+  if (t.U != 1 && t.U != 2 && t.U != 4 && t.U != 8) t.U = 4;
+  const uint64_t unit = (uint64_t)kSampWG * t.U;
+  if (t.spt < unit) t.spt = unit;
+  t.spt = ceil_div(t.spt, unit) * unit;
+  if (t.workgroups == 0) t.workgroups = 256 * 8;
+}
+
+static int launch_tasks(const SamplerCtx& A, TaskTable& T, int U, hipStream_t st) {
   uint64_t tiles = 0;
-  for (uint32_t i = 0; i < A.ntask; ++i) {
-    A.task[i].tile_begin = tiles;
-    tiles += ceil_div(A.task[i].k, A.spt);
+  for (uint32_t i = 0; i < T.ntask; ++i) {
+    T.task[i].tile_begin = tiles;
+    tiles += ceil_div(T.task[i].k, A.spt);
   }
   if (tiles == 0) return WEDGE_OK;
   if (tiles > 0x7FFFFFFFULL) return set_error(WEDGE_ERANGE, "wedge_sample_close: too many tiles");
   switch (U) {
-    case 1: k_sample_close<1><<<(unsigned)tiles, kSampWG, 0, st>>>(A); break;
-    case 2: k_sample_close<2><<<(unsigned)tiles, kSampWG, 0, st>>>(A); break;
-    case 8: k_sample_close<8><<<(unsigned)tiles, kSampWG, 0, st>>>(A); break;
-    default: k_sample_close<4><<<(unsigned)tiles, kSampWG, 0, st>>>(A); break;
+    case 1: k_sample_close<1><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T); break;
+    case 2: k_sample_close<2><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T); break;
+    case 8: k_sample_close<8><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T); break;
+    default: k_sample_close<4><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T); break;
   }
   WEDGE_LAUNCH_CHECK("k_sample_close");
+  return WEDGE_OK;
+}
+
+int launch_persistent(const SamplerCtx& A, const uint64_t* task_k, const uint64_t* tile_begin,
+                      uint64_t nrows, unsigned long long* ticket, const SampleTuning& t,
+                      hipStream_t st) {
+  int rc = fill<unsigned long long>(ticket, 1, 0ULL, st);
+  if (rc) return rc;
+  const unsigned grid = t.workgroups;
+  switch (t.U) {
+    case 1: k_sample_persistent<1><<<grid, kSampWG, 0, st>>>(A, task_k, tile_begin, nrows, ticket); break;
+    case 2: k_sample_persistent<2><<<grid, kSampWG, 0, st>>>(A, task_k, tile_begin, nrows, ticket); break;
+    case 8: k_sample_persistent<8><<<grid, kSampWG, 0, st>>>(A, task_k, tile_begin, nrows, ticket); break;
+    default: k_sample_persistent<4><<<grid, kSampWG, 0, st>>>(A, task_k, tile_begin, nrows, ticket); break;
+  }
+  WEDGE_LAUNCH_CHECK("k_sample_persistent");
   return WEDGE_OK;
 }
 
@@ -318,7 +373,8 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
       return set_error(WEDGE_ERANGE, "wedge_sample_close: k[%u] above 2^48", b);
     total += h_k[b];
   }
-  if (k_global > (1ULL << 48)) return set_error(WEDGE_ERANGE, "wedge_sample_close: k_global above 2^48");
+  if (k_global > (1ULL << 48))
+    return set_error(WEDGE_ERANGE, "wedge_sample_close: k_global above 2^48");
   if (total > 0 && (m == 0 || !d_col))
     return set_error(WEDGE_EINVAL, "wedge_sample_close: samples requested of a graph without edges");
   if (d_dump && dump_per_bin == 0) d_dump = nullptr;
@@ -326,41 +382,38 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
   if ((rc = fill<uint64_t>(d_q, ((uint64_t)max_bins + 1) * 4, 0, st))) return rc;
   if (d_probe_loads && (rc = fill<uint64_t>(d_probe_loads, 1, 0, st))) return rc;
   SampleTuning t = tuning ? *tuning : default_tuning(total);
-  if (t.U != 1 && t.U != 2 && t.U != 4 && t.U != 8) t.U = 4;
-  {
-    const uint64_t unit = (uint64_t)kSampWG * t.U;
-    if (t.spt < unit) t.spt = unit;
-    t.spt = ceil_div(t.spt, unit) * unit;
-  }
-  SampleArgs A;
+  normalise(t);
+  SamplerCtx A;
   A.rowptr = d_rowptr;
   A.col = d_col;
-  A.ix = index_view(const_cast<void*>(d_index), n, m, max_bins);
+  A.ix = index_view(const_cast<void*>(d_index), n, m, 1, max_bins);
   A.seed = seed;
   A.spt = t.spt;
   A.dump_per_bin = dump_per_bin;
   A.q = d_q;
   A.probe_loads = d_probe_loads;
   A.dump = d_dump;
-  A.graph_id = graph_id;
+  A.class_cap = class_capacity(n, m, 1);
   A.n = n;
   A.max_bins = max_bins;
-  A.class_cap = class_capacity(n, m);
-  A.ntask = 0;
+  A.num_graphs = 1;
+  TaskTable T;
+  T.graph_word = graph_id;
+  T.ntask = 0;
   for (uint32_t b = 0; b <= max_bins; ++b) {
     const bool glob = (b == max_bins);
     const uint64_t k = glob ? k_global : h_k[b];
     if (k == 0) continue;
-    Task& T = A.task[A.ntask++];
-    T.row = b;
-    T.bword = glob ? kGlobalWord : b;
-    T.k = k;
-    if (A.ntask == kMaxTasks) {
-      if ((rc = launch_tasks(A, t.U, st))) return rc;
-      A.ntask = 0;
+    Task& K = T.task[T.ntask++];
+    K.row = b;
+    K.bword = glob ? kGlobalWord : b;
+    K.k = k;
+    if (T.ntask == kMaxTasks) {
+      if ((rc = launch_tasks(A, T, t.U, st))) return rc;
+      T.ntask = 0;
     }
   }
-  if (A.ntask > 0 && (rc = launch_tasks(A, t.U, st))) return rc;
+  if (T.ntask > 0 && (rc = launch_tasks(A, T, t.U, st))) return rc;
   return WEDGE_OK;
 }
 
@@ -387,7 +440,7 @@ extern "C" int wedge_sample_close_tuned(const uint64_t* d_rowptr, const uint32_t
                                         uint64_t dump_per_bin, int lanes_in_flight,
                                         uint64_t samples_per_tile, void* stream) {
   clear_error();
-  SampleTuning t{lanes_in_flight, samples_per_tile};
+  SampleTuning t{lanes_in_flight, samples_per_tile, 0};
   return sample_close_impl(d_rowptr, d_col, n, m, d_index, max_bins, h_k, k_global, seed,
                            graph_id, d_q, d_probe_loads, d_dump, dump_per_bin, &t,
                            (hipStream_t)stream);

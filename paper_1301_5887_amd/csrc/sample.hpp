@@ -1,0 +1,56 @@
+// Sampler launch interface shared by the single-graph and batched paths.
+#pragma once
+
+#include "common.hpp"
+
+namespace wedge {
+
+constexpr int kSampWG = 256;
+constexpr int kMaxTasks = 64;
+
+// Everything a tile needs, passed by value to the kernels.
+struct SamplerCtx {
+  const uint64_t* rowptr;
+  const uint32_t* col;
+  IndexView ix;
+  uint64_t seed;
+  uint64_t spt;  // samples per tile
+  uint64_t dump_per_bin;
+  uint64_t* q;   // [rows * 4], row f = g * (max_bins + 1) + bin
+  uint64_t* probe_loads;
+  wedge_sample_rec* dump;
+  uint64_t class_cap;
+  uint32_t n;
+  uint32_t max_bins;
+  uint32_t num_graphs;
+};
+
+struct Task {
+  uint32_t row;    // index row (bin id, or max_bins for the global stream)
+  uint32_t bword;  // Philox counter word 1: bin id, or 0xFFFFFFFF
+  uint64_t k;      // samples
+  uint64_t tile_begin;
+};
+
+struct TaskTable {
+  uint64_t graph_word;  // Philox counter word 2
+  uint32_t ntask;
+  Task task[kMaxTasks];
+};
+
+// Launch shape: samples carried per lane (1, 2, 4, 8), samples per tile, and
+// workgroups of the persistent grid.
+struct SampleTuning {
+  int U;
+  uint64_t spt;
+  uint32_t workgroups;
+};
+
+SampleTuning default_tuning(uint64_t total_samples);
+void normalise(SampleTuning& t);
+
+int launch_persistent(const SamplerCtx& A, const uint64_t* task_k, const uint64_t* tile_begin,
+                      uint64_t nrows, unsigned long long* ticket, const SampleTuning& t,
+                      hipStream_t st);
+
+}  // namespace wedge

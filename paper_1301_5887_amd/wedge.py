@@ -46,6 +46,20 @@ class WedgeGlobalEstimate(ctypes.Structure):
                 ("t_bins_sum", ctypes.c_double)]
 
 
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("num_graphs", _c_u32), ("max_bins", _c_u32), ("tau", _c_u32), ("max_n", _c_u32),
+                ("omega", _c_u64), ("k_per_bin", _c_u64), ("k_global", _c_u64), ("seed", _c_u64),
+                ("total_edges", _c_u64), ("total_vertices", _c_u64)]
+
+
+class LaunchShape(ctypes.Structure):
+    _fields_ = [("lanes_in_flight", ctypes.c_int), ("samples_per_tile", _c_u32),
+                ("workgroups", _c_u32)]
+
+
+_dp = ctypes.POINTER(BatchDesc)
+_sp = ctypes.POINTER(LaunchShape)
+
 # name -> (restype, argtypes); the C-ABI surface declared in include/wedge.h
 SIGNATURES = {
     "wedge_last_error": (ctypes.c_char_p, []),
@@ -69,6 +83,21 @@ SIGNATURES = {
                                                 ctypes.c_int, _c_u64, _vp]),
     "wedge_estimate": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_u32, _c_u32, _c_u64, _c_u64,
                                       ctypes.c_double, _vp, _vp]),
+    "wedge_batch_workspace_bytes": (ctypes.c_size_t, [_dp]),
+    "wedge_batch_prepare": (ctypes.c_int, [_dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                           ctypes.c_size_t, _vp]),
+    "wedge_batch_sample": (ctypes.c_int, [_dp, _sp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp,
+                                          ctypes.c_size_t, _vp]),
+    "wedge_batch_run": (ctypes.c_int, [_dp, _vp, _vp, _vp, _vp, _sp, ctypes.c_double, _vp, _vp,
+                                       _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "wedge_batch_graph_create": (ctypes.c_int, [_dp, _vp, _vp, _vp, _vp, _sp, ctypes.c_double,
+                                                _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                                ctypes.POINTER(ctypes.c_void_p)]),
+    "wedge_batch_graph_launch": (ctypes.c_int, [_vp, _vp]),
+    "wedge_batch_graph_destroy": (ctypes.c_int, [_vp]),
+    "wedge_batch_autotune": (ctypes.c_int, [_dp, _sp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
+                                            ctypes.c_size_t, ctypes.POINTER(ctypes.c_float),
+                                            ctypes.POINTER(ctypes.c_int), _vp]),
 }
 
 _lib = None
@@ -346,3 +375,138 @@ def run_plain(src: torch.Tensor, dst: torch.Tensor, n: int, *, tau: int = 2, ome
     q = to_host_u64(so.q)
     est = estimate(bi, q, hk, kg, delta)
     return PlainResult(csr=g, bins=bi, samples=so, est=est)
+
+
+# ------------------------------------------------------------------ batches
+def make_shape(lanes: int = 4, spt: int = 4096, workgroups: int = 0) -> LaunchShape:
+    return LaunchShape(int(lanes), int(spt), int(workgroups))
+
+
+class Batch:
+    """A batch of graphs on the device (wedge_batch_*).
+
+    graphs: list of (n_g, src, dst) with local uint32 ids.  Results of graph
+    g equal the single-graph path on graph g with graph_id = g."""
+
+    def __init__(self, graphs, *, tau: int = 2, omega: int = 2, max_bins: int = 40,
+                 k_per_bin: int = 20_000, k_global: int | None = None, seed: int = 1,
+                 device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libwedge needs a GPU (no CPU fallback)")
+        dev = torch.device(device)
+        self.G = len(graphs)
+        ns = [int(g[0]) for g in graphs]
+        ms = [len(g[1]) for g in graphs]
+        self.n_g = np.array(ns, dtype=np.uint64)
+        self.voff = np.concatenate([[0], np.cumsum(ns)]).astype(np.uint64)
+        self.eoff = np.concatenate([[0], np.cumsum(ms)]).astype(np.uint64)
+        src = np.concatenate([np.asarray(g[1], dtype=np.uint32) for g in graphs]) if sum(ms) else \
+            np.zeros(1, np.uint32)
+        dst = np.concatenate([np.asarray(g[2], dtype=np.uint32) for g in graphs]) if sum(ms) else \
+            np.zeros(1, np.uint32)
+        self.desc = BatchDesc(self.G, max_bins, tau, max(ns), omega, k_per_bin,
+                              k_per_bin if k_global is None else k_global, seed, int(sum(ms)),
+                              int(sum(ns)))
+        self.B = max_bins
+        self.tau, self.omega = tau, omega
+        self.d_src = torch.from_numpy(src.view(np.int32)).to(dev)
+        self.d_dst = torch.from_numpy(dst.view(np.int32)).to(dev)
+        self.d_eoff = torch.from_numpy(self.eoff.view(np.int64)).to(dev)
+        self.d_voff = torch.from_numpy(self.voff.astype(np.uint32).view(np.int32)).to(dev)
+        nbytes = int(lib().wedge_batch_workspace_bytes(ctypes.byref(self.desc)))
+        if nbytes == 0:
+            _check(-2)
+        self.ws = _empty_bytes(nbytes, dev)
+        rows = self.G * (max_bins + 1)
+        self.n_b = torch.zeros(self.G * max_bins, dtype=torch.int64, device=dev)
+        self.p_b = torch.zeros(self.G * max_bins, dtype=torch.int64, device=dev)
+        self.q = torch.zeros(rows * 4, dtype=torch.int64, device=dev)
+        self.q_try = torch.zeros(rows * 4, dtype=torch.int64, device=dev)
+        self.probe = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.est_glob = torch.zeros(self.G * 6, dtype=torch.float64, device=dev)
+        self.est_bins = torch.zeros(self.G * max_bins * 3, dtype=torch.float64, device=dev)
+        self.graph = None
+
+    def _shape(self, shape):
+        return None if shape is None else ctypes.byref(shape)
+
+    def prepare(self, stream=None):
+        _check(lib().wedge_batch_prepare(ctypes.byref(self.desc), _ptr(self.d_src),
+                                         _ptr(self.d_dst), _ptr(self.d_eoff), _ptr(self.d_voff),
+                                         _ptr(self.n_b), _ptr(self.p_b), _ptr(self.ws),
+                                         self.ws.numel(), _stream(stream)))
+
+    def sample(self, shape: LaunchShape | None = None, delta: float = 1e-3, stream=None,
+               probe: bool = False):
+        _check(lib().wedge_batch_sample(ctypes.byref(self.desc), self._shape(shape), delta,
+                                        _ptr(self.q), _ptr(self.probe) if probe else None,
+                                        _ptr(self.est_glob), _ptr(self.est_bins), _ptr(self.ws),
+                                        self.ws.numel(), _stream(stream)))
+
+    def run(self, shape: LaunchShape | None = None, delta: float = 1e-3, stream=None):
+        _check(lib().wedge_batch_run(ctypes.byref(self.desc), _ptr(self.d_src), _ptr(self.d_dst),
+                                     _ptr(self.d_eoff), _ptr(self.d_voff), self._shape(shape),
+                                     delta, _ptr(self.n_b), _ptr(self.p_b), _ptr(self.q),
+                                     _ptr(self.est_glob), _ptr(self.est_bins), _ptr(self.ws),
+                                     self.ws.numel(), _stream(stream)))
+
+    def capture(self, shape: LaunchShape | None = None, delta: float = 1e-3):
+        """Capture the whole batch pipeline into a HIP graph."""
+        self.destroy_graph()
+        h = ctypes.c_void_p()
+        _check(lib().wedge_batch_graph_create(ctypes.byref(self.desc), _ptr(self.d_src),
+                                              _ptr(self.d_dst), _ptr(self.d_eoff),
+                                              _ptr(self.d_voff), self._shape(shape), delta,
+                                              _ptr(self.n_b), _ptr(self.p_b), _ptr(self.q),
+                                              _ptr(self.est_glob), _ptr(self.est_bins),
+                                              _ptr(self.ws), self.ws.numel(), ctypes.byref(h)))
+        self.graph = h
+
+    def replay(self, stream=None):
+        _check(lib().wedge_batch_graph_launch(self.graph, _stream(stream)))
+
+    def destroy_graph(self):
+        if self.graph is not None:
+            lib().wedge_batch_graph_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.destroy_graph()
+        except Exception:
+            pass
+
+    def autotune(self, cands: list[LaunchShape], reps: int = 3, stream=None):
+        """Time each candidate shape on the prepared batch; returns
+        (best shape, median ms per candidate).  Raises if any candidate's
+        counts differ from the first's."""
+        arr = (LaunchShape * len(cands))(*cands)
+        ms = (ctypes.c_float * len(cands))()
+        best = ctypes.c_int(-1)
+        _check(lib().wedge_batch_autotune(ctypes.byref(self.desc), arr, len(cands), reps,
+                                          _ptr(self.q), _ptr(self.q_try), _ptr(self.ws),
+                                          self.ws.numel(), ms, ctypes.byref(best),
+                                          _stream(stream)))
+        return cands[best.value], list(ms)
+
+    def host(self):
+        """Host copies: n_b, p_b [G, B]; q [G, B+1, 4]; est_glob [G, 6];
+        est_bins [G, B, 3]."""
+        G, B = self.G, self.B
+        return dict(n_b=to_host_u64(self.n_b).reshape(G, B),
+                    p_b=to_host_u64(self.p_b).reshape(G, B),
+                    q=to_host_u64(self.q).reshape(G, B + 1, 4),
+                    est_glob=self.est_glob.cpu().numpy().reshape(G, 6),
+                    est_bins=self.est_bins.cpu().numpy().reshape(G, B, 3))
+
+    def csr_of(self, g: int):
+        """Row offsets and adjacency of graph g in local ids (from the
+        workspace: rowptr is its first region, col the second)."""
+        n_tot = int(self.voff[-1])
+        rp_all = self.ws[: 8 * (n_tot + 1)].view(torch.int64)
+        off = (8 * (n_tot + 1) + 255) // 256 * 256
+        col_all = self.ws[off: off + 4 * 2 * max(int(self.eoff[-1]), 1)].view(torch.int32)
+        v0, v1 = int(self.voff[g]), int(self.voff[g + 1])
+        rp = rp_all[v0: v1 + 1].cpu().numpy().view(np.uint64).copy()
+        col = col_all[int(rp[0]): int(rp[-1])].cpu().numpy().view(np.uint32).copy() - v0
+        return rp - rp[0], col
