@@ -317,6 +317,99 @@ int wedge_batch_autotune(const wedge_batch_desc* d, const wedge_launch_shape* ca
                          int reps, uint64_t* d_q_ref, uint64_t* d_q_try, void* d_workspace,
                          size_t workspace_bytes, float* h_ms, int* h_best, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned control variate.  A small network g(x) in (0, 1) predicts the
+ * closure probability of a sampled wedge from its degrees; the estimate of a
+ * bin's closed fraction c_b (Thm. cd-est) becomes
+ *     c_CV = mean_EVAL(X - beta g) + beta mean_AUX(g),
+ * with beta fixed before the EVAL and AUX draws, which are independent of
+ * each other and of the training draws (distinct Philox key domains).  So
+ * c_CV is unbiased for any network, every closure test stays exact, and
+ * beta = 0 is plain wedge sampling.
+ *
+ * Network: x = (L(d_v), L(min(d_a,d_c)), L(max(d_a,d_c)), bin) / 32 with
+ * L(d) = e + (d - 2^e)/2^e, e = floor(log2 d) (Mitchell's log2);
+ * h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2), g = sigmoid(W3 h2 + b3),
+ * 4 -> 64 -> 64 -> 1, GELU(a) = a/2 (1 + erf(a/sqrt 2)).  Weights are kept
+ * in FP32 (master) and BF16 (used by the matrix-core products); products
+ * accumulate in FP32.  Loss: binary cross-entropy of g against the exact
+ * closure label, averaged over the batch; update: Adam (Kingma & Ba).
+ * Parameter vector order (4545 floats): W1[64][4], b1[64], W2[64][64],
+ * b2[64], W3[64], b3.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t dv;      /* centre degree */
+  uint32_t dlo;     /* smaller endpoint degree */
+  uint32_t dhi;     /* larger endpoint degree */
+  uint16_t bin;     /* BinId(dv) */
+  uint8_t closed;   /* exact closure label (0 when the search was skipped) */
+  uint8_t cls;      /* class as in wedge_sample_close */
+} wedge_feature_rec;
+
+/* Philox key domains of the streams (key word 1). */
+enum { WEDGE_DOMAIN_SAMPLE = 1, WEDGE_DOMAIN_TRAIN = 2, WEDGE_DOMAIN_AUX = 3,
+       WEDGE_DOMAIN_EVAL = 4 };
+
+/* The sampler of wedge_sample_close with key (seed, domain), samples
+ * s = s_begin .. s_begin + h_k[r] - 1 of every row r (bins r < max_bins and
+ * the global stream r = max_bins; h_k has max_bins + 1 entries).  Rows with
+ * h_k[r] > 0, taken in increasing r, fill record rows j = 0, 1, ...: the
+ * record of sample s of the j-th such row goes to
+ * d_out[j * out_stride + (s - s_begin)].
+ * closure = 0 skips the closure search (records get closed = cls = 0).
+ * d_q (nullable) receives the class counts of these samples as in
+ * wedge_sample_close.  Requires h_k[r] <= out_stride. */
+int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
+                          uint64_t m, const void* d_index, uint32_t max_bins, uint32_t tau,
+                          uint64_t omega, const uint64_t* h_k, uint64_t s_begin, uint64_t seed,
+                          uint32_t domain, uint32_t graph_id, int closure,
+                          wedge_feature_rec* d_out, uint64_t out_stride, uint64_t* d_q,
+                          void* stream);
+
+/* Network state on the device: FP32 master weights, BF16 copy, Adam
+ * moments.  wedge_mlp_state_bytes() bytes, 256-byte aligned. */
+size_t wedge_mlp_state_bytes(void);
+/* Loads 4545 FP32 parameters (device pointer) into the state, makes the BF16
+ * copy and clears the Adam moments. */
+int wedge_mlp_set(void* d_state, const float* d_params, void* stream);
+/* Copies the FP32 master parameters out (device pointer, 4545 floats). */
+int wedge_mlp_get(const void* d_state, float* d_params, void* stream);
+/* Fan-in-scaled uniform initialisation from Philox (key (seed, 5)). */
+int wedge_mlp_init(void* d_state, uint64_t seed, void* stream);
+/* g for n records (device FP32 out). */
+int wedge_mlp_forward(const void* d_state, const wedge_feature_rec* d_x, uint64_t n, float* d_g,
+                      void* stream);
+/* Gradient (4545 FP32, device) and mean loss (1 FP32, device, nullable) of
+ * the BCE loss (labels = closed) over the minibatch made of records
+ * j0 .. j0 + per_row - 1 of each of the `rows` rows of d_x[rows][stride]
+ * (n = rows * per_row records, so a minibatch can hold every bin).
+ * Workspace: wedge_mlp_grad_workspace(n) bytes. */
+size_t wedge_mlp_grad_workspace(uint64_t n);
+int wedge_mlp_grad(const void* d_state, const wedge_feature_rec* d_x, uint32_t rows,
+                   uint64_t stride, uint64_t j0, uint64_t per_row, float* d_grad, float* d_loss,
+                   void* d_workspace, size_t workspace_bytes, void* stream);
+/* One Adam step (t >= 1) of the master weights with gradient d_grad; the
+ * BF16 copy is refreshed. */
+int wedge_mlp_adam(void* d_state, const float* d_grad, uint32_t t, float lr, float beta1,
+                   float beta2, float eps, void* stream);
+
+/* Moments of the control variate over records d_x (rows x stride, the first
+ * n_per_row of each row used) with network outputs d_g (same layout), added
+ * into d_mom[rows][5] (int64, caller zeroes):
+ *   [0] count, [1] sum X, [2] round(2^32 sum g), [3] round(2^32 sum g^2),
+ *   [4] round(2^32 sum X g)
+ * with every term rounded to 2^-32 before summing, so sums are exact and
+ * independent of order.  X = closed. */
+int wedge_cv_moments(const wedge_feature_rec* d_x, const float* d_g, uint32_t rows,
+                     uint64_t stride, uint64_t n_per_row, int64_t* d_mom, void* stream);
+
+/* Empirical-Bernstein half-width (Maurer & Pontil 2009, Thm. 4, two-sided,
+ * each side at delta/2) of the mean of n i.i.d. values in an interval of
+ * length R with sample variance var:
+ *   sqrt(2 var ln(4/delta) / n) + 7 R ln(4/delta) / (3 (n - 1)).
+ * Host-only; returns +inf for n < 2. */
+double wedge_eb_halfwidth(uint64_t n, double var, double R, double delta);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,7 +71,8 @@ def lib():
         L.orc_center_order.restype = ctypes.c_uint64
         L.orc_sample.argtypes = [_u64p, _u32p, ctypes.c_uint32, _u64p, ctypes.c_uint64,
                                  ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, _u64p,
-                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, _u64p,
+                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                 ctypes.c_uint64, ctypes.c_uint64, _u64p,
                                  _u32p, _u32p, _u32p, _u8p, ctypes.c_uint64, ctypes.c_int]
         L.orc_sample.restype = ctypes.c_int
         L.orc_exact.argtypes = [_u64p, _u32p, ctypes.c_uint32, _u64p, ctypes.c_uint64,
@@ -189,9 +190,14 @@ class Samples:
     cls: np.ndarray | None
 
 
+DOMAIN_SAMPLE, DOMAIN_TRAIN, DOMAIN_AUX, DOMAIN_EVAL = 1, 2, 3, 4
+
+
 def sample(g: Graph, tau: int, omega: int, max_bins: int, k_per_bin, k_global: int,
-           seed: int, graph_id: int = 0, dump_per_bin: int = 0, nthreads: int = 0) -> Samples:
-    """Sampling mode: Thms cd-est/td-est over the fixed Philox stream."""
+           seed: int, graph_id: int = 0, dump_per_bin: int = 0, nthreads: int = 0,
+           domain: int = DOMAIN_SAMPLE, s_begin: int = 0) -> Samples:
+    """Sampling mode: Thms cd-est/td-est over the fixed Philox stream
+    (key (seed, domain)); samples s_begin .. s_begin + k - 1 of each row."""
     k = np.ascontiguousarray(k_per_bin, dtype=np.uint64)
     assert k.shape[0] == max_bins
     q = np.zeros((max_bins + 1) * 4, dtype=np.uint64)
@@ -209,7 +215,7 @@ def sample(g: Graph, tau: int, omega: int, max_bins: int, k_per_bin, k_global: i
     col = g.col if g.col.size > 0 else np.zeros(1, dtype=np.uint32)
     rc = lib().orc_sample(_p(g.rowptr, _u64p), _p(col, _u32p), g.n, _p(keys, _u64p), g.m,
                           tau, omega, max_bins, _p(k, _u64p), k_global, seed, graph_id,
-                          _p(q, _u64p), *ptrs, dump_per_bin, nthreads)
+                          domain, s_begin, _p(q, _u64p), *ptrs, dump_per_bin, nthreads)
     if rc != 0:
         raise ValueError("oracle sample: bad input (bin out of range or samples in an empty bin)")
     shp = (rows, dump_per_bin)

@@ -76,7 +76,8 @@ void philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-// Key domains: which experiment a random word belongs to.
+// Key domains (the key's second word): 1 = plain sampling; 2, 3, 4 = the
+// training, auxiliary and evaluation streams of the control variate.
 const uint64_t kDomainSample = 1;
 const uint64_t kGlobalBin = 0xFFFFFFFFULL;  // counter word 1 of the global stream
 
@@ -118,11 +119,11 @@ struct PhiloxWord {
   }
 };
 
-uint64_t draw_below(uint64_t seed, uint64_t s, uint64_t bin_word, uint64_t graph, int t,
-                    uint64_t N) {
+uint64_t draw_below(uint64_t seed, uint64_t domain, uint64_t s, uint64_t bin_word,
+                    uint64_t graph, int t, uint64_t N) {
   PhiloxWord src;
   src.key[0] = seed;
-  src.key[1] = kDomainSample;
+  src.key[1] = domain;
   src.ctr[0] = s;
   src.ctr[1] = bin_word;
   src.ctr[2] = graph;
@@ -220,7 +221,7 @@ uint64_t orc_lemire64_seq(uint64_t N, const uint64_t* xs, int nx, int* consumed)
 // The draw the sampler uses: word t of Philox((seed,1), (s, bin_word, g, r)).
 uint64_t orc_draw_below(uint64_t seed, uint64_t s, uint64_t bin_word, uint64_t graph, int t,
                         uint64_t N) {
-  return draw_below(seed, s, bin_word, graph, t, N);
+  return draw_below(seed, kDomainSample, s, bin_word, graph, t, N);
 }
 
 uint64_t orc_bin_lo_deg(uint32_t b, uint32_t tau, uint64_t omega) { return bin_lo_deg(b, tau, omega); }
@@ -317,13 +318,15 @@ uint64_t orc_center_order(const uint64_t* rowptr, uint32_t n, uint32_t* order_ou
 // and the global stream (one bin of all d >= 2, counter word 1 = 2^32-1):
 // cls = 3 if closed (both endpoints then have d >= 2), else 0.
 // q[(max_bins+1)*4]: row max_bins is the global stream.
-// Dump (nullable): for bin row r and s < dump_per_bin, entry
-// r*dump_per_bin + s of v/a/c/cls.  Returns 0, -1 on bad input.
+// Samples s run over [s_begin, s_begin + k) with Philox key (seed, domain).
+// Dump (nullable): for bin row r and s - s_begin < dump_per_bin, entry
+// r*dump_per_bin + (s - s_begin) of v/a/c/cls.  Returns 0, -1 on bad input.
 int orc_sample(const uint64_t* rowptr, const uint32_t* col, uint32_t n, const uint64_t* keys,
                uint64_t m, uint32_t tau, uint64_t omega, uint32_t max_bins,
                const uint64_t* k_per_bin, uint64_t k_global, uint64_t seed, uint32_t graph_id,
-               uint64_t* q, uint32_t* dump_v, uint32_t* dump_a, uint32_t* dump_c,
-               uint8_t* dump_cls, uint64_t dump_per_bin, int nthreads) {
+               uint64_t domain, uint64_t s_begin, uint64_t* q, uint32_t* dump_v,
+               uint32_t* dump_a, uint32_t* dump_c, uint8_t* dump_cls, uint64_t dump_per_bin,
+               int nthreads) {
   for (uint64_t i = 0; i < (uint64_t)(max_bins + 1) * 4; ++i) q[i] = 0;
   // per-vertex degree and bin
   std::vector<uint64_t> deg(n);
@@ -374,12 +377,12 @@ int orc_sample(const uint64_t* rowptr, const uint32_t* col, uint32_t n, const ui
     uint64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
 #pragma omp parallel for schedule(static) reduction(+ : c0, c1, c2, c3)
     for (int64_t si = 0; si < (int64_t)k; ++si) {
-      const uint64_t s = (uint64_t)si;
-      uint64_t w = draw_below(seed, s, bin_word, graph_id, 0, pb);
+      const uint64_t s = s_begin + (uint64_t)si;
+      uint64_t w = draw_below(seed, domain, s, bin_word, graph_id, 0, pb);
       size_t j = (size_t)(std::upper_bound(Pr, Pr + nL, w) - Pr);
       uint32_t v = Lr[j];
       uint64_t d = deg[v];
-      uint64_t o = draw_below(seed, s, bin_word, graph_id, 1, d * (d - 1));
+      uint64_t o = draw_below(seed, domain, s, bin_word, graph_id, 1, d * (d - 1));
       uint64_t i = o / (d - 1);
       uint64_t r = o % (d - 1);
       uint64_t j2 = r + (r >= i ? 1 : 0);
@@ -394,8 +397,8 @@ int orc_sample(const uint64_t* rowptr, const uint32_t* col, uint32_t n, const ui
           cls = (uint8_t)(1 + (vbin[a] == row ? 1 : 0) + (vbin[c] == row ? 1 : 0));
       }
       if (cls == 0) ++c0; else if (cls == 1) ++c1; else if (cls == 2) ++c2; else ++c3;
-      if (dump_v && s < dump_per_bin) {
-        uint64_t at = (uint64_t)row * dump_per_bin + s;
+      if (dump_v && (uint64_t)si < dump_per_bin) {
+        uint64_t at = (uint64_t)row * dump_per_bin + (uint64_t)si;
         dump_v[at] = v;
         dump_a[at] = a;
         dump_c[at] = c;

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "rng.hpp"
 #include "sample.hpp"
 #include "scan.hpp"
 
@@ -211,6 +212,13 @@ static int batch_sample_impl(const wedge_batch_desc* d, const SampleTuning* shap
   A.n = d->total_vertices;
   A.max_bins = d->max_bins;
   A.num_graphs = d->num_graphs;
+  A.domain = kDomainSample;
+  A.s_begin = 0;
+  A.feat = nullptr;
+  A.feat_stride = 0;
+  A.omega = d->omega;
+  A.tau = d->tau;
+  A.closure = 1;
   int rc;
   if ((rc = fill<uint64_t>(d_q, rows * 4, 0, st))) return rc;
   if (d_probe_loads && (rc = fill<uint64_t>(d_probe_loads, 1, 0, st))) return rc;

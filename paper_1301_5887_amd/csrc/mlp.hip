@@ -1,0 +1,555 @@
+// The control-variate network on the matrix cores: forward, backward and
+// Adam for a 4 -> 64 -> 64 -> 1 perceptron (GELU, sigmoid) with BF16 weights
+// and FP32 accumulation, on v_mfma_f32_16x16x16_bf16.
+//
+// Layout.  One wave carries 16 samples through the network as the columns
+// of 16x16 tiles.  Layers are computed transposed, H^T = W X^T, so the
+// output tile of one product (lane l holds rows 4*(l/16)..+3 of column
+// l%16) is exactly the B operand of the next: activations never leave
+// registers on the forward pass.  The weight-gradient products, whose inner
+// dimension is the sample, take their operands through LDS (one 64x16 BF16
+// tile each).  The first layer's inner dimension of 4 features is padded to
+// 16 with zeros; the 64 -> 1 output is a dot product on the vector unit.
+#include <math.h>
+
+#include "common.hpp"
+#include "rng.hpp"
+
+namespace wedge {
+
+constexpr int kH = 64;
+constexpr int OFF_W1 = 0, OFF_B1 = 256, OFF_W2 = 320, OFF_B2 = 4416, OFF_W3 = 4480,
+              OFF_B3 = 4544, NPARAM = 4545, kPad = 4608;
+constexpr uint64_t kDomainInit = 5;
+
+struct MlpState {
+  float master[kPad];
+  uint16_t bf[kPad];
+  float m[kPad];
+  float v[kPad];
+};
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f4 mfma16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// float -> bfloat16, round to nearest even
+__device__ inline uint16_t f2bf(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline s4 pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
+  s4 r;
+  r[0] = (short)a;
+  r[1] = (short)b;
+  r[2] = (short)c;
+  r[3] = (short)d;
+  return r;
+}
+
+// Mitchell's log2: e + (d - 2^e) / 2^e with e = floor(log2 d); exact in
+// FP32 for d < 2^24.
+__device__ inline float mitchell(uint32_t d) {
+  if (d == 0) return 0.0f;
+  const int e = 31 - __clz(d);
+  const uint32_t p = 1u << e;
+  return (float)e + (float)(d - p) / (float)p;
+}
+
+__device__ inline float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float a) {
+  const float cdf = 0.5f * (1.0f + erff(a * 0.70710678118654752f));
+  const float pdf = expf(-0.5f * a * a) * 0.39894228040143268f;
+  return cdf + a * pdf;
+}
+
+__device__ inline void features(const wedge_feature_rec& r, float x[4]) {
+  x[0] = mitchell(r.dv) * 0.03125f;
+  x[1] = mitchell(r.dlo) * 0.03125f;
+  x[2] = mitchell(r.dhi) * 0.03125f;
+  x[3] = (float)r.bin * 0.03125f;
+}
+
+// Weights of one wave in operand layout (sl = lane % 16, kb = lane / 16).
+struct WaveWeights {
+  s4 w1[4];       // layer-1 A tiles: W1[16m+sl][4kb+j] (zero for kb > 0)
+  s4 w2[4][4];    // layer-2 A tiles [m][kk]: W2[16m+sl][16kk+4kb+j]
+  float b1[4][4]; // b1[16m+4kb+t]
+  float b2[4][4];
+  float w3[4][4]; // BF16 W3[16m+4kb+t]
+  float b3;
+};
+
+__device__ inline void load_weights(const MlpState* __restrict__ S, WaveWeights& W, int sl,
+                                    int kb) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int r = 16 * m + sl;
+    if (kb == 0)
+      W.w1[m] = pack4(S->bf[OFF_W1 + r * 4 + 0], S->bf[OFF_W1 + r * 4 + 1],
+                      S->bf[OFF_W1 + r * 4 + 2], S->bf[OFF_W1 + r * 4 + 3]);
+    else
+      W.w1[m] = pack4(0, 0, 0, 0);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int c = OFF_W2 + r * kH + 16 * kk + 4 * kb;
+      W.w2[m][kk] = pack4(S->bf[c], S->bf[c + 1], S->bf[c + 2], S->bf[c + 3]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int h = 16 * m + 4 * kb + t;
+      W.b1[m][t] = S->master[OFF_B1 + h];
+      W.b2[m][t] = S->master[OFF_B2 + h];
+      W.w3[m][t] = bf2f(S->bf[OFF_W3 + h]);
+    }
+  }
+  W.b3 = S->master[OFF_B3];
+}
+
+struct TileAct {
+  float a1[4][4];  // pre-activations A1^T[16m+4kb+t][sl]
+  s4 h1[4];        // BF16 H1^T tiles (B operands of layer 2)
+  float a2[4][4];
+  float h2[4][4];
+  float z;         // logit of sample sl (same in the 4 lanes of the column)
+};
+
+__device__ inline void forward_tile(const WaveWeights& W, const float x[4], int kb, TileAct& T) {
+  const s4 xb = kb == 0 ? pack4(f2bf(x[0]), f2bf(x[1]), f2bf(x[2]), f2bf(x[3])) : pack4(0, 0, 0, 0);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma16(W.w1[m], xb, acc);
+    uint16_t hb[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float a = acc[t] + W.b1[m][t];
+      T.a1[m][t] = a;
+      hb[t] = f2bf(gelu(a));
+    }
+    T.h1[m] = pack4(hb[0], hb[1], hb[2], hb[3]);
+  }
+  float part = 0.f;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) acc = mfma16(W.w2[m][kk], T.h1[kk], acc);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float a = acc[t] + W.b2[m][t];
+      T.a2[m][t] = a;
+      const float h = gelu(a);
+      T.h2[m][t] = h;
+      part += W.w3[m][t] * h;
+    }
+  }
+  part += __shfl_xor(part, 16, 64);
+  part += __shfl_xor(part, 32, 64);
+  T.z = part + W.b3;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const MlpState* __restrict__ S,
+                                                     const wedge_feature_rec* __restrict__ x,
+                                                     uint64_t n, float* __restrict__ g) {
+  const int lane = threadIdx.x & 63, sl = lane & 15, kb = lane >> 4;
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / 64);
+  WaveWeights W;
+  load_weights(S, W, sl, kb);
+  for (uint64_t tile = wave; tile * 16 < n; tile += nwaves) {
+    const uint64_t i = tile * 16 + sl;
+    const bool valid = i < n;
+    float xf[4] = {0.f, 0.f, 0.f, 0.f};
+    if (valid) features(x[i], xf);
+    TileAct T;
+    forward_tile(W, xf, kb, T);
+    if (kb == 0 && valid) g[i] = 1.0f / (1.0f + expf(-T.z));
+  }
+}
+
+// Record i of a minibatch made of `per` consecutive records from each of the
+// rows of a [rows][stride] block, starting at column j0 of every row.
+struct RowView {
+  const wedge_feature_rec* x;
+  uint64_t stride, j0, per;
+  __device__ const wedge_feature_rec& operator[](uint64_t i) const {
+    return x[(i / per) * stride + j0 + (i % per)];
+  }
+};
+
+// Gradient of the mean BCE over minibatch records [chunk*wg, chunk*(wg+1))
+// into partial[wg][kPad]; one wave per workgroup.
+__global__ __launch_bounds__(64) void k_mlp_grad(const MlpState* __restrict__ S, RowView x,
+                                                 uint64_t n, uint64_t chunk, float inv_n,
+                                                 float* __restrict__ partial,
+                                                 float* __restrict__ loss_partial) {
+  __shared__ uint16_t s_da2[kH][16];  // dA2^T [o][s]
+  __shared__ uint16_t s_h1[kH][16];   // H1^T  [i][s]
+  __shared__ uint16_t s_da1[kH][16];  // dA1^T [i][s]
+  __shared__ uint16_t s_x[16][16];    // X     [s][f], f >= 4 zero
+  const int lane = threadIdx.x, sl = lane & 15, kb = lane >> 4;
+  WaveWeights W;
+  load_weights(S, W, sl, kb);
+  s4 w2t[4][4];  // A tiles of W2^T: [m][kk] = W2[16kk+4kb+j][16m+sl]
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int o = 16 * kk + 4 * kb, i = 16 * m + sl;
+      w2t[m][kk] = pack4(S->bf[OFF_W2 + (o + 0) * kH + i], S->bf[OFF_W2 + (o + 1) * kH + i],
+                         S->bf[OFF_W2 + (o + 2) * kH + i], S->bf[OFF_W2 + (o + 3) * kH + i]);
+    }
+  f4 dW2[4][4];
+  f4 dW1[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    dW1[m] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nn = 0; nn < 4; ++nn) dW2[m][nn] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  float gW3[4][4], gb2[4][4], gb1[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) gW3[m][t] = gb2[m][t] = gb1[m][t] = 0.f;
+  float gb3 = 0.f, lsum = 0.f;
+
+  const uint64_t begin = (uint64_t)blockIdx.x * chunk;
+  const uint64_t end = min(begin + chunk, n);
+  for (uint64_t base = begin; base < end; base += 16) {
+    const uint64_t i = base + sl;
+    const bool valid = i < end;
+    float xf[4] = {0.f, 0.f, 0.f, 0.f};
+    float y = 0.f;
+    if (valid) {
+      features(x[i], xf);
+      y = x[i].closed ? 1.f : 0.f;
+    }
+    TileAct T;
+    forward_tile(W, xf, kb, T);
+    const float gz = 1.0f / (1.0f + expf(-T.z));
+    const float dz = valid ? (gz - y) * inv_n : 0.f;
+    if (kb == 0) {
+      gb3 += dz;
+      if (valid) lsum += fmaxf(T.z, 0.f) + log1pf(expf(-fabsf(T.z))) - y * T.z;
+    }
+    float da2[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int h = 16 * m + 4 * kb + t;
+        gW3[m][t] += dz * T.h2[m][t];
+        da2[m][t] = dz * W.w3[m][t] * gelu_grad(T.a2[m][t]);
+        gb2[m][t] += da2[m][t];
+        s_da2[h][sl] = f2bf(da2[m][t]);
+        s_h1[h][sl] = (uint16_t)T.h1[m][t];
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s_x[sl][4 * kb + j] = kb == 0 ? f2bf(xf[j]) : (uint16_t)0;
+    __syncthreads();
+    // dW2[o][i] += sum_s dA2^T[o][s] H1^T[i][s]
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const s4 a = *reinterpret_cast<const s4*>(&s_da2[16 * m + sl][4 * kb]);
+#pragma unroll
+      for (int nn = 0; nn < 4; ++nn) {
+        const s4 b = *reinterpret_cast<const s4*>(&s_h1[16 * nn + sl][4 * kb]);
+        dW2[m][nn] = mfma16(a, b, dW2[m][nn]);
+      }
+    }
+    // dH1^T = W2^T dA2^T; dA1^T = dH1^T * GELU'(A1^T)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const s4 b = pack4(f2bf(da2[kk][0]), f2bf(da2[kk][1]), f2bf(da2[kk][2]), f2bf(da2[kk][3]));
+        acc = mfma16(w2t[m][kk], b, acc);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float da1 = acc[t] * gelu_grad(T.a1[m][t]);
+        gb1[m][t] += da1;
+        s_da1[16 * m + 4 * kb + t][sl] = f2bf(da1);
+      }
+    }
+    __syncthreads();
+    // dW1[i][f] += sum_s dA1^T[i][s] X[s][f]
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const s4 a = *reinterpret_cast<const s4*>(&s_da1[16 * m + sl][4 * kb]);
+      const s4 b = pack4(s_x[4 * kb + 0][sl], s_x[4 * kb + 1][sl], s_x[4 * kb + 2][sl],
+                         s_x[4 * kb + 3][sl]);
+      dW1[m] = mfma16(a, b, dW1[m]);
+    }
+    __syncthreads();
+  }
+  float* P = partial + (uint64_t)blockIdx.x * kPad;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+#pragma unroll
+    for (int nn = 0; nn < 4; ++nn)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        P[OFF_W2 + (16 * m + 4 * kb + t) * kH + 16 * nn + sl] = dW2[m][nn][t];
+    if (sl < 4)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) P[OFF_W1 + (16 * m + 4 * kb + t) * 4 + sl] = dW1[m][t];
+  }
+  // per-hidden sums over the 16 samples of a column group
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float a = gW3[m][t], b = gb2[m][t], c = gb1[m][t];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+      }
+      if (sl == 0) {
+        const int h = 16 * m + 4 * kb + t;
+        P[OFF_W3 + h] = a;
+        P[OFF_B2 + h] = b;
+        P[OFF_B1 + h] = c;
+      }
+    }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    gb3 += __shfl_xor(gb3, off, 64);
+    lsum += __shfl_xor(lsum, off, 64);
+  }
+  if (lane == 0) {
+    P[OFF_B3] = gb3;
+    loss_partial[blockIdx.x] = lsum;
+  }
+}
+
+// Sum of the partial gradients in workgroup order (deterministic).
+__global__ void k_mlp_reduce(const float* __restrict__ partial, uint32_t nwg,
+                             float* __restrict__ grad, const float* __restrict__ loss_partial,
+                             float inv_n, float* __restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < NPARAM) {
+    float s = 0.f;
+    for (uint32_t w = 0; w < nwg; ++w) s += partial[(uint64_t)w * kPad + p];
+    grad[p] = s;
+  }
+  if (p == 0 && loss) {
+    float s = 0.f;
+    for (uint32_t w = 0; w < nwg; ++w) s += loss_partial[w];
+    *loss = s * inv_n;
+  }
+}
+
+__global__ void k_mlp_adam(MlpState* __restrict__ S, const float* __restrict__ grad, float lr,
+                           float b1, float b2, float eps, float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  const float g = grad[p];
+  const float m = b1 * S->m[p] + (1.f - b1) * g;
+  const float v = b2 * S->v[p] + (1.f - b2) * g * g;
+  S->m[p] = m;
+  S->v[p] = v;
+  const float mh = m / c1, vh = v / c2;
+  const float w = S->master[p] - lr * mh / (sqrtf(vh) + eps);
+  S->master[p] = w;
+  S->bf[p] = f2bf(w);
+}
+
+__global__ void k_mlp_set(MlpState* __restrict__ S, const float* __restrict__ params) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kPad) return;
+  const float w = p < NPARAM ? params[p] : 0.f;
+  S->master[p] = w;
+  S->bf[p] = f2bf(w);
+  S->m[p] = 0.f;
+  S->v[p] = 0.f;
+}
+
+__global__ void k_mlp_get(const MlpState* __restrict__ S, float* __restrict__ params) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < NPARAM) params[p] = S->master[p];
+}
+
+__global__ void k_mlp_init(MlpState* __restrict__ S, uint64_t seed) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kPad) return;
+  float w = 0.f;
+  if (p < NPARAM) {
+    const float fan = (p < OFF_W2) ? 4.f : 64.f;  // W1, b1 see 4 inputs; the rest 64
+    const U64x4 o = philox4x64_10((uint64_t)p, 0, 0, 0, seed, kDomainInit);
+    const double u = (double)(o.w[0] >> 11) * (1.0 / 9007199254740992.0);
+    w = (float)((2.0 * u - 1.0) / sqrt((double)fan));
+  }
+  S->master[p] = w;
+  S->bf[p] = f2bf(w);
+  S->m[p] = 0.f;
+  S->v[p] = 0.f;
+}
+
+__global__ void k_cv_moments(const wedge_feature_rec* __restrict__ x, const float* __restrict__ g,
+                             uint64_t stride, uint64_t npr, long long* __restrict__ mom) {
+  const uint64_t row = blockIdx.y;
+  long long c = 0, sx = 0, sg = 0, sg2 = 0, sxg = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npr;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t at = row * stride + i;
+    const double gv = (double)g[at];
+    const long long gq = llrint(gv * 4294967296.0);
+    const long long g2q = llrint(gv * gv * 4294967296.0);
+    const int X = x[at].closed ? 1 : 0;
+    c += 1;
+    sx += X;
+    sg += gq;
+    sg2 += g2q;
+    sxg += X ? gq : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    c += __shfl_xor(c, off, 64);
+    sx += __shfl_xor(sx, off, 64);
+    sg += __shfl_xor(sg, off, 64);
+    sg2 += __shfl_xor(sg2, off, 64);
+    sxg += __shfl_xor(sxg, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    unsigned long long* M = (unsigned long long*)(mom + row * 5);
+    atomicAdd(M + 0, (unsigned long long)c);
+    atomicAdd(M + 1, (unsigned long long)sx);
+    atomicAdd(M + 2, (unsigned long long)sg);
+    atomicAdd(M + 3, (unsigned long long)sg2);
+    atomicAdd(M + 4, (unsigned long long)sxg);
+  }
+}
+
+static uint32_t grad_groups(uint64_t n, uint64_t* chunk) {
+  uint64_t c = (n + 1023) / 1024;
+  if (c < 256) c = 256;
+  c = (c + 15) / 16 * 16;
+  *chunk = c;
+  return (uint32_t)((n + c - 1) / c);
+}
+
+}  // namespace wedge
+
+using namespace wedge;
+
+extern "C" size_t wedge_mlp_state_bytes(void) { return round_up(sizeof(MlpState), 256); }
+
+extern "C" int wedge_mlp_set(void* d_state, const float* d_params, void* stream) {
+  clear_error();
+  if (!d_state || !d_params) return set_error(WEDGE_EINVAL, "wedge_mlp_set: null pointer");
+  if (!aligned(d_state, 256) || !aligned(d_params, 4))
+    return set_error(WEDGE_EINVAL, "wedge_mlp_set: misaligned pointer");
+  k_mlp_set<<<(kPad + 255) / 256, 256, 0, (hipStream_t)stream>>>((MlpState*)d_state, d_params);
+  WEDGE_LAUNCH_CHECK("k_mlp_set");
+  return WEDGE_OK;
+}
+
+extern "C" int wedge_mlp_get(const void* d_state, float* d_params, void* stream) {
+  clear_error();
+  if (!d_state || !d_params) return set_error(WEDGE_EINVAL, "wedge_mlp_get: null pointer");
+  k_mlp_get<<<(kPad + 255) / 256, 256, 0, (hipStream_t)stream>>>((const MlpState*)d_state,
+                                                                  d_params);
+  WEDGE_LAUNCH_CHECK("k_mlp_get");
+  return WEDGE_OK;
+}
+
+extern "C" int wedge_mlp_init(void* d_state, uint64_t seed, void* stream) {
+  clear_error();
+  if (!d_state || !aligned(d_state, 256))
+    return set_error(WEDGE_EINVAL, "wedge_mlp_init: null or misaligned state");
+  k_mlp_init<<<(kPad + 255) / 256, 256, 0, (hipStream_t)stream>>>((MlpState*)d_state, seed);
+  WEDGE_LAUNCH_CHECK("k_mlp_init");
+  return WEDGE_OK;
+}
+
+extern "C" int wedge_mlp_forward(const void* d_state, const wedge_feature_rec* d_x, uint64_t n,
+                                 float* d_g, void* stream) {
+  clear_error();
+  if (n == 0) return WEDGE_OK;
+  if (!d_state || !d_x || !d_g) return set_error(WEDGE_EINVAL, "wedge_mlp_forward: null pointer");
+  if (!aligned(d_state, 256) || !aligned(d_x, 16) || !aligned(d_g, 4))
+    return set_error(WEDGE_EINVAL, "wedge_mlp_forward: misaligned pointer");
+  uint64_t tiles = (n + 15) / 16;
+  uint64_t blocks = (tiles + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  k_mlp_forward<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>((const MlpState*)d_state, d_x,
+                                                                   n, d_g);
+  WEDGE_LAUNCH_CHECK("k_mlp_forward");
+  return WEDGE_OK;
+}
+
+extern "C" size_t wedge_mlp_grad_workspace(uint64_t n) {
+  uint64_t chunk;
+  const uint32_t nwg = grad_groups(n ? n : 1, &chunk);
+  return round_up((size_t)nwg * kPad * 4, 256) + round_up((size_t)nwg * 4, 256);
+}
+
+extern "C" int wedge_mlp_grad(const void* d_state, const wedge_feature_rec* d_x, uint32_t rows,
+                              uint64_t stride, uint64_t j0, uint64_t per_row, float* d_grad,
+                              float* d_loss, void* d_workspace, size_t workspace_bytes,
+                              void* stream) {
+  clear_error();
+  const uint64_t n = (uint64_t)rows * per_row;
+  if (n == 0) return set_error(WEDGE_ERANGE, "wedge_mlp_grad: empty minibatch");
+  if (j0 + per_row > stride) return set_error(WEDGE_ERANGE, "wedge_mlp_grad: j0 + per_row > stride");
+  if (!d_state || !d_x || !d_grad || !d_workspace)
+    return set_error(WEDGE_EINVAL, "wedge_mlp_grad: null pointer");
+  if (!aligned(d_state, 256) || !aligned(d_x, 16) || !aligned(d_grad, 4) ||
+      !aligned(d_workspace, 256))
+    return set_error(WEDGE_EINVAL, "wedge_mlp_grad: misaligned pointer");
+  if (workspace_bytes < wedge_mlp_grad_workspace(n))
+    return set_error(WEDGE_EWORKSPACE, "wedge_mlp_grad: workspace too small");
+  uint64_t chunk;
+  const uint32_t nwg = grad_groups(n, &chunk);
+  float* partial = (float*)d_workspace;
+  float* lpart = (float*)((char*)d_workspace + round_up((size_t)nwg * kPad * 4, 256));
+  hipStream_t st = (hipStream_t)stream;
+  const float inv_n = 1.0f / (float)n;
+  RowView view{d_x, stride, j0, per_row};
+  k_mlp_grad<<<nwg, 64, 0, st>>>((const MlpState*)d_state, view, n, chunk, inv_n, partial, lpart);
+  WEDGE_LAUNCH_CHECK("k_mlp_grad");
+  k_mlp_reduce<<<(NPARAM + 255) / 256, 256, 0, st>>>(partial, nwg, d_grad, lpart, inv_n, d_loss);
+  WEDGE_LAUNCH_CHECK("k_mlp_reduce");
+  return WEDGE_OK;
+}
+
+extern "C" int wedge_mlp_adam(void* d_state, const float* d_grad, uint32_t t, float lr,
+                              float beta1, float beta2, float eps, void* stream) {
+  clear_error();
+  if (!d_state || !d_grad) return set_error(WEDGE_EINVAL, "wedge_mlp_adam: null pointer");
+  if (t == 0) return set_error(WEDGE_ERANGE, "wedge_mlp_adam: step t must be >= 1");
+  const float c1 = (float)(1.0 - pow((double)beta1, (double)t));
+  const float c2 = (float)(1.0 - pow((double)beta2, (double)t));
+  k_mlp_adam<<<(NPARAM + 255) / 256, 256, 0, (hipStream_t)stream>>>(
+      (MlpState*)d_state, d_grad, lr, beta1, beta2, eps, c1, c2);
+  WEDGE_LAUNCH_CHECK("k_mlp_adam");
+  return WEDGE_OK;
+}
+
+extern "C" int wedge_cv_moments(const wedge_feature_rec* d_x, const float* d_g, uint32_t rows,
+                                uint64_t stride, uint64_t n_per_row, int64_t* d_mom,
+                                void* stream) {
+  clear_error();
+  if (rows == 0 || n_per_row == 0) return WEDGE_OK;
+  if (!d_x || !d_g || !d_mom) return set_error(WEDGE_EINVAL, "wedge_cv_moments: null pointer");
+  if (n_per_row > stride) return set_error(WEDGE_ERANGE, "wedge_cv_moments: n_per_row > stride");
+  uint64_t bx = (n_per_row + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  dim3 grid((unsigned)bx, rows);
+  k_cv_moments<<<grid, 256, 0, (hipStream_t)stream>>>(d_x, d_g, stride, n_per_row,
+                                                     (long long*)d_mom);
+  WEDGE_LAUNCH_CHECK("k_cv_moments");
+  return WEDGE_OK;
+}

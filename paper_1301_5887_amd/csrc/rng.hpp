@@ -36,20 +36,22 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   return U64x4{{c0, c1, c2, c3}};
 }
 
-// Sampling domain of the Philox key (the key's second word).
+// Key domains (the key's second word): 1 plain sampling; 2, 3, 4 the
+// training, auxiliary and evaluation streams of the control variate.
 constexpr uint64_t kDomainSample = 1;
 
 // Finish a uniform-below draw whose round-0 word was x: accept or walk the
-// retry rounds of word t for counter (s, bword, g).
-__device__ __forceinline__ uint64_t below_from(uint64_t x, uint64_t N, uint64_t seed, uint64_t s,
-                                               uint64_t bword, uint64_t g, int t) {
+// retry rounds of word t for counter (s, bword, g) under key (seed, domain).
+__device__ __forceinline__ uint64_t below_from(uint64_t x, uint64_t N, uint64_t seed,
+                                               uint64_t domain, uint64_t s, uint64_t bword,
+                                               uint64_t g, int t) {
   uint64_t lo = x * N;
   if (lo < N) {
     const uint64_t thr = (0 - N) % N;
     uint64_t r = 0;
     while (lo < thr) {
       ++r;
-      U64x4 o = philox4x64_10(s, bword, g, r, seed, kDomainSample);
+      U64x4 o = philox4x64_10(s, bword, g, r, seed, domain);
       x = o.w[t];
       lo = x * N;
     }

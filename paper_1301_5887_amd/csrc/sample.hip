@@ -37,10 +37,26 @@ struct TileSmem {
   uint64_t item[2];
 };
 
+// BinId(d) of the integer reading of Eq. binid, capped at limit.
+__device__ inline uint32_t bin_of_degree(uint64_t d, uint32_t tau, uint64_t omega, uint32_t limit) {
+  if (d <= tau) return d < limit ? (uint32_t)d : limit;
+  uint32_t b = tau;
+  uint64_t lo = tau, term = 1;
+  while (b < limit) {
+    uint64_t next = lo + term;
+    if (next < lo) next = ~0ULL;
+    if (next > d) break;
+    ++b;
+    lo = next;
+    if (__builtin_mul_overflow(term, omega, &term)) term = ~0ULL;
+  }
+  return b;
+}
+
 // One tile: samples [s0, s1) of index row f (graph g, bin word bword).
 template <int U>
 __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint32_t bword,
-                            uint64_t gword, uint64_t s0, uint64_t s1) {
+                            uint64_t gword, uint64_t s0, uint64_t s1, uint64_t fslot) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const BinMeta M = A.ix.bins[f];
@@ -83,8 +99,8 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       W[u] = 0;
       x1[u] = 0;
       if (act[u]) {
-        const U64x4 o = philox4x64_10(s[u], bw, gword, 0, seed, kDomainSample);
-        W[u] = M.cumw_base + below_from(o.w[0], M.p_b, seed, s[u], bw, gword, 0);
+        const U64x4 o = philox4x64_10(s[u], bw, gword, 0, seed, A.domain);
+        W[u] = M.cumw_base + below_from(o.w[0], M.p_b, seed, A.domain, s[u], bw, gword, 0);
         x1[u] = o.w[1];
       }
     }
@@ -126,7 +142,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       ia[u] = ic[u] = 0;
       if (act[u]) {
         const uint64_t dm1 = d[u] - 1;
-        const uint64_t o = below_from(x1[u], d[u] * dm1, seed, s[u], bw, gword, 1);
+        const uint64_t o = below_from(x1[u], d[u] * dm1, seed, A.domain, s[u], bw, gword, 1);
         const uint64_t i = o / dm1;
         const uint64_t r = o - i * dm1;
         ia[u] = i;
@@ -155,7 +171,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       dc[u] = rc1 - rc0;
       const bool in_a = da[u] <= dc[u];
       lo[u] = in_a ? ra0 : rc0;
-      len[u] = act[u] ? (in_a ? da[u] : dc[u]) : 0;
+      len[u] = (act[u] && A.closure) ? (in_a ? da[u] : dc[u]) : 0;
       key[u] = in_a ? c[u] : a[u];
       found[u] = false;
     }
@@ -198,13 +214,23 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       cnt1 += cls == 1;
       cnt2 += cls == 2;
       cnt3 += cls == 3;
-      if (A.dump && s[u] < A.dump_per_bin) {
+      if (A.dump && s[u] - A.s_begin < A.dump_per_bin) {
         wedge_sample_rec rec;
         rec.v = v[u];
         rec.a = a[u];
         rec.c = c[u];
         rec.cls = cls;
-        A.dump[f * A.dump_per_bin + s[u]] = rec;
+        A.dump[f * A.dump_per_bin + (s[u] - A.s_begin)] = rec;
+      }
+      if (A.feat) {
+        wedge_feature_rec fr;
+        fr.dv = (uint32_t)d[u];
+        fr.dlo = (uint32_t)min(da[u], dc[u]);
+        fr.dhi = (uint32_t)max(da[u], dc[u]);
+        fr.bin = (uint16_t)bin_of_degree(d[u], A.tau, A.omega, A.max_bins);
+        fr.closed = found[u] ? 1 : 0;
+        fr.cls = (uint8_t)cls;
+        A.feat[fslot * A.feat_stride + (s[u] - A.s_begin)] = fr;
       }
     }
   }
@@ -222,7 +248,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
   }
   __syncthreads();
   if (tid < 4) {
-    if (sm.red[tid]) atomicAdd((unsigned long long*)&A.q[f * 4 + tid], sm.red[tid]);
+    if (A.q && sm.red[tid]) atomicAdd((unsigned long long*)&A.q[f * 4 + tid], sm.red[tid]);
   } else if (tid == 4 && A.probe_loads) {
     atomicAdd((unsigned long long*)A.probe_loads, sm.red[4]);
   }
@@ -242,14 +268,14 @@ __global__ __launch_bounds__(kSampWG) void k_sample_close(const SamplerCtx A, co
   int e = 0;
   for (int i = 1; i < (int)T.ntask; ++i)
     if (T.task[i].tile_begin <= tile) e = i;
-  const uint64_t s0 = (tile - T.task[e].tile_begin) * A.spt;
-  const uint64_t s1 = min(s0 + A.spt, T.task[e].k);
+  const uint64_t s0 = A.s_begin + (tile - T.task[e].tile_begin) * A.spt;
+  const uint64_t s1 = min(s0 + A.spt, A.s_begin + T.task[e].k);
   if (s0 >= s1) return;
   if (!header_ok(A)) {
     if (threadIdx.x == 0) atomicAdd((unsigned long long*)&A.ix.hdr->mismatch, 1ULL);
     return;
   }
-  sample_tile<U>(A, sm, T.task[e].row, T.task[e].bword, T.graph_word, s0, s1);
+  sample_tile<U>(A, sm, T.task[e].row, T.task[e].bword, T.graph_word, s0, s1, T.task[e].slot);
 }
 
 // Persistent form: tiles of all (graph, row) pairs of a batch come from a
@@ -289,12 +315,12 @@ __global__ __launch_bounds__(kSampWG) void k_sample_persistent(const SamplerCtx 
     const uint64_t f = sm.item[1];
     __syncthreads();
     if (t >= total) break;
-    const uint64_t s0 = (t - tile_begin[f]) * A.spt;
-    const uint64_t s1 = min(s0 + A.spt, task_k[f]);
+    const uint64_t s0 = A.s_begin + (t - tile_begin[f]) * A.spt;
+    const uint64_t s1 = min(s0 + A.spt, A.s_begin + task_k[f]);
     if (s0 >= s1) continue;
     const uint32_t g = (uint32_t)(f / rows_per_graph);
     const uint32_t row = (uint32_t)(f % rows_per_graph);
-    sample_tile<U>(A, sm, f, row == A.max_bins ? kGlobalWord : row, g, s0, s1);
+    sample_tile<U>(A, sm, f, row == A.max_bins ? kGlobalWord : row, g, s0, s1, f);
   }
 }
 
@@ -397,6 +423,13 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
   A.n = n;
   A.max_bins = max_bins;
   A.num_graphs = 1;
+  A.domain = kDomainSample;
+  A.s_begin = 0;
+  A.feat = nullptr;
+  A.feat_stride = 0;
+  A.omega = 2;
+  A.tau = 1;
+  A.closure = 1;
   TaskTable T;
   T.graph_word = graph_id;
   T.ntask = 0;
@@ -408,6 +441,7 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
     K.row = b;
     K.bword = glob ? kGlobalWord : b;
     K.k = k;
+    K.slot = b;
     if (T.ntask == kMaxTasks) {
       if ((rc = launch_tasks(A, T, t.U, st))) return rc;
       T.ntask = 0;
@@ -444,4 +478,77 @@ extern "C" int wedge_sample_close_tuned(const uint64_t* d_rowptr, const uint32_t
   return sample_close_impl(d_rowptr, d_col, n, m, d_index, max_bins, h_k, k_global, seed,
                            graph_id, d_q, d_probe_loads, d_dump, dump_per_bin, &t,
                            (hipStream_t)stream);
+}
+
+extern "C" int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
+                                     uint64_t m, const void* d_index, uint32_t max_bins,
+                                     uint32_t tau, uint64_t omega, const uint64_t* h_k,
+                                     uint64_t s_begin, uint64_t seed, uint32_t domain,
+                                     uint32_t graph_id, int closure, wedge_feature_rec* d_out,
+                                     uint64_t out_stride, uint64_t* d_q, void* stream) {
+  clear_error();
+  if (n == 0) return set_error(WEDGE_ERANGE, "wedge_sample_features: n must be >= 1");
+  if (max_bins == 0 || max_bins > 4096)
+    return set_error(WEDGE_ERANGE, "wedge_sample_features: max_bins must be in [1, 4096]");
+  if (tau == 0 || omega < 2)
+    return set_error(WEDGE_ERANGE, "wedge_sample_features: need tau >= 1 and omega >= 2");
+  if (!d_rowptr || !d_index || !h_k || !d_out)
+    return set_error(WEDGE_EINVAL, "wedge_sample_features: null pointer");
+  if (!aligned(d_rowptr, 8) || !aligned(d_index, 256) || !aligned(d_out, 16) ||
+      !aligned(d_col, 4) || !aligned(d_q, 8))
+    return set_error(WEDGE_EINVAL, "wedge_sample_features: misaligned pointer");
+  if (s_begin > (1ULL << 48)) return set_error(WEDGE_ERANGE, "wedge_sample_features: s_begin");
+  uint64_t total = 0;
+  for (uint32_t r = 0; r <= max_bins; ++r) {
+    if (h_k[r] > out_stride)
+      return set_error(WEDGE_ERANGE, "wedge_sample_features: k[%u] > out_stride", r);
+    total += h_k[r];
+  }
+  if (total > 0 && (m == 0 || !d_col))
+    return set_error(WEDGE_EINVAL, "wedge_sample_features: samples of a graph without edges");
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (d_q && (rc = fill<uint64_t>(d_q, ((uint64_t)max_bins + 1) * 4, 0, st))) return rc;
+  uint64_t* q = d_q;
+  SampleTuning t = default_tuning(total);
+  normalise(t);
+  SamplerCtx A;
+  A.rowptr = d_rowptr;
+  A.col = d_col;
+  A.ix = index_view(const_cast<void*>(d_index), n, m, 1, max_bins);
+  A.seed = seed;
+  A.spt = t.spt;
+  A.dump_per_bin = 0;
+  A.q = q;
+  A.probe_loads = nullptr;
+  A.dump = nullptr;
+  A.class_cap = class_capacity(n, m, 1);
+  A.n = n;
+  A.max_bins = max_bins;
+  A.num_graphs = 1;
+  A.domain = domain;
+  A.s_begin = s_begin;
+  A.feat = d_out;
+  A.feat_stride = out_stride;
+  A.omega = omega;
+  A.tau = tau;
+  A.closure = closure ? 1 : 0;
+  TaskTable T;
+  T.graph_word = graph_id;
+  T.ntask = 0;
+  uint64_t slot = 0;
+  for (uint32_t b = 0; b <= max_bins; ++b) {
+    if (h_k[b] == 0) continue;
+    Task& K = T.task[T.ntask++];
+    K.row = b;
+    K.bword = (b == max_bins) ? kGlobalWord : b;
+    K.k = h_k[b];
+    K.slot = slot++;
+    if (T.ntask == kMaxTasks) {
+      if ((rc = launch_tasks(A, T, t.U, st))) return rc;
+      T.ntask = 0;
+    }
+  }
+  if (T.ntask > 0 && (rc = launch_tasks(A, T, t.U, st))) return rc;
+  return WEDGE_OK;
 }

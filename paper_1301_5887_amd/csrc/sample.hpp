@@ -23,6 +23,14 @@ struct SamplerCtx {
   uint32_t n;
   uint32_t max_bins;
   uint32_t num_graphs;
+  // stream selection and the feature output of the control variate
+  uint64_t domain;        // Philox key word 1 (1 = plain sampling)
+  uint64_t s_begin;       // first sample index of every row of this launch
+  wedge_feature_rec* feat;  // nullable: record of sample s of a task at
+  uint64_t feat_stride;     //   slot * feat_stride + (s - s_begin)
+  uint64_t omega;           // binning, for the centre's bin in a record
+  uint32_t tau;
+  int closure;              // 0: skip the closure search (feature-only draws)
 };
 
 struct Task {
@@ -30,6 +38,7 @@ struct Task {
   uint32_t bword;  // Philox counter word 1: bin id, or 0xFFFFFFFF
   uint64_t k;      // samples
   uint64_t tile_begin;
+  uint64_t slot;   // feature-record row of this task
 };
 
 struct TaskTable {

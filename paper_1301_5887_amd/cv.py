@@ -1,0 +1,300 @@
+"""Learned control variate for wedge sampling (binding + driver).
+
+For every bin b (and the global stream) the closed fraction c_b of Thm.
+cd-est is estimated by
+    c_CV = mean_EVAL(X - beta_b g) + beta_b mean_AUX(g)
+where X is the exact closure label of a uniform wedge of the bin, g in (0,1)
+is the network's closure probability from the wedge's degrees, beta_b is fixed
+from held-out training draws before any EVAL or AUX draw, and the TRAIN, AUX
+and EVAL draws use distinct Philox key domains, so c_CV is unbiased whatever
+the network learned.  EVAL and AUX draws come in blocks of doubling size;
+after block i the two-sided empirical-Bernstein half-widths at confidence
+delta_i = delta / (i (i+1)) (a union bound over all stopping times) are
+    eps_EVAL = EB(n, var(X - beta g), 1 + |beta|)
+    eps_AUX  = |beta| EB(n_aux, var(g), 1)
+and a bin stops once eps_EVAL + eps_AUX <= eps.  beta = 0 with no AUX draws
+is plain wedge sampling with the same stopping rule ("plain-EB").  All work
+runs in libwedge: the sampler in feature mode, the network's forward,
+gradient and Adam kernels, and the integer moment sums; this module only
+sequences the calls and evaluates the closed-form bounds.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import wedge as W
+
+FEATURE_DTYPE = np.dtype([("dv", "<u4"), ("dlo", "<u4"), ("dhi", "<u4"), ("bin", "<u2"),
+                          ("closed", "u1"), ("cls", "u1")])
+NPARAM = 4545
+Q32 = float(1 << 32)
+DOMAIN_SAMPLE, DOMAIN_TRAIN, DOMAIN_AUX, DOMAIN_EVAL = 1, 2, 3, 4
+
+
+def _L():
+    return W.lib()
+
+
+def eb_halfwidth(n: int, var: float, R: float, delta: float) -> float:
+    return float(_L().wedge_eb_halfwidth(int(n), float(max(var, 0.0)), float(R), float(delta)))
+
+
+def records_to_numpy(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint8).reshape(-1).view(FEATURE_DTYPE)
+
+
+def sample_features(g: W.Csr, bi: W.BinIndex, h_k: np.ndarray, s_begin: int, seed: int,
+                    domain: int, closure: bool, out: torch.Tensor, stride: int,
+                    graph_id: int = 0, stream=None):
+    """wedge_sample_features into out (int32 tensor viewed as records)."""
+    hk = np.ascontiguousarray(h_k, dtype=np.uint64)
+    assert hk.shape[0] == bi.max_bins + 1
+    W._check(_L().wedge_sample_features(W._ptr(g.rowptr), W._ptr(g.col), g.n, g.m,
+                                        W._ptr(bi.index), bi.max_bins, bi.tau, bi.omega,
+                                        hk.ctypes.data_as(W._vp), s_begin, seed, domain, graph_id,
+                                        int(closure), W._ptr(out), stride, None,
+                                        W._stream(stream)))
+
+
+def new_records(rows: int, stride: int, device="cuda") -> torch.Tensor:
+    return torch.empty(max(rows * stride, 1) * 4, dtype=torch.int32, device=device)
+
+
+class Mlp:
+    """Network state on the device (wedge_mlp_*)."""
+
+    def __init__(self, device="cuda"):
+        self.state = W._empty_bytes(int(_L().wedge_mlp_state_bytes()), torch.device(device))
+        self.grad = torch.zeros(NPARAM, dtype=torch.float32, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.ws = W.Workspace(device)
+        self.t = 0
+
+    def init(self, seed: int, stream=None):
+        W._check(_L().wedge_mlp_init(W._ptr(self.state), seed, W._stream(stream)))
+        self.t = 0
+
+    def set(self, params: torch.Tensor, stream=None):
+        assert params.dtype == torch.float32 and params.numel() == NPARAM and params.is_cuda
+        W._check(_L().wedge_mlp_set(W._ptr(self.state), W._ptr(params), W._stream(stream)))
+        self.t = 0
+
+    def get(self, stream=None) -> torch.Tensor:
+        out = torch.empty(NPARAM, dtype=torch.float32, device=self.state.device)
+        W._check(_L().wedge_mlp_get(W._ptr(self.state), W._ptr(out), W._stream(stream)))
+        return out
+
+    def forward(self, rec: torch.Tensor, n: int, out: torch.Tensor, stream=None):
+        W._check(_L().wedge_mlp_forward(W._ptr(self.state), W._ptr(rec), n, W._ptr(out),
+                                        W._stream(stream)))
+
+    def grad_of(self, rec: torch.Tensor, rows: int, stride: int, j0: int, per_row: int,
+                stream=None):
+        n = rows * per_row
+        ws = self.ws.get(int(_L().wedge_mlp_grad_workspace(n)))
+        W._check(_L().wedge_mlp_grad(W._ptr(self.state), W._ptr(rec), rows, stride, j0, per_row,
+                                     W._ptr(self.grad), W._ptr(self.loss), W._ptr(ws),
+                                     ws.numel(), W._stream(stream)))
+
+    def adam(self, lr=2e-3, b1=0.9, b2=0.999, eps=1e-8, grad: torch.Tensor | None = None,
+             stream=None):
+        self.t += 1
+        g = self.grad if grad is None else grad
+        W._check(_L().wedge_mlp_adam(W._ptr(self.state), W._ptr(g), self.t, lr, b1, b2, eps,
+                                     W._stream(stream)))
+
+
+def moments(rec: torch.Tensor, gv: torch.Tensor, rows: int, stride: int, per_row: int,
+            out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Integer moment sums [rows, 5] (count, sum X, 2^32 sum g, 2^32 sum g^2,
+    2^32 sum X g), accumulated into `out`."""
+    if out is None:
+        out = torch.zeros(rows * 5, dtype=torch.int64, device=rec.device)
+    W._check(_L().wedge_cv_moments(W._ptr(rec), W._ptr(gv), rows, stride, per_row, W._ptr(out),
+                                   W._stream(stream)))
+    return out
+
+
+@dataclass
+class RowStats:
+    n: int = 0
+    sx: int = 0
+    sg: int = 0
+    sg2: int = 0
+    sxg: int = 0
+    an: int = 0
+    ag: int = 0
+    ag2: int = 0
+
+
+def beta_from_moments(m) -> float:
+    """Least-squares coefficient Cov(X, g) / Var(g) from integer moments."""
+    n, sx, sg, sg2, sxg = (int(v) for v in m)
+    if n < 2:
+        return 0.0
+    mx, mg = sx / n, sg / Q32 / n
+    cov = sxg / Q32 / n - mx * mg
+    var = sg2 / Q32 / n - mg * mg
+    return cov / var if var > 1e-14 else 0.0
+
+
+def cv_row_estimate(st: RowStats, beta: float, delta_i: float, use_aux: bool):
+    """(estimate, half-width) of one row from its moments."""
+    n = st.n
+    if n < 2:
+        return float("nan"), float("inf")
+    mx = st.sx / n
+    mg = st.sg / Q32 / n
+    vx = (st.sx - n * mx * mx) / (n - 1)
+    vg = (st.sg2 / Q32 - n * mg * mg) / (n - 1)
+    cxg = (st.sxg / Q32 - n * mx * mg) / (n - 1)
+    vz = vx - 2 * beta * cxg + beta * beta * vg
+    if not use_aux:
+        return mx, eb_halfwidth(n, vx, 1.0, delta_i)
+    e_eval = eb_halfwidth(n, vz, 1.0 + abs(beta), delta_i / 2)
+    if st.an < 2:
+        return float("nan"), float("inf")
+    amg = st.ag / Q32 / st.an
+    avg = (st.ag2 / Q32 - st.an * amg * amg) / (st.an - 1)
+    e_aux = abs(beta) * eb_halfwidth(st.an, avg, 1.0, delta_i / 2)
+    est = (mx - beta * mg) + beta * amg
+    return est, e_eval + e_aux
+
+
+@dataclass
+class SequentialResult:
+    estimates: dict = field(default_factory=dict)     # row -> estimate
+    halfwidth: dict = field(default_factory=dict)
+    eval_samples: dict = field(default_factory=dict)
+    aux_samples: dict = field(default_factory=dict)
+    rounds: int = 0
+    seconds: float = 0.0
+
+    @property
+    def total_eval(self) -> int:
+        return int(sum(self.eval_samples.values()))
+
+    @property
+    def total_aux(self) -> int:
+        return int(sum(self.aux_samples.values()))
+
+
+def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: float, seed: int,
+               net: Mlp | None, beta: dict | None, n0: int = 1 << 14,
+               max_per_row: int = 1 << 26, stream=None) -> SequentialResult:
+    """EVAL (and, with a network, AUX) blocks of doubling size until every
+    row's half-width at delta_i = delta / (i (i+1)) is <= eps."""
+    dev = g.rowptr.device
+    B = bi.max_bins
+    rows = sorted(rows)
+    t0 = time.perf_counter()
+    res = SequentialResult()
+    stats = {r: RowStats() for r in rows}
+    active = list(rows)
+    done_at = 0
+    i = 0
+    while active:
+        i += 1
+        n_target = min(n0 << (i - 1), max_per_row)
+        blk = n_target - done_at
+        if blk <= 0:
+            break
+        hk = np.zeros(B + 1, dtype=np.uint64)
+        for r in active:
+            hk[r] = blk
+        A = len(active)   # records are compact: row j is active[j]
+        recs = new_records(A, blk, dev)
+        sample_features(g, bi, hk, done_at, seed, DOMAIN_EVAL, True, recs, blk, stream=stream)
+        gv = torch.zeros(A * blk, dtype=torch.float32, device=dev)
+        if net is not None:
+            net.forward(recs, A * blk, gv, stream=stream)
+        m = W.to_host_u64(moments(recs, gv, A, blk, blk)).view(np.int64).reshape(A, 5)
+        am = None
+        if net is not None:
+            arecs = new_records(A, blk, dev)
+            sample_features(g, bi, hk, done_at, seed, DOMAIN_AUX, False, arecs, blk,
+                            stream=stream)
+            agv = torch.zeros(A * blk, dtype=torch.float32, device=dev)
+            net.forward(arecs, A * blk, agv, stream=stream)
+            am = W.to_host_u64(moments(arecs, agv, A, blk, blk)).view(np.int64).reshape(A, 5)
+        delta_i = delta / (i * (i + 1))
+        still = []
+        for j, r in enumerate(active):
+            st = stats[r]
+            st.n += int(m[j, 0]); st.sx += int(m[j, 1]); st.sg += int(m[j, 2])
+            st.sg2 += int(m[j, 3]); st.sxg += int(m[j, 4])
+            if am is not None:
+                st.an += int(am[j, 0]); st.ag += int(am[j, 2]); st.ag2 += int(am[j, 3])
+            b = beta.get(r, 0.0) if beta else 0.0
+            est, hw = cv_row_estimate(st, b, delta_i, use_aux=net is not None)
+            res.estimates[r], res.halfwidth[r] = est, hw
+            res.eval_samples[r] = st.n
+            res.aux_samples[r] = st.an
+            if hw > eps and n_target < max_per_row:
+                still.append(r)
+        active = still
+        done_at = n_target
+        res.rounds = i
+    torch.cuda.synchronize()
+    res.seconds = time.perf_counter() - t0
+    return res
+
+
+def _holdout_moments(recs, gv, R, stride, j0, n):
+    """Moments of columns j0 .. j0 + n - 1 of every row (record and g
+    buffers offset by j0 keep the row stride)."""
+    off_r = recs[j0 * 4:]
+    off_g = gv[j0:]
+    m = moments(off_r, off_g, R, stride, n)
+    return W.to_host_u64(m).view(np.int64).reshape(R, 5)
+
+
+@dataclass
+class TrainResult:
+    net: Mlp
+    beta: dict
+    losses: list
+    train_samples: int
+    seconds: float
+
+
+def train(g: W.Csr, bi: W.BinIndex, rows: list[int], n_train: int, seed: int,
+          epochs: int = 2, per_row_batch: int = 256, lr: float = 2e-3, holdout: float = 0.2,
+          init_seed: int = 7, stream=None) -> TrainResult:
+    """TRAIN draws (exact labels) spread evenly over `rows`, Adam on
+    stratified minibatches, then beta per row from the held-out draws."""
+    dev = g.rowptr.device
+    B = bi.max_bins
+    rows = sorted(rows)
+    t0 = time.perf_counter()
+    per_row = max(n_train // len(rows), 2 * per_row_batch)
+    hk = np.zeros(B + 1, dtype=np.uint64)
+    for r in rows:
+        hk[r] = per_row
+    recs = new_records(len(rows), per_row, dev)
+    sample_features(g, bi, hk, 0, seed, DOMAIN_TRAIN, True, recs, per_row, stream=stream)
+    n_fit = int(per_row * (1 - holdout)) // per_row_batch * per_row_batch
+    net = Mlp(dev)
+    net.init(init_seed, stream=stream)
+    losses = []
+    R = len(rows)   # records are compact: row j of `recs` is rows[j]
+    for ep in range(epochs):
+        for j0 in range(0, n_fit, per_row_batch):
+            net.grad_of(recs, R, per_row, j0, per_row_batch, stream=stream)
+            net.adam(lr=lr, stream=stream)
+        losses.append(float(net.loss.item()))
+    # beta from the held-out draws (columns n_fit .. per_row of every row)
+    gv = torch.zeros(R * per_row, dtype=torch.float32, device=dev)
+    net.forward(recs, R * per_row, gv, stream=stream)
+    n_hold = per_row - n_fit
+    mom = _holdout_moments(recs, gv, R, per_row, n_fit, n_hold)
+    beta = {r: beta_from_moments(mom[i]) for i, r in enumerate(rows)}
+    torch.cuda.synchronize()
+    return TrainResult(net=net, beta=beta, losses=losses, train_samples=per_row * R,
+                       seconds=time.perf_counter() - t0)

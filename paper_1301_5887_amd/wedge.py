@@ -98,6 +98,22 @@ SIGNATURES = {
     "wedge_batch_autotune": (ctypes.c_int, [_dp, _sp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
                                             ctypes.c_size_t, ctypes.POINTER(ctypes.c_float),
                                             ctypes.POINTER(ctypes.c_int), _vp]),
+    "wedge_sample_features": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _c_u32,
+                                             _c_u64, _vp, _c_u64, _c_u64, _c_u32, _c_u32,
+                                             ctypes.c_int, _vp, _c_u64, _vp, _vp]),
+    "wedge_mlp_state_bytes": (ctypes.c_size_t, []),
+    "wedge_mlp_set": (ctypes.c_int, [_vp, _vp, _vp]),
+    "wedge_mlp_get": (ctypes.c_int, [_vp, _vp, _vp]),
+    "wedge_mlp_init": (ctypes.c_int, [_vp, _c_u64, _vp]),
+    "wedge_mlp_forward": (ctypes.c_int, [_vp, _vp, _c_u64, _vp, _vp]),
+    "wedge_mlp_grad_workspace": (ctypes.c_size_t, [_c_u64]),
+    "wedge_mlp_grad": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _c_u64, _c_u64, _vp, _vp, _vp,
+                                      ctypes.c_size_t, _vp]),
+    "wedge_mlp_adam": (ctypes.c_int, [_vp, _vp, _c_u32, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, _vp]),
+    "wedge_cv_moments": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _c_u64, _vp, _vp]),
+    "wedge_eb_halfwidth": (ctypes.c_double, [_c_u64, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double]),
 }
 
 _lib = None

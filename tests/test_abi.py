@@ -167,3 +167,35 @@ def test_no_cpu_fallback_without_gpu():
     t = torch.zeros(4, dtype=torch.int32)
     with pytest.raises(RuntimeError):
         W.build_csr(t, t, 4)
+
+
+def test_eb_halfwidth_matches_oracle():
+    from oracle import mlp_oracle as M
+    for n, var, R, d in [(2, 0.1, 1.0, 0.1), (1000, 0.0, 1.0, 1e-3), (123457, 0.0167, 1.8, 1e-4)]:
+        assert W.lib().wedge_eb_halfwidth(n, var, R, d) == pytest.approx(
+            M.eb_halfwidth(n, var, R, d), rel=1e-15)
+    assert W.lib().wedge_eb_halfwidth(1, 0.1, 1.0, 0.1) == float("inf")
+
+
+def test_cv_row_estimate_matches_oracle_formula():
+    from oracle import mlp_oracle as M
+    from paper_1301_5887_amd import cv as C
+    rng = np.random.default_rng(3)
+    X = (rng.random(20000) < 0.25).astype(np.int64)
+    g = rng.random(20000).astype(np.float32).astype(np.float64) * 0.5
+    ga = rng.random(9000).astype(np.float32).astype(np.float64) * 0.5
+    q = lambda v: np.rint(v * 2.0 ** 32).astype(np.int64)  # noqa: E731
+    st = C.RowStats(n=len(X), sx=int(X.sum()), sg=int(q(g).sum()), sg2=int(q(g * g).sum()),
+                    sxg=int((X * q(g)).sum()), an=len(ga), ag=int(q(ga).sum()),
+                    ag2=int(q(ga * ga).sum()))
+    beta = 0.6
+    est, hw = C.cv_row_estimate(st, beta, 1e-3, use_aux=True)
+    assert est == pytest.approx(M.cv_estimate(X, q(g) / 2.0 ** 32, q(ga) / 2.0 ** 32, beta),
+                                abs=1e-12)
+    z = X - beta * g
+    ref = M.eb_halfwidth(len(X), z.var(ddof=1), 1 + beta, 5e-4) + \
+        beta * M.eb_halfwidth(len(ga), ga.var(ddof=1), 1.0, 5e-4)
+    assert hw == pytest.approx(ref, rel=1e-6)
+    b = C.beta_from_moments([st.n, st.sx, st.sg, st.sg2, st.sxg])
+    ref_b = np.cov(X, g, bias=True)[0, 1] / np.var(g)
+    assert b == pytest.approx(ref_b, rel=1e-6)

@@ -1,0 +1,210 @@
+"""Learned control variate on the GPU: the feature stream against the
+oracle's sampler, the network's forward pass, gradient and Adam step against
+the MLP oracle (BF16 tolerance), exact integer moments, and the estimator's
+defining identities and unbiasedness."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as M
+from oracle import oracle as O
+from paper_1301_5887_amd import cv as C
+from paper_1301_5887_amd import wedge as W
+from paper_1301_5887_amd.synth import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    n, src, dst = gen.chung_lu_c1(1)
+    g = W.build_csr(dev(src), dev(dst), n)
+    bi = W.bin_counts(g, 2, 2, 24)
+    og = O.build_graph(src, dst, n)
+    return g, bi, og
+
+
+def test_feature_stream_matches_oracle(c1):
+    g, bi, og = c1
+    B = bi.max_bins
+    rows = [r for r in range(B) if bi.h_p_b[r] > 0] + [B]
+    k, s_begin, seed = 3000, 1000, 77
+    hk = np.zeros(B + 1, dtype=np.uint64)
+    hk[rows] = k
+    print(f"[cv] feature stream rows={len(rows)} k={k} s_begin={s_begin}", flush=True)
+    for domain, closure in ((C.DOMAIN_TRAIN, True), (C.DOMAIN_AUX, False)):
+        recs = C.new_records(len(rows), k)
+        C.sample_features(g, bi, hk, s_begin, seed, domain, closure, recs, k)
+        torch.cuda.synchronize()
+        r = C.records_to_numpy(recs).reshape(len(rows), k)
+        s = O.sample(og, 2, 2, B, hk[:B], int(hk[B]), seed, dump_per_bin=k, domain=domain,
+                     s_begin=s_begin)
+        deg = og.degrees().astype(np.int64)
+        for j, row in enumerate(rows):
+            v, a, c, cls = s.v[row], s.a[row], s.c[row], s.cls[row]
+            assert (r["dv"][j] == deg[v]).all()
+            assert (r["dlo"][j] == np.minimum(deg[a], deg[c])).all()
+            assert (r["dhi"][j] == np.maximum(deg[a], deg[c])).all()
+            assert all(int(b) == O.bin_id(int(d), 2, 2) for b, d in zip(r["bin"][j][:200], deg[v][:200]))
+            if closure:
+                assert (r["closed"][j] == (cls > 0)).all()
+                assert (r["cls"][j] == cls).all()
+            else:
+                assert (r["closed"][j] == 0).all()
+
+
+def make_records(n, seed):
+    rng = np.random.default_rng(seed)
+    rec = np.zeros(n, dtype=C.FEATURE_DTYPE)
+    rec["dv"] = rng.integers(2, 3000, n)
+    a = rng.integers(1, 3000, n)
+    b = rng.integers(1, 3000, n)
+    rec["dlo"] = np.minimum(a, b)
+    rec["dhi"] = np.maximum(a, b)
+    rec["bin"] = [O.bin_id(int(d), 2, 2) for d in rec["dv"]]
+    rec["closed"] = (rng.random(n) < 0.3).astype(np.uint8)
+    return rec
+
+
+def upload_records(rec):
+    return torch.from_numpy(rec.view(np.uint8).copy()).cuda().view(torch.int32)
+
+
+def oracle_x(rec):
+    return M.features(rec["dv"].astype(np.int64), rec["dlo"].astype(np.int64),
+                      rec["dhi"].astype(np.int64), rec["bin"].astype(np.int64))
+
+
+def net_with(theta):
+    net = C.Mlp()
+    net.set(torch.tensor(theta, dtype=torch.float32, device="cuda"))
+    return net
+
+
+def test_mlp_forward_matches_oracle():
+    rec = make_records(3001, 1)            # ragged: not a multiple of 16
+    theta = M.init_params(3)
+    net = net_with(theta)
+    g = torch.zeros(len(rec), dtype=torch.float32, device="cuda")
+    net.forward(upload_records(rec), len(rec), g)
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy().astype(np.float64)
+    go, _ = M.forward(theta, oracle_x(rec), rounding=True)
+    err = np.abs(gg - go)
+    assert err.max() < 2e-3 and err.mean() < 2e-4, (err.max(), err.mean())
+
+
+def test_mlp_gradient_matches_oracle():
+    rec = make_records(1040, 2)
+    theta = M.init_params(4)
+    net = net_with(theta)
+    net.grad_of(upload_records(rec), 1, len(rec), 0, len(rec))
+    torch.cuda.synchronize()
+    gg = net.grad.cpu().numpy().astype(np.float64)
+    y = rec["closed"].astype(np.float64)
+    go = M.backward(theta, oracle_x(rec), y, rounding=True)
+    for (name, _), sz, off in zip(M.SHAPES, M.SIZES, np.cumsum([0] + M.SIZES[:-1])):
+        a, b = gg[off:off + sz], go[off:off + sz]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        cos = float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+        assert rel <= 2e-2 and cos >= 0.999, (name, rel, cos)
+    lo = M.loss(theta, oracle_x(rec), y, rounding=True)
+    assert abs(float(net.loss.item()) - lo) <= 1e-3 * abs(lo)
+
+
+def test_minibatch_view_selects_rows():
+    """A minibatch of per_row records from each row equals the gradient over
+    those records laid out contiguously."""
+    rec = make_records(4 * 300, 5)
+    theta = M.init_params(6)
+    net = net_with(theta)
+    d = upload_records(rec)
+    net.grad_of(d, 4, 300, 40, 32)            # rows of 300, columns 40..71
+    torch.cuda.synchronize()
+    g1 = net.grad.cpu().numpy().copy()
+    sub = np.concatenate([rec[r * 300 + 40: r * 300 + 72] for r in range(4)])
+    net.grad_of(upload_records(sub), 1, len(sub), 0, len(sub))
+    torch.cuda.synchronize()
+    g2 = net.grad.cpu().numpy()
+    assert np.allclose(g1, g2, rtol=1e-5, atol=1e-9)
+
+
+def test_adam_step_matches_oracle():
+    theta = M.init_params(8)
+    net = net_with(theta)
+    rng = np.random.default_rng(9)
+    m = np.zeros(M.NPARAM)
+    v = np.zeros(M.NPARAM)
+    th = theta.copy()
+    for t in range(1, 4):
+        grad = rng.normal(scale=1e-2, size=M.NPARAM).astype(np.float32)
+        net.adam(lr=1e-3, grad=torch.tensor(grad, device="cuda"))
+        th, m, v = M.adam_step(th, grad.astype(np.float64), m, v, t, lr=1e-3)
+    torch.cuda.synchronize()
+    got = net.get().cpu().numpy().astype(np.float64)
+    assert np.allclose(got, th, rtol=1e-5, atol=1e-7)
+
+
+def test_moments_are_exact_integers():
+    rec = make_records(5000, 10)
+    d = upload_records(rec)
+    net = net_with(M.init_params(11))
+    g = torch.zeros(len(rec), dtype=torch.float32, device="cuda")
+    net.forward(d, len(rec), g)
+    mom = C.moments(d, g, 5, 1000, 997)       # 5 rows of 1000, first 997 used
+    torch.cuda.synchronize()
+    got = W.to_host_u64(mom).view(np.int64).reshape(5, 5)
+    gv = g.cpu().numpy().astype(np.float64).reshape(5, 1000)[:, :997]
+    X = rec["closed"].reshape(5, 1000)[:, :997].astype(np.int64)
+    gq = np.rint(gv * 2.0 ** 32).astype(np.int64)
+    g2q = np.rint(gv * gv * 2.0 ** 32).astype(np.int64)
+    ref = np.stack([np.full(5, 997), X.sum(1), gq.sum(1), g2q.sum(1), (X * gq).sum(1)], 1)
+    assert (got == ref).all()
+
+
+def test_constant_network_equals_plain(c1):
+    """g constant: the control variate cancels, c_CV = plain mean exactly."""
+    g, bi, og = c1
+    theta = np.zeros(M.NPARAM)
+    theta[-1] = -0.4
+    net = net_with(theta)
+    rows = [r for r in range(bi.max_bins) if bi.h_p_b[r] > 0]
+    beta = {r: 0.8 for r in rows}
+    cvr = C.sequential(g, bi, rows, 1e-9, 1e-3, 5, net, beta, n0=1 << 13, max_per_row=1 << 13)
+    pl = C.sequential(g, bi, rows, 1e-9, 1e-3, 5, None, None, n0=1 << 13, max_per_row=1 << 13)
+    for r in rows:
+        assert cvr.estimates[r] == pytest.approx(pl.estimates[r], abs=1e-12)
+
+
+def test_cv_unbiased_and_not_worse_than_plain(c1):
+    """Over independent seeds, the CV estimate of every bin is centred on the
+    exact closed fraction (3 standard errors) and its spread is no larger
+    than plain sampling's beyond noise."""
+    g, bi, og = c1
+    B = bi.max_bins
+    P = O.exact(og, 2, 2, B)
+    rows = [r for r in range(B) if bi.h_p_b[r] > 0]
+    tr = C.train(g, bi, rows, 200_000, seed=3, epochs=2)
+    assert tr.losses[-1] < 0.69
+    ests_cv = {r: [] for r in rows}
+    ests_pl = {r: [] for r in rows}
+    R, n = 24, 1 << 12
+    for sd in range(R):
+        cvr = C.sequential(g, bi, rows, 1e-9, 1e-3, 100 + sd, tr.net, tr.beta, n0=n,
+                           max_per_row=n)
+        pl = C.sequential(g, bi, rows, 1e-9, 1e-3, 100 + sd, None, None, n0=n, max_per_row=n)
+        for r in rows:
+            ests_cv[r].append(cvr.estimates[r])
+            ests_pl[r].append(pl.estimates[r])
+    for r in rows:
+        c_true = float(P[r, 1:].sum()) / float(bi.h_p_b[r])
+        e = np.array(ests_cv[r])
+        se = max(e.std(ddof=1), 1e-6) / math.sqrt(R)
+        assert abs(e.mean() - c_true) <= 3.5 * se + 1e-9, (r, e.mean(), c_true, se)
+        assert e.std(ddof=1) <= 1.5 * np.std(ests_pl[r], ddof=1) + 1e-6
