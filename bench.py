@@ -30,10 +30,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "closure checks/s + s per M edges at fixed CI; learned-CV vs plain samples"
 PEAK_HBM_GBS = 8000.0
-# bytes the sampler must read per sample besides its search: vlist[v] (4),
-# rowptr[v] (8), the two neighbour ids (8), rowptr of both endpoints and
-# their successors (32); plus 4 bytes per adjacency word the search reads.
-BYTES_PER_SAMPLE = 52
+# bytes the sampler must read per sample besides its search: the centre's
+# adjacency start (8), the two neighbour ids (8), rowptr of both endpoints
+# and their successors (32); plus 4 bytes per adjacency word the search reads.
+BYTES_PER_SAMPLE = 48
 BYTES_PER_PROBE = 4
 PMC_FILE = os.path.join(ROOT, "profiles", "sample_close_rmat_s24_counters.json")
 SAMPLER_SRC = os.path.join(ROOT, "paper_1301_5887_amd", "csrc", "sample.hip")
@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--max-bins", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples-per-bin", type=int, default=1 << 17)
+    ap.add_argument("--no-cv", action="store_true",
+                    help="skip the plain-EB / learned-CV comparison")
+    ap.add_argument("--cv-train", type=int, default=10_000_000)
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="after timing, run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -183,6 +186,21 @@ def main():
         log(f"[bench] calibration copy of {nbytes} bytes done")
         del a, b
 
+    cvcmp = None
+    if not args.no_cv:
+        from paper_1301_5887_amd import cv as CV
+        g = W.Csr(n=n, m=int(m), rowptr=rowptr, col=col)
+        bi = W.BinIndex(n=n, m=int(m), tau=2, omega=2, max_bins=B, n_b=n_b, p_b=p_b,
+                        index=index, h_n_b=h_nb.numpy().view(np.uint64).copy(),
+                        h_p_b=h_pb.numpy().view(np.uint64).copy())
+        cvcmp = CV.compare(g, bi, eps=args.eps, delta=args.delta, seed=args.seed + 1000,
+                           n_train=args.cv_train)
+        cvcmp["plain_hoeffding"] = {"closure_checks": K,
+                                    "seconds": avg["sample_close"] / 1000.0}
+        log(f"[bench] estimator comparison: plain-Hoeffding {K} checks, plain-EB "
+            f"{cvcmp['plain_eb']['closure_checks']}, learned-CV "
+            f"{cvcmp['learned_cv']['closure_checks']} (eval {cvcmp['learned_cv']['eval_checks']})")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(src, dst, n, B, hk, kg, args, W, torch)
@@ -211,6 +229,7 @@ def main():
         "phase_ms": {kx: round(vx, 4) for kx, vx in avg.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "estimators": cvcmp,
         "estimates": {"c": est.glob["c"], "c_global": est.glob["c_global"], "t": est.glob["t"],
                       "t_global": est.glob["t_global"], "eps": est.glob["eps_global"]},
         "paper_context": "Hadoop, 32 nodes: 225 s + 0.33 s per million edges",

@@ -325,10 +325,12 @@ int wedge_batch_autotune(const wedge_batch_desc* d, const wedge_launch_shape* ca
  * with beta fixed before the EVAL and AUX draws, which are independent of
  * each other and of the training draws (distinct Philox key domains).  So
  * c_CV is unbiased for any network, every closure test stays exact, and
- * beta = 0 is plain wedge sampling.
+ * beta = 0 is plain wedge sampling.  mean_AUX(g) may be replaced by the
+ * exact mean of g over the bin's wedges (wedge_cv_census below).
  *
- * Network: x = (L(d_v), L(min(d_a,d_c)), L(max(d_a,d_c)), bin) / 32 with
- * L(d) = e + (d - 2^e)/2^e, e = floor(log2 d) (Mitchell's log2);
+ * Network: x = (K(d_v), K(min(d_a,d_c)), K(max(d_a,d_c))) / 256 and bin / 32,
+ * K(d) = floor(8 L(d)) with L(d) = e + (d - 2^e)/2^e, e = floor(log2 d)
+ * (Mitchell's log2) -- the log-degree in steps of 1/8, exact in BF16;
  * h1 = GELU(W1 x + b1), h2 = GELU(W2 h1 + b2), g = sigmoid(W3 h2 + b3),
  * 4 -> 64 -> 64 -> 1, GELU(a) = a/2 (1 + erf(a/sqrt 2)).  Weights are kept
  * in FP32 (master) and BF16 (used by the matrix-core products); products
@@ -402,6 +404,33 @@ int wedge_mlp_adam(void* d_state, const float* d_grad, uint32_t t, float lr, flo
  * independent of order.  X = closed. */
 int wedge_cv_moments(const wedge_feature_rec* d_x, const float* d_g, uint32_t rows,
                      uint64_t stride, uint64_t n_per_row, int64_t* d_mom, void* stream);
+
+/* Census of the wedges of every bin by (bin, centre bucket, endpoint bucket
+ * pair), buckets K(d) = floor(8 L(d)) as in the network's features.  With
+ * it the mean of the network over all wedges of bin b is the finite sum
+ *   mu_b = (1/p_b) sum_keys sum_{i<=j} census[key][i,j] g(key, i, j),
+ * which makes the control variate's mean exact (no auxiliary draws).
+ * d_census: wedge_cv_census_bytes(max_bins) bytes, 256-byte aligned; keys
+ * are the (bin, centre bucket) pairs degrees >= 2 can take, numbered in
+ * increasing degree order; the count of key `key` and bucket pair
+ * (i <= j < 256) is entry j (j + 1) / 2 + i of its row of 32896 uint64.
+ * In: the graph and index as for wedge_sample_close. */
+size_t wedge_cv_census_bytes(uint32_t max_bins);
+int wedge_cv_census(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
+                    const void* d_index, uint32_t max_bins, uint32_t tau, uint64_t omega,
+                    void* d_census, size_t census_bytes, void* stream);
+/* Synchronises and reads the key list: *h_nkeys, and (nullable)
+ * h_key_bin[], h_key_bucket[] (room for 256 + max_bins + 1 entries). */
+int wedge_cv_census_keys(const void* d_census, uint32_t max_bins, uint32_t* h_nkeys,
+                         uint32_t* h_key_bin, uint32_t* h_key_bucket, void* stream);
+/* For every key: d_key_sum[key] = sum over its bucket pairs of
+ * census * g (FP64, fixed summation order) and d_key_count[key] = its wedge
+ * count (sums to p_b over the keys of bin b).  Workspace:
+ * wedge_cv_exact_mean_workspace(max_bins) bytes. */
+size_t wedge_cv_exact_mean_workspace(uint32_t max_bins);
+int wedge_cv_exact_mean(const void* d_state, const void* d_census, uint32_t max_bins,
+                        double* d_key_sum, uint64_t* d_key_count, void* d_workspace,
+                        size_t workspace_bytes, void* stream);
 
 /* Empirical-Bernstein half-width (Maurer & Pontil 2009, Thm. 4, two-sided,
  * each side at delta/2) of the mean of n i.i.d. values in an interval of

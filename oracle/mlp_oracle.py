@@ -7,9 +7,13 @@ estimator (Thm. cd-est) only as a control variate, so every closure test
 stays exact.  This module is the plain NumPy float64 definition of what the
 GPU kernels compute:
 
-  features  x = (L(d_v), L(min(d_a, d_c)), L(max(d_a, d_c)), bin) / 32 with
+  features  x = (K(d_v) / 256, K(min(d_a, d_c)) / 256, K(max(d_a, d_c)) / 256,
+            bin / 32) with K(d) = floor(8 L(d)) the log-degree bucket and
             L(d) = e + (d - 2^e) / 2^e, e = floor(log2 d) (Mitchell's
-            piecewise-linear log2, exact in float32 for d < 2^24)
+            piecewise-linear log2); every feature is exact in bfloat16, and
+            the network is a function of (bin, bucket of the centre, bucket
+            pair of the endpoints), which makes its mean over all wedges of
+            a bin a finite sum over a census of bucket pairs
   layer 1   h1 = GELU(W1 x + b1),  GELU(a) = a/2 (1 + erf(a / sqrt 2))
   layer 2   h2 = GELU(W2 h1 + b2)
   output    z = W3 h2 + b3,  g = sigmoid(z)
@@ -66,13 +70,26 @@ def mitchell_log2(d) -> np.ndarray:
     return e + (d - p) / p
 
 
+def bucket(d) -> np.ndarray:
+    """K(d) = floor(8 L(d)) for d >= 1 (0 for d = 0), exactly in integers."""
+    d = np.asarray(d, dtype=np.int64)
+    out = np.zeros(d.shape, dtype=np.int64)
+    pos = d > 0
+    e = np.floor(np.log2(np.maximum(d, 1))).astype(np.int64)
+    e = np.where((np.int64(1) << e) > d, e - 1, e)          # guard float log2
+    e = np.where((np.int64(1) << (e + 1)) <= d, e + 1, e)
+    p = np.int64(1) << e
+    out[pos] = (8 * e + ((d - p) * 8) // p)[pos]
+    return out
+
+
 def features(dv, da, dc, b) -> np.ndarray:
     """Feature rows (n, 4) of wedges with centre degree dv, endpoint degrees
     da, dc (unordered) and centre bin b."""
     lo = np.minimum(da, dc)
     hi = np.maximum(da, dc)
-    x = np.stack([mitchell_log2(dv), mitchell_log2(lo), mitchell_log2(hi),
-                  np.asarray(b, dtype=np.float64)], axis=1) / 32.0
+    x = np.stack([bucket(dv) / 256.0, bucket(lo) / 256.0, bucket(hi) / 256.0,
+                  np.asarray(b, dtype=np.float64) / 32.0], axis=1)
     return x
 
 

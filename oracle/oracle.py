@@ -82,6 +82,11 @@ def lib():
         L.orc_triangles_forward.restype = ctypes.c_uint64
         L.orc_estimate.argtypes = [_u64p, _u64p, _u64p, ctypes.c_uint32, ctypes.c_uint64,
                                    ctypes.c_double, _f64p, _f64p]
+        L.orc_bucket.argtypes = [ctypes.c_uint64]
+        L.orc_bucket.restype = ctypes.c_uint32
+        L.orc_pair_census.argtypes = [_u64p, _u32p, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint64, ctypes.c_uint32, _u64p]
+        L.orc_pair_census.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -264,3 +269,24 @@ def k_for_bins(p_b, k: int) -> np.ndarray:
     """k samples for every bin with wedges, 0 for the others (Thm cd-est)."""
     pb = np.asarray(p_b, dtype=np.uint64)
     return np.where(pb > 0, np.uint64(k), np.uint64(0)).astype(np.uint64)
+
+
+def bucket(d: int) -> int:
+    """floor(8 L(d)) with L Mitchell's log2 (control-variate feature bucket)."""
+    return int(lib().orc_bucket(d))
+
+
+def pair_census(g: Graph, tau: int, omega: int, max_bins: int) -> dict:
+    """{(bin, centre bucket, lo bucket, hi bucket): wedges} by enumeration."""
+    out = np.zeros(max_bins * 256 ** 3, dtype=np.uint64)
+    col = g.col if g.col.size > 0 else np.zeros(1, dtype=np.uint32)
+    rc = lib().orc_pair_census(_p(g.rowptr, _u64p), _p(col, _u32p), g.n, tau, omega, max_bins,
+                               _p(out, _u64p))
+    if rc != 0:
+        raise ValueError("degree beyond max_bins")
+    nz = np.nonzero(out)[0]
+    res = {}
+    for f in nz:
+        f = int(f)
+        res[(f >> 24, (f >> 16) & 255, (f >> 8) & 255, f & 255)] = int(out[f])
+    return res

@@ -478,6 +478,42 @@ uint64_t orc_triangles_forward(const uint64_t* rowptr, const uint32_t* col, uint
   return t;
 }
 
+// ------------------------------------------------- control-variate pair table
+// Bucket of a degree: floor(8 L(d)) with L Mitchell's log2,
+// L(d) = e + (d - 2^e)/2^e, e = floor(log2 d): 8e + floor(8 (d - 2^e) / 2^e).
+uint32_t orc_bucket(uint64_t d) {
+  if (d == 0) return 0;
+  uint32_t e = 63 - (uint32_t)__builtin_clzll(d);
+  uint64_t p = (uint64_t)1 << e;
+  return 8 * e + (uint32_t)(((d - p) * 8) / p);
+}
+
+// Census of every wedge by (centre bin, centre bucket, smaller endpoint
+// bucket, larger endpoint bucket), by enumeration of all neighbour pairs of
+// every centre (Sec. 2.1).  Entry for bin b, centre bucket k and bucket pair
+// (i <= j) at ((b * 256 + k) * 256 + i) * 256 + j of out[max_bins*256^3]
+// (caller zeroes; small graphs only).
+int orc_pair_census(const uint64_t* rowptr, const uint32_t* col, uint32_t n, uint32_t tau,
+                    uint64_t omega, uint32_t max_bins, uint64_t* out) {
+  BinTable bins(tau, omega, max_bins);
+  for (uint32_t v = 0; v < n; ++v) {
+    uint64_t d = rowptr[v + 1] - rowptr[v];
+    if (d < 2) continue;
+    uint32_t b = bins(d);
+    if (b >= max_bins) return -1;
+    uint32_t k = orc_bucket(d);
+    for (uint64_t x = rowptr[v]; x < rowptr[v + 1]; ++x)
+      for (uint64_t y = x + 1; y < rowptr[v + 1]; ++y) {
+        uint32_t a = col[x], c = col[y];
+        uint32_t ba = orc_bucket(rowptr[a + 1] - rowptr[a]);
+        uint32_t bc = orc_bucket(rowptr[c + 1] - rowptr[c]);
+        uint32_t i = ba < bc ? ba : bc, j = ba < bc ? bc : ba;
+        out[(((uint64_t)b * 256 + k) * 256 + i) * 256 + j] += 1;
+      }
+  }
+  return 0;
+}
+
 // ---------------------------------------------------------------- estimates
 // Alg. phase4c summary and Eq. global_est, in double, in this order:
 //   c_b = (q1+q2+q3)/k_b;  t_b = (p_b * (6q1+3q2+2q3)) / (6 k_b)

@@ -41,6 +41,8 @@ static size_t index_layout(uint64_t n_total, uint64_t m_total, uint32_t G, uint3
   off += round_up(sizeof(BinMeta) * (size_t)G * ((size_t)max_bins + 1), 256);
   if (v) v->vlist = (uint32_t*)(c + off);
   off += round_up((size_t)n_total * 4, 256);
+  if (v) v->vrow = (uint64_t*)(c + off);
+  off += round_up((size_t)n_total * 8, 256);
   if (v) v->cls_deg = (uint32_t*)(c + off);
   off += round_up(cap * 4, 256);
   if (v) v->cls_start = (uint32_t*)(c + off);
@@ -100,6 +102,7 @@ struct ClassLoad {
 
 struct ClassApply {
   const uint64_t* k;
+  const uint64_t* rowptr;
   uint64_t N;
   uint64_t cap;
   uint64_t dmask;
@@ -107,6 +110,7 @@ struct ClassApply {
   __device__ void operator()(uint64_t i, uint64_t prefix, uint64_t first) const {
     const uint64_t x = k[i];
     ix.vlist[i] = (uint32_t)x;
+    ix.vrow[i] = rowptr[(uint32_t)x];
     if (first) {
       if (prefix < cap) {
         ix.cls_deg[prefix] = (uint32_t)((x >> 32) & dmask);
@@ -295,7 +299,7 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
   uint64_t* sorted = nullptr;
   rc = radix_sort(w.keys_a, w.keys_b, n, shifts, np, radix_scratch(w.radix, n), st, &sorted);
   if (rc) return rc;
-  rc = scan_apply<uint64_t>(ClassLoad{sorted}, ClassApply{sorted, n, cap, dmask, ix}, n,
+  rc = scan_apply<uint64_t>(ClassLoad{sorted}, ClassApply{sorted, d_rowptr, n, cap, dmask, ix}, n,
                             w.scan_ws, st);
   if (rc) return rc;
   rc = scan_apply<uint64_t>(WedgeLoad{ix, n}, CumwApply{ix}, cap, w.scan_ws, st);

@@ -73,6 +73,7 @@ struct IndexView {
   IndexHeader* hdr;
   BinMeta* bins;      // [max_bins + 1]
   uint32_t* vlist;    // [n] vertices ordered by (degree, id)
+  uint64_t* vrow;     // [n] rowptr[vlist[i]]: adjacency start of each centre
   uint32_t* cls_deg;  // [class_cap] degree of class j (ascending)
   uint32_t* cls_start;// [class_cap] first position of class j in vlist
   uint64_t* cls_cumw; // [class_cap] inclusive prefix of count_j * C(d_j, 2)
@@ -102,6 +103,10 @@ size_t csr_workspace_bytes(uint64_t m_in);
 int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint32_t n,
               const uint64_t* d_eoff, const uint32_t* d_voff, uint32_t G, uint64_t* d_rowptr,
               uint32_t* d_col, uint64_t* d_info, void* d_workspace, hipStream_t st);
+
+// Forward pass of the control-variate network (mlp.hip).
+int mlp_forward_impl(const void* d_state, const wedge_feature_rec* d_x, uint64_t n, float* d_g,
+                     hipStream_t st);
 
 // Graph of global vertex v: last g with voff[g] <= v (voff[0] = 0).
 __device__ inline uint32_t graph_of(const uint32_t* __restrict__ voff, uint32_t G, uint32_t v) {

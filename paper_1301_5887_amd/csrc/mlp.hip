@@ -53,14 +53,6 @@ __device__ inline s4 pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
   return r;
 }
 
-// Mitchell's log2: e + (d - 2^e) / 2^e with e = floor(log2 d); exact in
-// FP32 for d < 2^24.
-__device__ inline float mitchell(uint32_t d) {
-  if (d == 0) return 0.0f;
-  const int e = 31 - __clz(d);
-  const uint32_t p = 1u << e;
-  return (float)e + (float)(d - p) / (float)p;
-}
 
 __device__ inline float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
 __device__ inline float gelu_grad(float a) {
@@ -69,10 +61,19 @@ __device__ inline float gelu_grad(float a) {
   return cdf + a * pdf;
 }
 
+// Log-degree bucket K(d) = floor(8 L(d)), L Mitchell's log2, in integers.
+__device__ inline uint32_t log_bucket(uint32_t d) {
+  if (d == 0) return 0;
+  const uint32_t e = 31 - __clz(d);
+  return 8 * e + (uint32_t)((((uint64_t)d - (1ULL << e)) * 8) >> e);
+}
+
+// x = (K(d_v), K(d_lo), K(d_hi)) / 256 and bin / 32: every value is exact in
+// BF16, so the network is a function of (bin, bucket, bucket, bucket).
 __device__ inline void features(const wedge_feature_rec& r, float x[4]) {
-  x[0] = mitchell(r.dv) * 0.03125f;
-  x[1] = mitchell(r.dlo) * 0.03125f;
-  x[2] = mitchell(r.dhi) * 0.03125f;
+  x[0] = (float)log_bucket(r.dv) * 0.00390625f;
+  x[1] = (float)log_bucket(r.dlo) * 0.00390625f;
+  x[2] = (float)log_bucket(r.dhi) * 0.00390625f;
   x[3] = (float)r.bin * 0.03125f;
 }
 
@@ -474,6 +475,19 @@ extern "C" int wedge_mlp_init(void* d_state, uint64_t seed, void* stream) {
   return WEDGE_OK;
 }
 
+namespace wedge {
+int mlp_forward_impl(const void* d_state, const wedge_feature_rec* d_x, uint64_t n, float* d_g,
+                     hipStream_t st) {
+  if (n == 0) return WEDGE_OK;
+  uint64_t tiles = (n + 15) / 16;
+  uint64_t blocks = (tiles + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  k_mlp_forward<<<(unsigned)blocks, 256, 0, st>>>((const MlpState*)d_state, d_x, n, d_g);
+  WEDGE_LAUNCH_CHECK("k_mlp_forward");
+  return WEDGE_OK;
+}
+}  // namespace wedge
+
 extern "C" int wedge_mlp_forward(const void* d_state, const wedge_feature_rec* d_x, uint64_t n,
                                  float* d_g, void* stream) {
   clear_error();
@@ -481,13 +495,7 @@ extern "C" int wedge_mlp_forward(const void* d_state, const wedge_feature_rec* d
   if (!d_state || !d_x || !d_g) return set_error(WEDGE_EINVAL, "wedge_mlp_forward: null pointer");
   if (!aligned(d_state, 256) || !aligned(d_x, 16) || !aligned(d_g, 4))
     return set_error(WEDGE_EINVAL, "wedge_mlp_forward: misaligned pointer");
-  uint64_t tiles = (n + 15) / 16;
-  uint64_t blocks = (tiles + 3) / 4;
-  if (blocks > 4096) blocks = 4096;
-  k_mlp_forward<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>((const MlpState*)d_state, d_x,
-                                                                   n, d_g);
-  WEDGE_LAUNCH_CHECK("k_mlp_forward");
-  return WEDGE_OK;
+  return mlp_forward_impl(d_state, d_x, n, d_g, (hipStream_t)stream);
 }
 
 extern "C" size_t wedge_mlp_grad_workspace(uint64_t n) {

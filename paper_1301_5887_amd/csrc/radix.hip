@@ -21,13 +21,58 @@ __global__ __launch_bounds__(kRadixWG) void k_radix_hist(const uint64_t* __restr
   uint32_t c = 0;
 #pragma unroll
   for (int w = 0; w < kRadixWG / 64; ++w) c += s_h[w][tid];
-  hist[(uint64_t)tid * ntiles + blockIdx.x] = c;
+  hist[(uint64_t)blockIdx.x * 256 + tid] = c;
 }
 
-struct LoadHist {
-  const uint32_t* h;
-  __device__ uint64_t operator()(uint64_t i) const { return h[i]; }
-};
+// Column scan of the tile-major histogram table hist[tile][digit]:
+// offs[tile][d] = base[d] + sum_{t < tile} hist[t][d], base[d] = number of
+// keys with a smaller digit.  Chunks of kChunk tiles: per-chunk column sums,
+// one workgroup scans chunks and digits, then each chunk writes its rows.
+constexpr uint32_t kChunk = 256;
+
+__global__ __launch_bounds__(256) void k_colsum(const uint32_t* __restrict__ hist,
+                                                uint32_t ntiles,
+                                                uint64_t* __restrict__ chunk_sum) {
+  const uint32_t d = threadIdx.x;
+  const uint64_t t0 = (uint64_t)blockIdx.x * kChunk;
+  const uint64_t t1 = min(t0 + kChunk, (uint64_t)ntiles);
+  uint64_t s = 0;
+  for (uint64_t t = t0; t < t1; ++t) s += hist[t * 256 + d];
+  chunk_sum[(uint64_t)blockIdx.x * 256 + d] = s;
+}
+
+__global__ __launch_bounds__(256) void k_colscan_top(uint64_t* __restrict__ chunk_sum,
+                                                     uint32_t nchunks) {
+  __shared__ uint64_t s_w[4];
+  const uint32_t d = threadIdx.x, lane = d & 63, wave = d >> 6;
+  uint64_t total = 0;
+  for (uint32_t c = 0; c < nchunks; ++c) total += chunk_sum[(uint64_t)c * 256 + d];
+  const uint64_t incl = wave_incl_scan(total, (int)lane);
+  if (lane == 63) s_w[wave] = incl;
+  __syncthreads();
+  uint64_t run = incl - total;
+  for (uint32_t w = 0; w < wave; ++w) run += s_w[w];
+  for (uint32_t c = 0; c < nchunks; ++c) {  // in place: exclusive prefix per chunk
+    const uint64_t x = chunk_sum[(uint64_t)c * 256 + d];
+    chunk_sum[(uint64_t)c * 256 + d] = run;
+    run += x;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_colscan_apply(const uint32_t* __restrict__ hist,
+                                                       uint32_t ntiles,
+                                                       const uint64_t* __restrict__ chunk_pre,
+                                                       uint64_t* __restrict__ offs) {
+  const uint32_t d = threadIdx.x;
+  const uint64_t t0 = (uint64_t)blockIdx.x * kChunk;
+  const uint64_t t1 = min(t0 + kChunk, (uint64_t)ntiles);
+  uint64_t run = chunk_pre[(uint64_t)blockIdx.x * 256 + d];
+  for (uint64_t t = t0; t < t1; ++t) {
+    offs[t * 256 + d] = run;
+    run += hist[t * 256 + d];
+  }
+}
+
 
 __global__ __launch_bounds__(kRadixWG) void k_radix_scatter(const uint64_t* __restrict__ in,
                                                             uint64_t* __restrict__ out, uint64_t N,
@@ -43,7 +88,7 @@ __global__ __launch_bounds__(kRadixWG) void k_radix_scatter(const uint64_t* __re
   const uint64_t tile = blockIdx.x;
   const uint64_t base = tile * kRadixTile;
   for (int i = tid; i < (kRadixWG / 64) * 256; i += kRadixWG) (&s_cnt[0][0])[i] = 0;
-  s_glob[tid] = offs[(uint64_t)tid * ntiles + tile];
+  s_glob[tid] = offs[tile * 256 + tid];
   __syncthreads();
 
   // Wave w owns tile positions [w*64*I, (w+1)*64*I); item i of lane l sits at
@@ -122,9 +167,13 @@ int radix_sort(uint64_t* keys, uint64_t* alt, uint64_t N, const int* shifts, int
     for (int p = 0; p < npass; ++p) {
       k_radix_hist<<<(unsigned)nt, kRadixWG, 0, st>>>(a, N, shifts[p], sc.hist, (uint32_t)nt);
       WEDGE_LAUNCH_CHECK("k_radix_hist");
-      int rc = scan_apply<uint64_t>(LoadHist{sc.hist}, StoreExclusive<uint64_t>{sc.offs},
-                                    256 * nt, sc.scan_ws, st);
-      if (rc != WEDGE_OK) return rc;
+      const uint32_t nchunks = (uint32_t)ceil_div(nt, kChunk);
+      k_colsum<<<nchunks, 256, 0, st>>>(sc.hist, (uint32_t)nt, sc.scan_ws);
+      WEDGE_LAUNCH_CHECK("k_colsum");
+      k_colscan_top<<<1, 256, 0, st>>>(sc.scan_ws, nchunks);
+      WEDGE_LAUNCH_CHECK("k_colscan_top");
+      k_colscan_apply<<<nchunks, 256, 0, st>>>(sc.hist, (uint32_t)nt, sc.scan_ws, sc.offs);
+      WEDGE_LAUNCH_CHECK("k_colscan_apply");
       k_radix_scatter<<<(unsigned)nt, kRadixWG, 0, st>>>(a, b, N, shifts[p], sc.offs,
                                                          (uint32_t)nt);
       WEDGE_LAUNCH_CHECK("k_radix_scatter");

@@ -1,8 +1,8 @@
 // LSD radix sort of uint64 keys over chosen 8-bit digits (stable per pass).
 //
-// One pass = per-tile digit histograms (LDS atomics), one device-wide scan
-// of the digit-major histogram table (tile offsets for every digit), and a
-// scatter kernel that ranks each key stably inside its tile with wave
+// One pass = per-tile digit histograms (LDS atomics, stored tile-major), a
+// column scan of that table (tile offsets for every digit), and a scatter
+// kernel that ranks each key stably inside its tile with wave
 // ballots (a match mask over the 8 digit bits), reorders the tile in LDS,
 // and writes runs of equal digits contiguously so the stores coalesce.
 #pragma once
@@ -18,8 +18,8 @@ constexpr int kRadixWG = 256;
 constexpr int kRadixItems = 16;
 constexpr int kRadixTile = kRadixWG * kRadixItems;  // 4096 keys, 32 KB in LDS
 
-// Scratch for sorting N keys: histogram (u32) and offsets (u64) tables plus
-// the scan's partials.
+// Scratch for sorting N keys: tile-major histogram (u32) and offset (u64)
+// tables [tile][digit], and per-chunk column sums.
 struct RadixScratch {
   uint32_t* hist;
   uint64_t* offs;
@@ -31,7 +31,7 @@ inline size_t radix_scratch_bytes(uint64_t N) {
   uint64_t t = radix_tiles(N);
   if (t == 0) t = 1;
   return round_up(256 * t * 4, 256) + round_up(256 * t * 8, 256) +
-         round_up(scan_ws_elems(256 * t) * 8, 256);
+         round_up(256 * (ceil_div(t, 256) + 1) * 8, 256);
 }
 inline RadixScratch radix_scratch(void* p, uint64_t N) {
   uint64_t t = radix_tiles(N);

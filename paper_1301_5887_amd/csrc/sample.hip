@@ -8,8 +8,9 @@
 // entry per distinct degree, or every S-th entry when the row has more than
 // the LDS holds) in LDS, then each lane carries U independent samples
 // through the dependent gather chain
-//     Philox -> centre class (LDS search) -> vlist -> rowptr[v] -> col (a, c)
-//            -> rowptr[a], rowptr[c] -> binary search in the shorter row,
+//     Philox -> centre class (LDS search) -> adjacency start of the centre
+//            -> col (a, c) -> rowptr[a], rowptr[c] -> binary search in the
+//            shorter row,
 // issuing the loads of its U samples back to back so that U x (waves per CU)
 // chains are in flight per CU.  Class counts are reduced per wave with
 // shuffles, per workgroup in LDS, and added to the row's four uint64
@@ -134,8 +135,14 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       vi[u] = st + (W[u] - cprev) / pv;
       if (vi[u] >= A.n) vi[u] = A.n - 1;  // unreachable for a consistent index
     }
+    // the centre's adjacency start comes straight from the index; its id is
+    // only needed for a dump
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = act[u] ? A.ix.vlist[vi[u]] : 0;
+    for (int u = 0; u < U; ++u) rp[u] = act[u] ? A.ix.vrow[vi[u]] : 0;
+    if (A.dump) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = act[u] ? A.ix.vlist[vi[u]] : 0;
+    }
     // 3. ordered pair of distinct neighbours, numbered in ascending id order
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -149,8 +156,6 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
         ic[u] = r + (r >= i ? 1 : 0);
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) rp[u] = act[u] ? rowptr[v[u]] : 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       a[u] = act[u] ? col[rp[u] + ia[u]] : 0;

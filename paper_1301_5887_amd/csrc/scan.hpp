@@ -3,8 +3,9 @@
 // scan_apply(load, apply, N, ws): for every i < N, apply(i, prefix_i, x_i)
 // with x_i = load(i) and prefix_i = sum_{j<i} x_j.  Phase 1 reduces tiles of
 // 4096 elements to partial sums, phase 2 scans the partials (recursively),
-// phase 3 rescans each tile in LDS and calls the consumer, so a compaction or
-// an offset table is written in the same pass that computes its positions.
+// phase 3 rescans each tile in registers and calls the consumer, so a
+// compaction or an offset table is written in the same pass that computes
+// its positions.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,8 +17,6 @@ namespace wedge {
 constexpr int kScanWG = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanWG * kScanItems;
-
-__host__ __device__ constexpr int scan_pad(int j) { return j + (j >> 4); }
 
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T x, int lane) {
@@ -58,44 +57,41 @@ __global__ __launch_bounds__(kScanWG) void k_scan_reduce(Load load, uint64_t N, 
   }
 }
 
+// Element (it, tid) of a tile is global index base + it * 256 + tid (striped,
+// coalesced).  Each of the 16 rows is scanned across the wave with shuffles;
+// the four wave totals of every row go through LDS.
 template <class T, class Load, class Apply>
 __global__ __launch_bounds__(kScanWG) void k_scan_apply(Load load, Apply apply, uint64_t N,
                                                         const T* block_prefix) {
-  __shared__ T s[scan_pad(kScanTile)];
-  __shared__ T s_w[kScanWG / 64];
+  __shared__ T s_tot[kScanItems][kScanWG / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-  T v[kScanItems];
+  T v[kScanItems], ex[kScanItems];
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
-    int j = it * kScanWG + tid;
-    uint64_t g = base + j;
+    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
     v[it] = g < N ? load(g) : T(0);
-    s[scan_pad(j)] = v[it];
   }
-  __syncthreads();
-  T tsum = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) tsum += s[scan_pad(tid * kScanItems + i)];
-  T incl = wave_incl_scan(tsum, lane);
-  if (lane == 63) s_w[wave] = incl;
+  for (int it = 0; it < kScanItems; ++it) {
+    const T incl = wave_incl_scan(v[it], lane);
+    ex[it] = incl - v[it];
+    if (lane == 63) s_tot[it][wave] = incl;
+  }
   __syncthreads();
   T run = block_prefix ? block_prefix[blockIdx.x] : T(0);
-  for (int w = 0; w < wave; ++w) run += s_w[w];
-  run += incl - tsum;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    int j = scan_pad(tid * kScanItems + i);
-    T x = s[j];
-    s[j] = run;
-    run += x;
-  }
-  __syncthreads();
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
-    int j = it * kScanWG + tid;
-    uint64_t g = base + j;
-    if (g < N) apply(g, s[scan_pad(j)], v[it]);
+    T row = 0, before = 0;
+#pragma unroll
+    for (int w = 0; w < kScanWG / 64; ++w) {
+      const T x = s_tot[it][w];
+      if (w < wave) before += x;
+      row += x;
+    }
+    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
+    if (g < N) apply(g, run + before + ex[it], v[it]);
+    run += row;
   }
 }
 

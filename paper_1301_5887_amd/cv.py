@@ -121,6 +121,66 @@ def moments(rec: torch.Tensor, gv: torch.Tensor, rows: int, stride: int, per_row
     return out
 
 
+KPAIRS = 256 * 257 // 2
+
+
+class Census:
+    """wedge_cv_census of a graph and the exact means it yields."""
+
+    def __init__(self, g: W.Csr, bi: W.BinIndex, stream=None):
+        dev = g.rowptr.device
+        self.bi = bi
+        self.buf = W._empty_bytes(int(_L().wedge_cv_census_bytes(bi.max_bins)), dev)
+        W._check(_L().wedge_cv_census(W._ptr(g.rowptr), W._ptr(g.col), g.n, g.m,
+                                      W._ptr(bi.index), bi.max_bins, bi.tau, bi.omega,
+                                      W._ptr(self.buf), self.buf.numel(), W._stream(stream)))
+        cap = 256 + bi.max_bins + 1
+        nk = ctypes.c_uint32(0)
+        kb = np.zeros(cap, dtype=np.uint32)
+        kk = np.zeros(cap, dtype=np.uint32)
+        W._check(_L().wedge_cv_census_keys(W._ptr(self.buf), bi.max_bins, ctypes.byref(nk),
+                                           kb.ctypes.data_as(W._vp), kk.ctypes.data_as(W._vp),
+                                           W._stream(stream)))
+        self.nkeys = nk.value
+        self.key_bin = kb[: self.nkeys].copy()
+        self.key_bucket = kk[: self.nkeys].copy()
+
+    def table(self) -> np.ndarray:
+        """[nkeys, 32896] wedge counts (host copy)."""
+        off = _table_offset(self.bi.max_bins)
+        t = self.buf[off: off + 8 * self.nkeys * KPAIRS].view(torch.int64)
+        return t.cpu().numpy().view(np.uint64).reshape(self.nkeys, KPAIRS)
+
+    def means(self, net: "Mlp", stream=None) -> dict:
+        """Exact mean of g over the wedges of every bin (and 'global')."""
+        dev = self.buf.device
+        cap = 256 + self.bi.max_bins + 1
+        ws = W._empty_bytes(int(_L().wedge_cv_exact_mean_workspace(self.bi.max_bins)), dev)
+        ksum = torch.zeros(cap, dtype=torch.float64, device=dev)
+        kcnt = torch.zeros(cap, dtype=torch.int64, device=dev)
+        W._check(_L().wedge_cv_exact_mean(W._ptr(net.state), W._ptr(self.buf), self.bi.max_bins,
+                                          W._ptr(ksum), W._ptr(kcnt), W._ptr(ws), ws.numel(),
+                                          W._stream(stream)))
+        s = ksum.cpu().numpy()[: self.nkeys]
+        c = W.to_host_u64(kcnt)[: self.nkeys]
+        B = self.bi.max_bins
+        num = np.zeros(B)
+        den = np.zeros(B, dtype=np.uint64)
+        for key in range(self.nkeys):          # keys in increasing degree order
+            num[self.key_bin[key]] += s[key]
+            den[self.key_bin[key]] += c[key]
+        out = {b: num[b] / float(den[b]) for b in range(B) if den[b] > 0}
+        out[B] = float(num.sum()) / float(den.sum()) if den.sum() > 0 else 0.0
+        self.counts = den
+        return out
+
+
+def _table_offset(max_bins: int) -> int:
+    cap = 256 + max_bins + 1
+    r = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    return r(8) + r(max_bins * 256 * 4) + 3 * r(cap * 4)
+
+
 @dataclass
 class RowStats:
     n: int = 0
@@ -131,6 +191,19 @@ class RowStats:
     an: int = 0
     ag: int = 0
     ag2: int = 0
+
+
+def rho2_from_moments(m) -> float:
+    """Squared correlation of X and g (the fraction of Var X a control
+    variate with the best beta removes)."""
+    n, sx, sg, sg2, sxg = (int(v) for v in m)
+    if n < 2:
+        return 0.0
+    mx, mg = sx / n, sg / Q32 / n
+    cov = sxg / Q32 / n - mx * mg
+    vg = sg2 / Q32 / n - mg * mg
+    vx = mx - mx * mx
+    return cov * cov / (vx * vg) if vx > 0 and vg > 1e-14 else 0.0
 
 
 def beta_from_moments(m) -> float:
@@ -144,8 +217,11 @@ def beta_from_moments(m) -> float:
     return cov / var if var > 1e-14 else 0.0
 
 
-def cv_row_estimate(st: RowStats, beta: float, delta_i: float, use_aux: bool):
-    """(estimate, half-width) of one row from its moments."""
+def cv_row_estimate(st: RowStats, beta: float, delta_i: float, use_aux: bool,
+                    exact_mean: float | None = None):
+    """(estimate, half-width) of one row from its moments; with exact_mean
+    the control variate's mean is known and the whole delta_i goes to the
+    EVAL bound."""
     n = st.n
     if n < 2:
         return float("nan"), float("inf")
@@ -155,6 +231,9 @@ def cv_row_estimate(st: RowStats, beta: float, delta_i: float, use_aux: bool):
     vg = (st.sg2 / Q32 - n * mg * mg) / (n - 1)
     cxg = (st.sxg / Q32 - n * mx * mg) / (n - 1)
     vz = vx - 2 * beta * cxg + beta * beta * vg
+    if exact_mean is not None:
+        return (mx - beta * mg) + beta * exact_mean, eb_halfwidth(n, vz, 1.0 + abs(beta),
+                                                                  delta_i)
     if not use_aux:
         return mx, eb_halfwidth(n, vx, 1.0, delta_i)
     e_eval = eb_halfwidth(n, vz, 1.0 + abs(beta), delta_i / 2)
@@ -187,9 +266,11 @@ class SequentialResult:
 
 def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: float, seed: int,
                net: Mlp | None, beta: dict | None, n0: int = 1 << 14,
-               max_per_row: int = 1 << 26, stream=None) -> SequentialResult:
-    """EVAL (and, with a network, AUX) blocks of doubling size until every
-    row's half-width at delta_i = delta / (i (i+1)) is <= eps."""
+               max_per_row: int = 1 << 26, exact_means: dict | None = None,
+               stream=None) -> SequentialResult:
+    """EVAL (and, with a network and no exact means, AUX) blocks of
+    doubling size until every row's half-width at delta_i = delta / (i (i+1))
+    is <= eps."""
     dev = g.rowptr.device
     B = bi.max_bins
     rows = sorted(rows)
@@ -216,7 +297,7 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             net.forward(recs, A * blk, gv, stream=stream)
         m = W.to_host_u64(moments(recs, gv, A, blk, blk)).view(np.int64).reshape(A, 5)
         am = None
-        if net is not None:
+        if net is not None and exact_means is None:
             arecs = new_records(A, blk, dev)
             sample_features(g, bi, hk, done_at, seed, DOMAIN_AUX, False, arecs, blk,
                             stream=stream)
@@ -232,7 +313,8 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             if am is not None:
                 st.an += int(am[j, 0]); st.ag += int(am[j, 2]); st.ag2 += int(am[j, 3])
             b = beta.get(r, 0.0) if beta else 0.0
-            est, hw = cv_row_estimate(st, b, delta_i, use_aux=net is not None)
+            em = exact_means.get(r) if (exact_means is not None and net is not None) else None
+            est, hw = cv_row_estimate(st, b, delta_i, use_aux=net is not None, exact_mean=em)
             res.estimates[r], res.halfwidth[r] = est, hw
             res.eval_samples[r] = st.n
             res.aux_samples[r] = st.an
@@ -262,6 +344,7 @@ class TrainResult:
     losses: list
     train_samples: int
     seconds: float
+    rho2: dict = field(default_factory=dict)
 
 
 def train(g: W.Csr, bi: W.BinIndex, rows: list[int], n_train: int, seed: int,
@@ -295,6 +378,60 @@ def train(g: W.Csr, bi: W.BinIndex, rows: list[int], n_train: int, seed: int,
     n_hold = per_row - n_fit
     mom = _holdout_moments(recs, gv, R, per_row, n_fit, n_hold)
     beta = {r: beta_from_moments(mom[i]) for i, r in enumerate(rows)}
+    rho2 = {r: rho2_from_moments(mom[i]) for i, r in enumerate(rows)}
     torch.cuda.synchronize()
     return TrainResult(net=net, beta=beta, losses=losses, train_samples=per_row * R,
-                       seconds=time.perf_counter() - t0)
+                       seconds=time.perf_counter() - t0, rho2=rho2)
+
+
+def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, seed: int = 11,
+            n_train: int = 10_000_000, epochs: int = 2, per_row_batch: int = 1024,
+            lr: float = 2e-3, n0: int = 1 << 16) -> dict:
+    """Samples and wall time to reach a half-width <= eps at confidence
+    1 - delta on every sampled bin and on the global stream, for plain
+    sampling with the empirical-Bernstein stopping rule and for the learned
+    control variate with the same rule.  TRAIN draws count as closure
+    checks of the control-variate form; AUX draws (no closure test) are
+    reported separately."""
+    B = bi.max_bins
+    rows = [r for r in range(B) if bi.h_p_b[r] > 0] + [B]
+    torch.cuda.synchronize()
+    pe = sequential(g, bi, rows, eps, delta, seed, None, None, n0=n0)
+    tr = train(g, bi, rows, n_train, seed, epochs=epochs, per_row_batch=per_row_batch, lr=lr)
+    cvr = sequential(g, bi, rows, eps, delta, seed, tr.net, tr.beta, n0=n0)
+    t0 = time.perf_counter()
+    census = Census(g, bi)
+    means = census.means(tr.net)
+    torch.cuda.synchronize()
+    t_census = time.perf_counter() - t0
+    cvx = sequential(g, bi, rows, eps, delta, seed, tr.net, tr.beta, n0=n0, exact_means=means)
+    per_row = {}
+    for r in rows:
+        name = "global" if r == B else str(r)
+        per_row[name] = {"beta": round(tr.beta[r], 5), "rho2": round(tr.rho2[r], 5),
+                         "plain_eb_samples": pe.eval_samples[r],
+                         "cv_eval_samples": cvr.eval_samples[r],
+                         "cv_aux_samples": cvr.aux_samples[r],
+                         "cv_exact_eval_samples": cvx.eval_samples[r],
+                         "exact_mean_g": means.get(r),
+                         "plain_eb_estimate": pe.estimates[r], "cv_estimate": cvr.estimates[r],
+                         "cv_exact_estimate": cvx.estimates[r],
+                         "plain_eb_halfwidth": pe.halfwidth[r], "cv_halfwidth": cvr.halfwidth[r],
+                         "cv_exact_halfwidth": cvx.halfwidth[r]}
+    cv_checks = cvr.total_eval + tr.train_samples
+    return {
+        "eps": eps, "delta": delta, "rows": len(rows),
+        "plain_eb": {"closure_checks": pe.total_eval, "seconds": pe.seconds, "rounds": pe.rounds},
+        "learned_cv": {"closure_checks": cv_checks, "eval_checks": cvr.total_eval,
+                       "train_checks": tr.train_samples, "aux_draws": cvr.total_aux,
+                       "seconds": cvr.seconds + tr.seconds, "train_seconds": tr.seconds,
+                       "rounds": cvr.rounds, "final_train_loss": tr.losses[-1]},
+        "learned_cv_exact_mean": {"closure_checks": cvx.total_eval + tr.train_samples,
+                                  "eval_checks": cvx.total_eval,
+                                  "train_checks": tr.train_samples,
+                                  "seconds": cvx.seconds + tr.seconds + t_census,
+                                  "census_seconds": t_census, "rounds": cvx.rounds},
+        "network_gain_eval_checks": pe.total_eval / max(cvr.total_eval, 1),
+        "network_gain_eval_checks_exact_mean": pe.total_eval / max(cvx.total_eval, 1),
+        "per_row": per_row,
+    }

@@ -208,3 +208,103 @@ def test_cv_unbiased_and_not_worse_than_plain(c1):
         se = max(e.std(ddof=1), 1e-6) / math.sqrt(R)
         assert abs(e.mean() - c_true) <= 3.5 * se + 1e-9, (r, e.mean(), c_true, se)
         assert e.std(ddof=1) <= 1.5 * np.std(ests_pl[r], ddof=1) + 1e-6
+
+
+def small_graphs():
+    e = np.array([[1, 2], [1, 3], [2, 4], [3, 4], [3, 5], [4, 5], [4, 6]], dtype=np.uint32)
+    yield "worked_example", 7, e[:, 0], e[:, 1]
+    rng = np.random.default_rng(12)
+    yield "random", 300, rng.integers(0, 300, 3000).astype(np.uint32), \
+        rng.integers(0, 300, 3000).astype(np.uint32)
+    n, src, dst = gen.chung_lu_c1(1)
+    yield "chung_lu", n, src, dst
+
+
+@pytest.mark.parametrize("case", ["worked_example", "random", "chung_lu"])
+def test_census_matches_oracle(case):
+    name, n, src, dst = next(c for c in small_graphs() if c[0] == case)
+    print(f"[cv] census {name}", flush=True)
+    tau, omega, B = 2, 2, 24
+    g = W.build_csr(dev(src), dev(dst), n)
+    bi = W.bin_counts(g, tau, omega, B)
+    cen = C.Census(g, bi)
+    tab = cen.table()
+    og = O.build_graph(src, dst, n)
+    ref = O.pair_census(og, tau, omega, B)
+    got = {}
+    for key in range(cen.nkeys):
+        nz = np.nonzero(tab[key])[0]
+        for p in nz:
+            j = int((math.isqrt(8 * int(p) + 1) - 1) // 2)
+            i = int(p) - j * (j + 1) // 2
+            got[(int(cen.key_bin[key]), int(cen.key_bucket[key]), i, j)] = int(tab[key, p])
+    assert got == ref
+    per_bin = np.zeros(B, dtype=np.uint64)
+    for (b, k, i, j), c in ref.items():
+        per_bin[b] += c
+    assert (per_bin == bi.h_p_b).all()
+
+
+def test_exact_mean_matches_oracle_and_sampling(c1):
+    g, bi, og = c1
+    B = bi.max_bins
+    theta = M.init_params(21)
+    net = net_with(theta)
+    cen = C.Census(g, bi)
+    means = cen.means(net)
+    ref = O.pair_census(og, 2, 2, B)
+    num = np.zeros(B)
+    den = np.zeros(B)
+    keys = list(ref.keys())
+    kb = np.array([k[0] for k in keys])
+    x = np.stack([np.array([k[1] for k in keys]) / 256.0, np.array([k[2] for k in keys]) / 256.0,
+                  np.array([k[3] for k in keys]) / 256.0, kb / 32.0], axis=1)
+    go, _ = M.forward(theta, x, rounding=True)
+    cnt = np.array([ref[k] for k in keys], dtype=np.float64)
+    for b in range(B):
+        sel = kb == b
+        if sel.any():
+            num[b] = (cnt[sel] * go[sel]).sum()
+            den[b] = cnt[sel].sum()
+    for b in range(B):
+        if den[b] > 0:
+            assert abs(means[b] - num[b] / den[b]) < 2e-3, b
+    # the mean over uniform EVAL draws agrees within sampling error
+    rows = [b for b in range(B) if bi.h_p_b[b] > 0]
+    k = 1 << 16
+    hk = np.zeros(B + 1, dtype=np.uint64)
+    hk[rows] = k
+    recs = C.new_records(len(rows), k)
+    C.sample_features(g, bi, hk, 0, 9, C.DOMAIN_EVAL, False, recs, k)
+    gv = torch.zeros(len(rows) * k, dtype=torch.float32, device="cuda")
+    net.forward(recs, len(rows) * k, gv)
+    emp = gv.cpu().numpy().reshape(len(rows), k).astype(np.float64)
+    for j, b in enumerate(rows):
+        se = emp[j].std(ddof=1) / math.sqrt(k)
+        assert abs(emp[j].mean() - means[b]) <= 5 * se + 1e-7, (b, emp[j].mean(), means[b], se)
+
+
+def test_exact_mean_cv_unbiased_and_tighter(c1):
+    g, bi, og = c1
+    B = bi.max_bins
+    P = O.exact(og, 2, 2, B)
+    rows = [r for r in range(B) if bi.h_p_b[r] > 0]
+    tr = C.train(g, bi, rows, 200_000, seed=4, epochs=2)
+    means = C.Census(g, bi).means(tr.net)
+    ests, pl = {r: [] for r in rows}, {r: [] for r in rows}
+    R, n = 24, 1 << 12
+    for sd in range(R):
+        cvx = C.sequential(g, bi, rows, 1e-9, 1e-3, 300 + sd, tr.net, tr.beta, n0=n,
+                           max_per_row=n, exact_means=means)
+        p = C.sequential(g, bi, rows, 1e-9, 1e-3, 300 + sd, None, None, n0=n, max_per_row=n)
+        for r in rows:
+            ests[r].append(cvx.estimates[r])
+            pl[r].append(p.estimates[r])
+    worse = 0
+    for r in rows:
+        c_true = float(P[r, 1:].sum()) / float(bi.h_p_b[r])
+        e = np.array(ests[r])
+        se = max(e.std(ddof=1), 1e-6) / math.sqrt(R)
+        assert abs(e.mean() - c_true) <= 3.5 * se + 1e-9, (r, e.mean(), c_true, se)
+        worse += e.std(ddof=1) > np.std(pl[r], ddof=1)
+    assert worse <= len(rows) // 2

@@ -24,7 +24,8 @@ def dev(a):
 
 def index_vlist(bi, n):
     """Centre order stored in the index: header (256 B), bin rows
-    ((max_bins+1) x 64 B, padded to 256 B), then vlist[n]."""
+    ((max_bins+1) x 64 B, padded to 256 B), then vlist[n] (then the centres'
+    adjacency starts)."""
     off = 256 + ((bi.max_bins + 1) * 64 + 255) // 256 * 256
     raw = bi.index[off:off + 4 * n].cpu().numpy().view(np.uint32)
     return raw.copy()
