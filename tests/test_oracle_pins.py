@@ -524,3 +524,45 @@ def test_estimate_formulas_reference_values():
     assert per_bin[2, 3] == 1 and per_bin[0, 3] == 0
     assert glob[0] == 0.75 and glob[1] == 0.75 * 10 / 3
     assert glob[2] == 0.75 and glob[3] == 0.75 * 10 / 3
+
+
+def _bucket_by_definition(d: int) -> int:
+    """floor(8 * Mitchell log2 d) in integers: with e = floor(log2 d),
+    8 (e + (d - 2^e) / 2^e) floors to 8 e + floor(8 (d - 2^e) / 2^e)."""
+    e = d.bit_length() - 1
+    return 8 * e + (8 * (d - (1 << e))) // (1 << e)
+
+
+def test_bucket_is_floor_of_eight_mitchell_log2():
+    from oracle import mlp_oracle as M
+    ds = list(range(1, 5000)) + [2**20 - 1, 2**20, 2**20 + 1, 3 * 2**25, 2**32 - 1]
+    for d in ds:
+        ref = math.floor(8 * float(M.mitchell_log2(np.array([d]))[0]))
+        assert O.bucket(d) == ref == _bucket_by_definition(d), d
+    assert O.bucket(1) == 0 and O.bucket(2) == 8 and O.bucket(3) == 12
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_pair_census_matches_wedge_enumeration(seed):
+    """Census of (bin, centre bucket, endpoint bucket pair) against every
+    wedge listed one by one; its bin sums are the p_b of Alg. phase1b."""
+    from collections import Counter
+    rng = np.random.default_rng(100 + seed)
+    n = 60
+    edges = random_edges(rng, n, 260)
+    edges += [(0, j) for j in range(1, 45)]          # a hub spreads many buckets
+    src = np.array([e[0] for e in edges], dtype=np.uint32)
+    dst = np.array([e[1] for e in edges], dtype=np.uint32)
+    adj = BF.simple_graph(edges, n)
+    deg = {v: len(nb) for v, nb in adj.items()}
+    want = Counter()
+    for v, a, c in BF.all_wedges(adj):
+        lo, hi = sorted((deg[a], deg[c]))
+        want[(O.bin_id(deg[v], 2, 2), _bucket_by_definition(deg[v]),
+              _bucket_by_definition(lo), _bucket_by_definition(hi))] += 1
+    g = O.build_graph(src, dst, n)
+    got = O.pair_census(g, 2, 2, 64)
+    assert got == dict(want)
+    _, p_b = O.bins(g, 2, 2, 64)
+    for b in range(64):
+        assert sum(w for key, w in got.items() if key[0] == b) == int(p_b[b])
