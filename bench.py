@@ -199,7 +199,9 @@ def main():
                                     "seconds": avg["sample_close"] / 1000.0}
         log(f"[bench] estimator comparison: plain-Hoeffding {K} checks, plain-EB "
             f"{cvcmp['plain_eb']['closure_checks']}, learned-CV "
-            f"{cvcmp['learned_cv']['closure_checks']} (eval {cvcmp['learned_cv']['eval_checks']})")
+            f"{cvcmp['learned_cv_exact_mean']['closure_checks']} "
+            f"(eval {cvcmp['learned_cv_exact_mean']['eval_checks']}, "
+            f"{cvcmp['learned_cv_exact_mean']['seconds']:.4f} s)")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -353,17 +353,18 @@ enum { WEDGE_DOMAIN_SAMPLE = 1, WEDGE_DOMAIN_TRAIN = 2, WEDGE_DOMAIN_AUX = 3,
        WEDGE_DOMAIN_EVAL = 4 };
 
 /* The sampler of wedge_sample_close with key (seed, domain), samples
- * s = s_begin .. s_begin + h_k[r] - 1 of every row r (bins r < max_bins and
- * the global stream r = max_bins; h_k has max_bins + 1 entries).  Rows with
- * h_k[r] > 0, taken in increasing r, fill record rows j = 0, 1, ...: the
- * record of sample s of the j-th such row goes to
- * d_out[j * out_stride + (s - s_begin)].
+ * s = s_begin[r] .. s_begin[r] + h_k[r] - 1 of every row r (bins r < max_bins
+ * and the global stream r = max_bins; h_k and h_s_begin have max_bins + 1
+ * entries, h_s_begin nullable = all zero).  Rows with h_k[r] > 0, taken in
+ * increasing r, fill record rows j = 0, 1, ...: the record of sample s of the
+ * j-th such row goes to d_out[j * out_stride + (s - s_begin[r])].
  * closure = 0 skips the closure search (records get closed = cls = 0).
  * d_q (nullable) receives the class counts of these samples as in
  * wedge_sample_close.  Requires h_k[r] <= out_stride. */
 int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
                           uint64_t m, const void* d_index, uint32_t max_bins, uint32_t tau,
-                          uint64_t omega, const uint64_t* h_k, uint64_t s_begin, uint64_t seed,
+                          uint64_t omega, const uint64_t* h_k, const uint64_t* h_s_begin,
+                          uint64_t seed,
                           uint32_t domain, uint32_t graph_id, int closure,
                           wedge_feature_rec* d_out, uint64_t out_stride, uint64_t* d_q,
                           void* stream);
@@ -394,28 +395,45 @@ int wedge_mlp_grad(const void* d_state, const wedge_feature_rec* d_x, uint32_t r
  * BF16 copy is refreshed. */
 int wedge_mlp_adam(void* d_state, const float* d_grad, uint32_t t, float lr, float beta1,
                    float beta2, float eps, void* stream);
+/* Minibatch training as one sequence of device work: for each of `epochs`
+ * passes over columns 0 .. n_fit - 1 of the `rows` rows of d_x[rows][stride]
+ * (n_fit a multiple of per_row_batch, n_fit <= stride), minibatches of
+ * per_row_batch consecutive columns of every row, each a wedge_mlp_grad
+ * followed by a wedge_mlp_adam at steps t0 + 1, t0 + 2, ...  The loss of the
+ * last minibatch goes to d_loss (device FP32, nullable).  Workspace:
+ * wedge_mlp_train_workspace(rows, per_row_batch) bytes. */
+size_t wedge_mlp_train_workspace(uint32_t rows, uint64_t per_row_batch);
+int wedge_mlp_train(void* d_state, const wedge_feature_rec* d_x, uint32_t rows, uint64_t stride,
+                    uint64_t n_fit, uint64_t per_row_batch, uint32_t epochs, uint32_t t0,
+                    float lr, float beta1, float beta2, float eps, float* d_loss,
+                    void* d_workspace, size_t workspace_bytes, void* stream);
 
 /* Moments of the control variate over records d_x (rows x stride, the first
- * n_per_row of each row used) with network outputs d_g (same layout), added
+ * n_per_row of each row used, or the first h_counts[r] of row r when the host
+ * array h_counts is given) with network outputs d_g (same layout), added
  * into d_mom[rows][5] (int64, caller zeroes):
  *   [0] count, [1] sum X, [2] round(2^32 sum g), [3] round(2^32 sum g^2),
  *   [4] round(2^32 sum X g)
  * with every term rounded to 2^-32 before summing, so sums are exact and
  * independent of order.  X = closed. */
 int wedge_cv_moments(const wedge_feature_rec* d_x, const float* d_g, uint32_t rows,
-                     uint64_t stride, uint64_t n_per_row, int64_t* d_mom, void* stream);
+                     uint64_t stride, uint64_t n_per_row, const uint64_t* h_counts,
+                     int64_t* d_mom, void* stream);
 
 /* Census of the wedges of every bin by (bin, centre bucket, endpoint bucket
  * pair), buckets K(d) = floor(8 L(d)) as in the network's features.  With
  * it the mean of the network over all wedges of bin b is the finite sum
  *   mu_b = (1/p_b) sum_keys sum_{i<=j} census[key][i,j] g(key, i, j),
  * which makes the control variate's mean exact (no auxiliary draws).
- * d_census: wedge_cv_census_bytes(max_bins) bytes, 256-byte aligned; keys
- * are the (bin, centre bucket) pairs degrees >= 2 can take, numbered in
+ * d_census: wedge_cv_census_bytes(n, m, max_bins) bytes, 256-byte aligned;
+ * keys are the (bin, centre bucket) pairs degrees >= 2 can take, numbered in
  * increasing degree order; the count of key `key` and bucket pair
- * (i <= j < 256) is entry j (j + 1) / 2 + i of its row of 32896 uint64.
+ * (i <= j < 256) is entry j (j + 1) / 2 + i of its row of 32896 uint64.  The
+ * key list and the table sit at offsets that depend on max_bins only; the
+ * rest of the buffer is per-graph scratch (a bucket byte per vertex and the
+ * total degree before each degree class).
  * In: the graph and index as for wedge_sample_close. */
-size_t wedge_cv_census_bytes(uint32_t max_bins);
+size_t wedge_cv_census_bytes(uint32_t n, uint64_t m, uint32_t max_bins);
 int wedge_cv_census(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
                     const void* d_index, uint32_t max_bins, uint32_t tau, uint64_t omega,
                     void* d_census, size_t census_bytes, void* stream);
@@ -425,7 +443,8 @@ int wedge_cv_census_keys(const void* d_census, uint32_t max_bins, uint32_t* h_nk
                          uint32_t* h_key_bin, uint32_t* h_key_bucket, void* stream);
 /* For every key: d_key_sum[key] = sum over its bucket pairs of
  * census * g (FP64, fixed summation order) and d_key_count[key] = its wedge
- * count (sums to p_b over the keys of bin b).  Workspace:
+ * count (sums to p_b over the keys of bin b).  Reads the key count from the
+ * device first (synchronises the stream).  Workspace:
  * wedge_cv_exact_mean_workspace(max_bins) bytes. */
 size_t wedge_cv_exact_mean_workspace(uint32_t max_bins);
 int wedge_cv_exact_mean(const void* d_state, const void* d_census, uint32_t max_bins,

@@ -2,59 +2,19 @@
 // the input convention of Sec. 4.1 / 5.1: undirected, self-loops and
 // repeated edges carry no meaning).
 //
-// 1. k_canon_keys: each input edge (u, w) becomes the two directed keys
-//    u<<32|w and w<<32|u (a self-loop stays a key u<<32|u; an edge with an
-//    id >= n becomes the self-loop 0<<32|0 and is counted as rejected).
-// 2. LSD radix sort over the significant digits of dst, then of src.
-// 3. One fused scan pass: a key is kept iff it is not a self-loop and
-//    differs from its predecessor; its exclusive count is its position in
-//    col, and every change of src writes the row starts it spans.
+// 1. Onesweep LSD radix sort of the directed keys u<<32|w and w<<32|u of
+//    every input edge (u, w) over the significant digits of dst, then of
+//    src; the first pass builds the keys from the edge list as it reads it
+//    (a self-loop stays a key u<<32|u; an edge with an id >= n becomes the
+//    self-loop 0<<32|0 and is counted as rejected).
+// 2. One scan over the sorted keys: a key is kept iff it is not a self-loop
+//    and differs from its predecessor; its exclusive count is its position
+//    in col, and every change of src writes the row starts it spans.
 #include "common.hpp"
 #include "radix.hpp"
 #include "scan.hpp"
 
 namespace wedge {
-
-// Graph of edge i of a batch: last g with eoff[g] <= i.
-__device__ inline uint32_t graph_of_edge(const uint64_t* __restrict__ eoff, uint32_t G,
-                                         uint64_t i) {
-  uint32_t lo = 0, hi = G;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (eoff[mid] <= i) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-// Edge i -> the keys u<<32|w and w<<32|u in global ids.  In a batch (G > 1)
-// ids are local to their graph and are shifted by the graph's vertex offset.
-__global__ void k_canon_keys(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
-                             uint64_t m_in, uint32_t n, const uint64_t* __restrict__ eoff,
-                             const uint32_t* __restrict__ voff, uint32_t G,
-                             uint64_t* __restrict__ keys, unsigned long long* __restrict__ rejected) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (; i < m_in; i += stride) {
-    uint64_t u = src[i], w = dst[i];
-    uint64_t base = 0, lim = n;
-    if (G > 1) {
-      const uint32_t g = graph_of_edge(eoff, G, i);
-      base = voff[g];
-      lim = voff[g + 1] - base;
-    }
-    if (u >= lim || w >= lim) {
-      atomicAdd(rejected, 1ULL);
-      u = w = 0;
-    } else {
-      u += base;
-      w += base;
-    }
-    ulonglong2 kv;
-    kv.x = (u << 32) | w;
-    kv.y = (w << 32) | u;
-    reinterpret_cast<ulonglong2*>(keys)[i] = kv;
-  }
-}
 
 struct DedupLoad {
   const uint64_t* k;
@@ -66,34 +26,74 @@ struct DedupLoad {
   }
 };
 
-struct DedupApply {
-  const uint64_t* k;
-  uint64_t N;
-  uint32_t n;
-  uint32_t* col;
-  uint64_t* rowptr;
-  uint64_t* info;
-  __device__ void operator()(uint64_t i, uint64_t prefix, uint64_t keep) const {
-    const uint64_t x = k[i];
-    const uint32_t s = (uint32_t)(x >> 32);
-    if (keep) col[prefix] = (uint32_t)x;
-    // rowptr[v] = number of kept keys with src < v: the first key of each
-    // src writes it for every vertex since the previous key's src.
-    uint64_t first_v;
-    if (i == 0) {
-      first_v = 0;
-    } else {
-      const uint32_t sp = (uint32_t)(k[i - 1] >> 32);
-      first_v = (sp == s) ? (uint64_t)s + 1 : (uint64_t)sp + 1;
-    }
-    for (uint64_t v = first_v; v <= s; ++v) rowptr[v] = prefix;
-    if (i == N - 1) {
-      const uint64_t total = prefix + keep;
-      for (uint64_t v = (uint64_t)s + 1; v <= n; ++v) rowptr[v] = total;
-      info[0] = total / 2;
-    }
+// Row starts and compaction over the sorted keys.  Element (it, tid) of a
+// tile of kScanTile keys is base + it * 256 + tid (coalesced); every key and
+// its predecessor are loaded before the scan, so the writes that follow wait
+// on no further loads.
+__global__ __launch_bounds__(kScanWG) void k_dedup_apply(const uint64_t* __restrict__ k,
+                                                         uint64_t N, uint32_t n,
+                                                         const uint64_t* __restrict__ block_prefix,
+                                                         uint32_t* __restrict__ col,
+                                                         uint64_t* __restrict__ rowptr,
+                                                         uint64_t* __restrict__ info) {
+  __shared__ uint64_t s_tot[kScanItems][kScanWG / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint64_t x[kScanItems], prev[kScanItems];
+#pragma unroll
+  for (int it = 0; it < kScanItems; ++it) {
+    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
+    x[it] = g < N ? k[g] : 0;
+    prev[it] = (g > 0 && g < N) ? k[g - 1] : ~0ULL;
   }
-};
+  uint32_t keep = 0;  // bit it: key (it, tid) is kept
+  uint64_t ex[kScanItems];
+#pragma unroll
+  for (int it = 0; it < kScanItems; ++it) {
+    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
+    const bool loop = (uint32_t)(x[it] >> 32) == (uint32_t)x[it];
+    const uint64_t v = (g < N && !loop && x[it] != prev[it]) ? 1 : 0;
+    keep |= (uint32_t)v << it;
+    const uint64_t incl = wave_incl_scan(v, lane);
+    ex[it] = incl - v;
+    if (lane == 63) s_tot[it][wave] = incl;
+  }
+  __syncthreads();
+  uint64_t run = block_prefix ? block_prefix[blockIdx.x] : 0;
+#pragma unroll
+  for (int it = 0; it < kScanItems; ++it) {
+    uint64_t row = 0, before = 0;
+#pragma unroll
+    for (int w = 0; w < kScanWG / 64; ++w) {
+      const uint64_t t = s_tot[it][w];
+      if (w < wave) before += t;
+      row += t;
+    }
+    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
+    if (g < N) {
+      const uint64_t prefix = run + before + ex[it];
+      const bool kept = (keep >> it) & 1;
+      const uint32_t s = (uint32_t)(x[it] >> 32);
+      if (kept) col[prefix] = (uint32_t)x[it];
+      // rowptr[v] = number of kept keys with src < v: the first key of each
+      // src writes it for every vertex since the previous key's src.
+      uint64_t first_v;
+      if (g == 0) {
+        first_v = 0;
+      } else {
+        const uint32_t sp = (uint32_t)(prev[it] >> 32);
+        first_v = (sp == s) ? (uint64_t)s + 1 : (uint64_t)sp + 1;
+      }
+      for (uint64_t v = first_v; v <= s; ++v) rowptr[v] = prefix;
+      if (g == N - 1) {
+        const uint64_t total = prefix + (kept ? 1 : 0);
+        for (uint64_t v = (uint64_t)s + 1; v <= n; ++v) rowptr[v] = total;
+        info[0] = total / 2;
+      }
+    }
+    run += row;
+  }
+}
 
 struct CsrWorkspace {
   uint64_t* keys_a;
@@ -117,7 +117,7 @@ static size_t csr_layout(uint64_t m_in, CsrWorkspace* w, void* base) {
   if (w) w->scan_ws = (uint64_t*)(c + off);
   off += round_up(scan_ws_elems(N) * 8, 256);
   if (w) w->radix = (void*)(c + off);
-  off += radix_scratch_bytes(N);
+  off += os_scratch_bytes(N);
   return off;
 }
 
@@ -132,24 +132,34 @@ int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint3
   int rc = fill<uint64_t>(d_info, 2, 0, st);
   if (rc) return rc;
   if (N == 0) return fill<uint64_t>(d_rowptr, (uint64_t)n + 1, 0, st);
-  {
-    uint64_t blocks = ceil_div(m_in, 256);
-    if (blocks > 1u << 20) blocks = 1u << 20;
-    k_canon_keys<<<(unsigned)blocks, 256, 0, st>>>(d_src, d_dst, m_in, n, d_eoff, d_voff, G,
-                                                   w.keys_a, (unsigned long long*)(d_info + 1));
-    WEDGE_LAUNCH_CHECK("k_canon_keys");
-  }
   // digits of dst (bits 0..nb) then of src (bits 32..32+nb)
   int shifts[16];
   int np = 0;
   const int nb = bit_width((uint64_t)n - 1);
   for (int s = 0; s < nb; s += 8) shifts[np++] = s;
   for (int s = 0; s < nb; s += 8) shifts[np++] = 32 + s;
+  EdgeSource E{d_src, d_dst, m_in, n, d_eoff, d_voff, G, (unsigned long long*)(d_info + 1)};
   uint64_t* sorted = nullptr;
-  rc = radix_sort(w.keys_a, w.keys_b, N, shifts, np, radix_scratch(w.radix, N), st, &sorted);
+  rc = onesweep_sort_edges(E, w.keys_a, w.keys_b, shifts, np, os_scratch(w.radix, N), st, &sorted);
   if (rc) return rc;
-  return scan_apply<uint64_t>(DedupLoad{sorted}, DedupApply{sorted, N, n, d_col, d_rowptr, d_info},
-                              N, w.scan_ws, st);
+  // kept-key counts per tile, their exclusive scan, then the apply pass
+  const uint64_t nb_tiles = ceil_div(N, kScanTile);
+  uint64_t* part = w.scan_ws;
+  if (nb_tiles == 1) {
+    k_dedup_apply<<<1, kScanWG, 0, st>>>(sorted, N, n, nullptr, d_col, d_rowptr, d_info);
+    WEDGE_LAUNCH_CHECK("k_dedup_apply");
+    return WEDGE_OK;
+  }
+  k_scan_reduce<uint64_t, DedupLoad><<<(unsigned)(nb_tiles + 1), kScanWG, 0, st>>>(
+      DedupLoad{sorted}, N, part);
+  WEDGE_LAUNCH_CHECK("k_scan_reduce");
+  rc = scan_apply<uint64_t>(LoadArray<uint64_t>{part}, StoreExclusive<uint64_t>{part},
+                            nb_tiles + 1, part + nb_tiles + 1, st);
+  if (rc) return rc;
+  k_dedup_apply<<<(unsigned)nb_tiles, kScanWG, 0, st>>>(sorted, N, n, part, d_col, d_rowptr,
+                                                        d_info);
+  WEDGE_LAUNCH_CHECK("k_dedup_apply");
+  return WEDGE_OK;
 }
 
 }  // namespace wedge

@@ -54,11 +54,11 @@ __device__ inline s4 pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
 }
 
 
-__device__ inline float gelu(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
-__device__ inline float gelu_grad(float a) {
-  const float cdf = 0.5f * (1.0f + erff(a * 0.70710678118654752f));
-  const float pdf = expf(-0.5f * a * a) * 0.39894228040143268f;
-  return cdf + a * pdf;
+// GELU(a) = a Phi(a) with Phi the standard normal CDF; its derivative is
+// Phi(a) + a phi(a).  The forward pass keeps Phi for the backward pass.
+__device__ inline float norm_cdf(float a) { return 0.5f * (1.0f + erff(a * 0.70710678118654752f)); }
+__device__ inline float gelu_grad_from(float a, float cdf) {
+  return cdf + a * (expf(-0.5f * a * a) * 0.39894228040143268f);
 }
 
 // Log-degree bucket K(d) = floor(8 L(d)), L Mitchell's log2, in integers.
@@ -115,24 +115,38 @@ __device__ inline void load_weights(const MlpState* __restrict__ S, WaveWeights&
 
 struct TileAct {
   float a1[4][4];  // pre-activations A1^T[16m+4kb+t][sl]
+  float c1[4][4];  // Phi(a1)
   s4 h1[4];        // BF16 H1^T tiles (B operands of layer 2)
   float a2[4][4];
-  float h2[4][4];
+  float c2[4][4];  // Phi(a2); H2 = a2 * c2
   float z;         // logit of sample sl (same in the 4 lanes of the column)
 };
 
-__device__ inline void forward_tile(const WaveWeights& W, const float x[4], int kb, TileAct& T) {
+// Biases and output weights held in registers (forward kernel).
+struct RegBias {
+  const WaveWeights& W;
+  __device__ float b1(int m, int t) const { return W.b1[m][t]; }
+  __device__ float b2(int m, int t) const { return W.b2[m][t]; }
+  __device__ float w3(int m, int t) const { return W.w3[m][t]; }
+  __device__ float b3() const { return W.b3; }
+};
+
+template <class Bias>
+__device__ inline void forward_tile(const s4 (&w1)[4], const s4 (&w2)[4][4], const Bias& Bs,
+                                    const float x[4], int kb, TileAct& T) {
   const s4 xb = kb == 0 ? pack4(f2bf(x[0]), f2bf(x[1]), f2bf(x[2]), f2bf(x[3])) : pack4(0, 0, 0, 0);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     f4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mfma16(W.w1[m], xb, acc);
+    acc = mfma16(w1[m], xb, acc);
     uint16_t hb[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const float a = acc[t] + W.b1[m][t];
+      const float a = acc[t] + Bs.b1(m, t);
+      const float c = norm_cdf(a);
       T.a1[m][t] = a;
-      hb[t] = f2bf(gelu(a));
+      T.c1[m][t] = c;
+      hb[t] = f2bf(a * c);
     }
     T.h1[m] = pack4(hb[0], hb[1], hb[2], hb[3]);
   }
@@ -141,19 +155,19 @@ __device__ inline void forward_tile(const WaveWeights& W, const float x[4], int 
   for (int m = 0; m < 4; ++m) {
     f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mfma16(W.w2[m][kk], T.h1[kk], acc);
+    for (int kk = 0; kk < 4; ++kk) acc = mfma16(w2[m][kk], T.h1[kk], acc);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const float a = acc[t] + W.b2[m][t];
+      const float a = acc[t] + Bs.b2(m, t);
+      const float c = norm_cdf(a);
       T.a2[m][t] = a;
-      const float h = gelu(a);
-      T.h2[m][t] = h;
-      part += W.w3[m][t] * h;
+      T.c2[m][t] = c;
+      part += Bs.w3(m, t) * (a * c);
     }
   }
   part += __shfl_xor(part, 16, 64);
   part += __shfl_xor(part, 32, 64);
-  T.z = part + W.b3;
+  T.z = part + Bs.b3();
 }
 
 __global__ __launch_bounds__(256) void k_mlp_forward(const MlpState* __restrict__ S,
@@ -170,7 +184,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const MlpState* __restrict_
     float xf[4] = {0.f, 0.f, 0.f, 0.f};
     if (valid) features(x[i], xf);
     TileAct T;
-    forward_tile(W, xf, kb, T);
+    forward_tile(W.w1, W.w2, RegBias{W}, xf, kb, T);
     if (kb == 0 && valid) g[i] = 1.0f / (1.0f + expf(-T.z));
   }
 }
@@ -185,61 +199,179 @@ struct RowView {
   }
 };
 
-// Gradient of the mean BCE over minibatch records [chunk*wg, chunk*(wg+1))
-// into partial[wg][kPad]; one wave per workgroup.
-__global__ __launch_bounds__(64) void k_mlp_grad(const MlpState* __restrict__ S, RowView x,
-                                                 uint64_t n, uint64_t chunk, float inv_n,
-                                                 float* __restrict__ partial,
-                                                 float* __restrict__ loss_partial) {
-  __shared__ uint16_t s_da2[kH][16];  // dA2^T [o][s]
-  __shared__ uint16_t s_h1[kH][16];   // H1^T  [i][s]
-  __shared__ uint16_t s_da1[kH][16];  // dA1^T [i][s]
-  __shared__ uint16_t s_x[16][16];    // X     [s][f], f >= 4 zero
-  const int lane = threadIdx.x, sl = lane & 15, kb = lane >> 4;
-  WaveWeights W;
-  load_weights(S, W, sl, kb);
-  s4 w2t[4][4];  // A tiles of W2^T: [m][kk] = W2[16kk+4kb+j][16m+sl]
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int o = 16 * kk + 4 * kb, i = 16 * m + sl;
-      w2t[m][kk] = pack4(S->bf[OFF_W2 + (o + 0) * kH + i], S->bf[OFF_W2 + (o + 1) * kH + i],
-                         S->bf[OFF_W2 + (o + 2) * kH + i], S->bf[OFF_W2 + (o + 3) * kH + i]);
-    }
+constexpr int kGradWaves = 4;
+constexpr int kGradTilesPerWave = 4;
+constexpr uint64_t kGradChunk = 16ULL * kGradWaves * kGradTilesPerWave;  // records per WG
+
+// LDS operand tiles of one wave (transposes for the weight-gradient products)
+struct GradSmem {
+  uint16_t da2[kH][16];  // dA2^T [o][s]
+  uint16_t h1[kH][16];   // H1^T  [i][s]
+  uint16_t da1[kH][16];  // dA1^T [i][s]
+  uint16_t x[16][16];    // X     [s][f], f >= 4 zero
+};
+
+// LDS ordering between lanes of one wave
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Gradient accumulators of one wave (lane-distributed as the MFMA outputs).
+struct GradAcc {
   f4 dW2[4][4];
   f4 dW1[4];
+  float gW3[4][4], gb2[4][4], gb1[4][4];
+  float gb3, lsum;
+};
+
+// Adds (first = false) or stores (first = true) a wave's accumulators into
+// the parameter-ordered array P; lanes touch disjoint entries, so a whole
+// wave's update needs no atomics.
+__device__ inline void acc_to(const GradAcc& A, float* P, int sl, int kb, int lane, bool first) {
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    dW1[m] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int nn = 0; nn < 4; ++nn) dW2[m][nn] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int nn = 0; nn < 4; ++nn)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float& dst = P[OFF_W2 + (16 * m + 4 * kb + t) * kH + 16 * nn + sl];
+        dst = first ? A.dW2[m][nn][t] : dst + A.dW2[m][nn][t];
+      }
+    if (sl < 4)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float& dst = P[OFF_W1 + (16 * m + 4 * kb + t) * 4 + sl];
+        dst = first ? A.dW1[m][t] : dst + A.dW1[m][t];
+      }
   }
-  float gW3[4][4], gb2[4][4], gb1[4][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) gW3[m][t] = gb2[m][t] = gb1[m][t] = 0.f;
-  float gb3 = 0.f, lsum = 0.f;
+    for (int t = 0; t < 4; ++t) {
+      float a = A.gW3[m][t], b = A.gb2[m][t], c = A.gb1[m][t];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+      }
+      if (sl == 0) {
+        const int h = 16 * m + 4 * kb + t;
+        P[OFF_W3 + h] = first ? a : P[OFF_W3 + h] + a;
+        P[OFF_B2 + h] = first ? b : P[OFF_B2 + h] + b;
+        P[OFF_B1 + h] = first ? c : P[OFF_B1 + h] + c;
+      }
+    }
+  float gb3 = A.gb3, lsum = A.lsum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    gb3 += __shfl_xor(gb3, off, 64);
+    lsum += __shfl_xor(lsum, off, 64);
+  }
+  if (lane == 0) {
+    P[OFF_B3] = first ? gb3 : P[OFF_B3] + gb3;
+    P[NPARAM] = first ? lsum : P[NPARAM] + lsum;  // loss sum in the padding
+  }
+}
 
-  const uint64_t begin = (uint64_t)blockIdx.x * chunk;
-  const uint64_t end = min(begin + chunk, n);
-  for (uint64_t base = begin; base < end; base += 16) {
+// Biases and output weights read from LDS (gradient kernel).
+struct LdsBias {
+  const float* pb1;
+  const float* pb2;
+  const float* pw3;
+  float pb3;
+  int kb;
+  __device__ float b1(int m, int t) const { return pb1[16 * m + 4 * kb + t]; }
+  __device__ float b2(int m, int t) const { return pb2[16 * m + 4 * kb + t]; }
+  __device__ float w3(int m, int t) const { return pw3[16 * m + 4 * kb + t]; }
+  __device__ float b3() const { return pb3; }
+};
+
+// Gradient of the mean BCE over minibatch records [kGradChunk*wg, +kGradChunk)
+// into partial[wg][kPad] (entry NPARAM holds the loss sum).  Four waves per
+// workgroup, each on its own 16-record tiles; the waves' sums are combined in
+// LDS in wave order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const MlpState* __restrict__ S,
+                                                              RowView x, uint64_t n, float inv_n,
+                                                              float* __restrict__ partial) {
+  __shared__ GradSmem s_w[kGradWaves];
+  __shared__ float s_p[kPad];
+  __shared__ float s_b1[kH], s_b2[kH], s_w3[kH], s_b3;
+  __shared__ s4 s_w2t[4][4][64];  // A tiles of W2^T [m][kk][lane]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sl = lane & 15, kb = lane >> 4;
+  GradSmem& sm = s_w[wave];
+  // operand tiles of W1 and W2 stay in registers; biases, W3 and the W2^T
+  // tiles of the backward product come from LDS
+  s4 w1[4], w2[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int r = 16 * m + sl;
+    w1[m] = kb == 0 ? pack4(S->bf[OFF_W1 + r * 4 + 0], S->bf[OFF_W1 + r * 4 + 1],
+                            S->bf[OFF_W1 + r * 4 + 2], S->bf[OFF_W1 + r * 4 + 3])
+                    : pack4(0, 0, 0, 0);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int c = OFF_W2 + r * kH + 16 * kk + 4 * kb;
+      w2[m][kk] = pack4(S->bf[c], S->bf[c + 1], S->bf[c + 2], S->bf[c + 3]);
+    }
+  }
+  if (tid < kH) {
+    s_b1[tid] = S->master[OFF_B1 + tid];
+    s_b2[tid] = S->master[OFF_B2 + tid];
+    s_w3[tid] = bf2f(S->bf[OFF_W3 + tid]);
+    if (tid == 0) s_b3 = S->master[OFF_B3];
+  }
+  for (int e = tid; e < 16 * 64; e += 64 * kGradWaves) {
+    const int m = e >> 8, kk = (e >> 6) & 3, l = e & 63;
+    const int o = 16 * kk + 4 * (l >> 4), i = 16 * m + (l & 15);
+    s_w2t[m][kk][l] = pack4(S->bf[OFF_W2 + (o + 0) * kH + i], S->bf[OFF_W2 + (o + 1) * kH + i],
+                            S->bf[OFF_W2 + (o + 2) * kH + i], S->bf[OFF_W2 + (o + 3) * kH + i]);
+  }
+  __syncthreads();
+  const LdsBias Bs{s_b1, s_b2, s_w3, s_b3, kb};
+  GradAcc A;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    A.dW1[m] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nn = 0; nn < 4; ++nn) A.dW2[m][nn] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) A.gW3[m][t] = A.gb2[m][t] = A.gb1[m][t] = 0.f;
+  }
+  A.gb3 = 0.f;
+  A.lsum = 0.f;
+
+  const uint64_t begin = (uint64_t)blockIdx.x * kGradChunk;
+  const uint64_t end = min(begin + kGradChunk, n);
+  // the next tile's record is loaded while the current tile is computed
+  wedge_feature_rec next{};
+  {
+    const uint64_t i0 = begin + 16 * (uint64_t)wave + sl;
+    if (i0 < end) next = x[i0];
+  }
+  for (uint64_t base = begin + 16 * (uint64_t)wave; base < end; base += 16 * kGradWaves) {
     const uint64_t i = base + sl;
     const bool valid = i < end;
+    const wedge_feature_rec r = next;
+    {
+      const uint64_t i2 = i + 16 * kGradWaves;
+      if (i2 < end) next = x[i2];
+    }
     float xf[4] = {0.f, 0.f, 0.f, 0.f};
     float y = 0.f;
     if (valid) {
-      features(x[i], xf);
-      y = x[i].closed ? 1.f : 0.f;
+      features(r, xf);
+      y = r.closed ? 1.f : 0.f;
     }
     TileAct T;
-    forward_tile(W, xf, kb, T);
+    forward_tile(w1, w2, Bs, xf, kb, T);
     const float gz = 1.0f / (1.0f + expf(-T.z));
     const float dz = valid ? (gz - y) * inv_n : 0.f;
     if (kb == 0) {
-      gb3 += dz;
-      if (valid) lsum += fmaxf(T.z, 0.f) + log1pf(expf(-fabsf(T.z))) - y * T.z;
+      A.gb3 += dz;
+      if (valid) A.lsum += fmaxf(T.z, 0.f) + log1pf(expf(-fabsf(T.z))) - y * T.z;
     }
     float da2[4][4];
 #pragma unroll
@@ -247,23 +379,23 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const MlpState* __restrict__ S,
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int h = 16 * m + 4 * kb + t;
-        gW3[m][t] += dz * T.h2[m][t];
-        da2[m][t] = dz * W.w3[m][t] * gelu_grad(T.a2[m][t]);
-        gb2[m][t] += da2[m][t];
-        s_da2[h][sl] = f2bf(da2[m][t]);
-        s_h1[h][sl] = (uint16_t)T.h1[m][t];
+        A.gW3[m][t] += dz * (T.a2[m][t] * T.c2[m][t]);
+        da2[m][t] = dz * Bs.w3(m, t) * gelu_grad_from(T.a2[m][t], T.c2[m][t]);
+        A.gb2[m][t] += da2[m][t];
+        sm.da2[h][sl] = f2bf(da2[m][t]);
+        sm.h1[h][sl] = (uint16_t)T.h1[m][t];
       }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s_x[sl][4 * kb + j] = kb == 0 ? f2bf(xf[j]) : (uint16_t)0;
-    __syncthreads();
+    for (int j = 0; j < 4; ++j) sm.x[sl][4 * kb + j] = kb == 0 ? f2bf(xf[j]) : (uint16_t)0;
+    wave_lds_sync();
     // dW2[o][i] += sum_s dA2^T[o][s] H1^T[i][s]
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const s4 a = *reinterpret_cast<const s4*>(&s_da2[16 * m + sl][4 * kb]);
+      const s4 a = *reinterpret_cast<const s4*>(&sm.da2[16 * m + sl][4 * kb]);
 #pragma unroll
       for (int nn = 0; nn < 4; ++nn) {
-        const s4 b = *reinterpret_cast<const s4*>(&s_h1[16 * nn + sl][4 * kb]);
-        dW2[m][nn] = mfma16(a, b, dW2[m][nn]);
+        const s4 b = *reinterpret_cast<const s4*>(&sm.h1[16 * nn + sl][4 * kb]);
+        A.dW2[m][nn] = mfma16(a, b, A.dW2[m][nn]);
       }
     }
     // dH1^T = W2^T dA2^T; dA1^T = dH1^T * GELU'(A1^T)
@@ -273,82 +405,57 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const MlpState* __restrict__ S,
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const s4 b = pack4(f2bf(da2[kk][0]), f2bf(da2[kk][1]), f2bf(da2[kk][2]), f2bf(da2[kk][3]));
-        acc = mfma16(w2t[m][kk], b, acc);
+        acc = mfma16(s_w2t[m][kk][lane], b, acc);
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const float da1 = acc[t] * gelu_grad(T.a1[m][t]);
-        gb1[m][t] += da1;
-        s_da1[16 * m + 4 * kb + t][sl] = f2bf(da1);
+        const float da1 = acc[t] * gelu_grad_from(T.a1[m][t], T.c1[m][t]);
+        A.gb1[m][t] += da1;
+        sm.da1[16 * m + 4 * kb + t][sl] = f2bf(da1);
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     // dW1[i][f] += sum_s dA1^T[i][s] X[s][f]
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const s4 a = *reinterpret_cast<const s4*>(&s_da1[16 * m + sl][4 * kb]);
-      const s4 b = pack4(s_x[4 * kb + 0][sl], s_x[4 * kb + 1][sl], s_x[4 * kb + 2][sl],
-                         s_x[4 * kb + 3][sl]);
-      dW1[m] = mfma16(a, b, dW1[m]);
+      const s4 a = *reinterpret_cast<const s4*>(&sm.da1[16 * m + sl][4 * kb]);
+      const s4 b = pack4(sm.x[4 * kb + 0][sl], sm.x[4 * kb + 1][sl], sm.x[4 * kb + 2][sl],
+                         sm.x[4 * kb + 3][sl]);
+      A.dW1[m] = mfma16(a, b, A.dW1[m]);
     }
+    wave_lds_sync();
+  }
+  // waves in order: 0 stores, 1..3 add
+  for (int w = 0; w < kGradWaves; ++w) {
+    if (wave == w) acc_to(A, s_p, sl, kb, lane, w == 0);
     __syncthreads();
   }
   float* P = partial + (uint64_t)blockIdx.x * kPad;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-#pragma unroll
-    for (int nn = 0; nn < 4; ++nn)
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        P[OFF_W2 + (16 * m + 4 * kb + t) * kH + 16 * nn + sl] = dW2[m][nn][t];
-    if (sl < 4)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) P[OFF_W1 + (16 * m + 4 * kb + t) * 4 + sl] = dW1[m][t];
-  }
-  // per-hidden sums over the 16 samples of a column group
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      float a = gW3[m][t], b = gb2[m][t], c = gb1[m][t];
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-        c += __shfl_xor(c, off, 64);
-      }
-      if (sl == 0) {
-        const int h = 16 * m + 4 * kb + t;
-        P[OFF_W3 + h] = a;
-        P[OFF_B2 + h] = b;
-        P[OFF_B1 + h] = c;
-      }
-    }
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    gb3 += __shfl_xor(gb3, off, 64);
-    lsum += __shfl_xor(lsum, off, 64);
-  }
-  if (lane == 0) {
-    P[OFF_B3] = gb3;
-    loss_partial[blockIdx.x] = lsum;
-  }
+  for (int p = tid; p <= NPARAM; p += 64 * kGradWaves) P[p] = s_p[p];
 }
 
-// Sum of the partial gradients in workgroup order (deterministic).
-__global__ void k_mlp_reduce(const float* __restrict__ partial, uint32_t nwg,
-                             float* __restrict__ grad, const float* __restrict__ loss_partial,
-                             float inv_n, float* __restrict__ loss) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < NPARAM) {
-    float s = 0.f;
-    for (uint32_t w = 0; w < nwg; ++w) s += partial[(uint64_t)w * kPad + p];
-    grad[p] = s;
+// Sum of the partial gradients (deterministic: wave q of a block sums the
+// workgroups w = q mod 4 in order, and the four sums are added in q order);
+// the padding entry NPARAM carries the loss sum.
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ partial,
+                                                    uint32_t nwg, float* __restrict__ grad,
+                                                    float inv_n, float* __restrict__ loss) {
+  __shared__ float s_q[4][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
+  float s = 0.f;
+  if (p <= NPARAM) {
+#pragma unroll 4
+    for (uint32_t w = q; w < nwg; w += 4) s += partial[(uint64_t)w * kPad + p];
   }
-  if (p == 0 && loss) {
-    float s = 0.f;
-    for (uint32_t w = 0; w < nwg; ++w) s += loss_partial[w];
-    *loss = s * inv_n;
+  s_q[q][lane] = s;
+  __syncthreads();
+  if (q == 0 && p <= NPARAM) {
+    const float t = ((s_q[0][lane] + s_q[1][lane]) + s_q[2][lane]) + s_q[3][lane];
+    if (p < NPARAM)
+      grad[p] = t;
+    else if (loss)
+      *loss = t * inv_n;
   }
 }
 
@@ -398,9 +505,19 @@ __global__ void k_mlp_init(MlpState* __restrict__ S, uint64_t seed) {
   S->v[p] = 0.f;
 }
 
-__global__ void k_cv_moments(const wedge_feature_rec* __restrict__ x, const float* __restrict__ g,
-                             uint64_t stride, uint64_t npr, long long* __restrict__ mom) {
-  const uint64_t row = blockIdx.y;
+constexpr int kMomRows = 64;  // rows per launch
+struct RowCounts {
+  uint64_t n[kMomRows];
+};
+
+// Rows row0 + blockIdx.y; row r uses its first counts.n[blockIdx.y] records.
+__global__ __launch_bounds__(256) void k_cv_moments(const wedge_feature_rec* __restrict__ x,
+                                                    const float* __restrict__ g, uint64_t stride,
+                                                    uint32_t row0, RowCounts counts,
+                                                    long long* __restrict__ mom) {
+  __shared__ long long s_m[4][5];
+  const uint64_t row = row0 + blockIdx.y;
+  const uint64_t npr = counts.n[blockIdx.y];
   long long c = 0, sx = 0, sg = 0, sg2 = 0, sxg = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npr;
        i += (uint64_t)gridDim.x * blockDim.x) {
@@ -423,22 +540,41 @@ __global__ void k_cv_moments(const wedge_feature_rec* __restrict__ x, const floa
     sg2 += __shfl_xor(sg2, off, 64);
     sxg += __shfl_xor(sxg, off, 64);
   }
+  const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    unsigned long long* M = (unsigned long long*)(mom + row * 5);
-    atomicAdd(M + 0, (unsigned long long)c);
-    atomicAdd(M + 1, (unsigned long long)sx);
-    atomicAdd(M + 2, (unsigned long long)sg);
-    atomicAdd(M + 3, (unsigned long long)sg2);
-    atomicAdd(M + 4, (unsigned long long)sxg);
+    s_m[wave][0] = c;
+    s_m[wave][1] = sx;
+    s_m[wave][2] = sg;
+    s_m[wave][3] = sg2;
+    s_m[wave][4] = sxg;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {  // integer sums: the order of the atomics does not matter
+    const long long t = s_m[0][threadIdx.x] + s_m[1][threadIdx.x] + s_m[2][threadIdx.x] +
+                        s_m[3][threadIdx.x];
+    atomicAdd((unsigned long long*)(mom + row * 5 + threadIdx.x), (unsigned long long)t);
   }
 }
 
-static uint32_t grad_groups(uint64_t n, uint64_t* chunk) {
-  uint64_t c = (n + 1023) / 1024;
-  if (c < 256) c = 256;
-  c = (c + 15) / 16 * 16;
-  *chunk = c;
-  return (uint32_t)((n + c - 1) / c);
+static uint32_t grad_groups(uint64_t n) { return (uint32_t)ceil_div(n, kGradChunk); }
+
+// One minibatch: gradient into d_grad (and the mean loss into d_loss).
+static int grad_impl(const MlpState* S, const wedge_feature_rec* d_x, uint64_t stride,
+                     uint64_t j0, uint64_t per_row, uint64_t n, float* d_grad, float* d_loss,
+                     float* partial, hipStream_t st) {
+  const uint32_t nwg = grad_groups(n);
+  const float inv_n = 1.0f / (float)n;
+  RowView view{d_x, stride, j0, per_row};
+  k_mlp_grad<<<nwg, 64 * kGradWaves, 0, st>>>(S, view, n, inv_n, partial);
+  WEDGE_LAUNCH_CHECK("k_mlp_grad");
+  k_mlp_reduce<<<(NPARAM + 1 + 63) / 64, 256, 0, st>>>(partial, nwg, d_grad, inv_n, d_loss);
+  WEDGE_LAUNCH_CHECK("k_mlp_reduce");
+  return WEDGE_OK;
+}
+
+static void adam_consts(uint32_t t, float b1, float b2, float* c1, float* c2) {
+  *c1 = (float)(1.0 - pow((double)b1, (double)t));
+  *c2 = (float)(1.0 - pow((double)b2, (double)t));
 }
 
 }  // namespace wedge
@@ -499,9 +635,7 @@ extern "C" int wedge_mlp_forward(const void* d_state, const wedge_feature_rec* d
 }
 
 extern "C" size_t wedge_mlp_grad_workspace(uint64_t n) {
-  uint64_t chunk;
-  const uint32_t nwg = grad_groups(n ? n : 1, &chunk);
-  return round_up((size_t)nwg * kPad * 4, 256) + round_up((size_t)nwg * 4, 256);
+  return round_up((size_t)grad_groups(n ? n : 1) * kPad * 4, 256);
 }
 
 extern "C" int wedge_mlp_grad(const void* d_state, const wedge_feature_rec* d_x, uint32_t rows,
@@ -519,18 +653,8 @@ extern "C" int wedge_mlp_grad(const void* d_state, const wedge_feature_rec* d_x,
     return set_error(WEDGE_EINVAL, "wedge_mlp_grad: misaligned pointer");
   if (workspace_bytes < wedge_mlp_grad_workspace(n))
     return set_error(WEDGE_EWORKSPACE, "wedge_mlp_grad: workspace too small");
-  uint64_t chunk;
-  const uint32_t nwg = grad_groups(n, &chunk);
-  float* partial = (float*)d_workspace;
-  float* lpart = (float*)((char*)d_workspace + round_up((size_t)nwg * kPad * 4, 256));
-  hipStream_t st = (hipStream_t)stream;
-  const float inv_n = 1.0f / (float)n;
-  RowView view{d_x, stride, j0, per_row};
-  k_mlp_grad<<<nwg, 64, 0, st>>>((const MlpState*)d_state, view, n, chunk, inv_n, partial, lpart);
-  WEDGE_LAUNCH_CHECK("k_mlp_grad");
-  k_mlp_reduce<<<(NPARAM + 255) / 256, 256, 0, st>>>(partial, nwg, d_grad, lpart, inv_n, d_loss);
-  WEDGE_LAUNCH_CHECK("k_mlp_reduce");
-  return WEDGE_OK;
+  return grad_impl((const MlpState*)d_state, d_x, stride, j0, per_row, n, d_grad, d_loss,
+                   (float*)d_workspace, (hipStream_t)stream);
 }
 
 extern "C" int wedge_mlp_adam(void* d_state, const float* d_grad, uint32_t t, float lr,
@@ -538,26 +662,80 @@ extern "C" int wedge_mlp_adam(void* d_state, const float* d_grad, uint32_t t, fl
   clear_error();
   if (!d_state || !d_grad) return set_error(WEDGE_EINVAL, "wedge_mlp_adam: null pointer");
   if (t == 0) return set_error(WEDGE_ERANGE, "wedge_mlp_adam: step t must be >= 1");
-  const float c1 = (float)(1.0 - pow((double)beta1, (double)t));
-  const float c2 = (float)(1.0 - pow((double)beta2, (double)t));
+  float c1, c2;
+  adam_consts(t, beta1, beta2, &c1, &c2);
   k_mlp_adam<<<(NPARAM + 255) / 256, 256, 0, (hipStream_t)stream>>>(
       (MlpState*)d_state, d_grad, lr, beta1, beta2, eps, c1, c2);
   WEDGE_LAUNCH_CHECK("k_mlp_adam");
   return WEDGE_OK;
 }
 
-extern "C" int wedge_cv_moments(const wedge_feature_rec* d_x, const float* d_g, uint32_t rows,
-                                uint64_t stride, uint64_t n_per_row, int64_t* d_mom,
-                                void* stream) {
+extern "C" size_t wedge_mlp_train_workspace(uint32_t rows, uint64_t per_row_batch) {
+  return wedge_mlp_grad_workspace((uint64_t)rows * per_row_batch) + round_up(kPad * 4, 256);
+}
+
+extern "C" int wedge_mlp_train(void* d_state, const wedge_feature_rec* d_x, uint32_t rows,
+                               uint64_t stride, uint64_t n_fit, uint64_t per_row_batch,
+                               uint32_t epochs, uint32_t t0, float lr, float beta1, float beta2,
+                               float eps, float* d_loss, void* d_workspace,
+                               size_t workspace_bytes, void* stream) {
   clear_error();
-  if (rows == 0 || n_per_row == 0) return WEDGE_OK;
+  if (rows == 0 || per_row_batch == 0 || n_fit == 0 || epochs == 0)
+    return set_error(WEDGE_ERANGE, "wedge_mlp_train: empty schedule");
+  if (n_fit % per_row_batch != 0 || n_fit > stride)
+    return set_error(WEDGE_ERANGE,
+                     "wedge_mlp_train: n_fit must be a multiple of per_row_batch and <= stride");
+  if (!d_state || !d_x || !d_workspace)
+    return set_error(WEDGE_EINVAL, "wedge_mlp_train: null pointer");
+  if (!aligned(d_state, 256) || !aligned(d_x, 16) || !aligned(d_workspace, 256))
+    return set_error(WEDGE_EINVAL, "wedge_mlp_train: misaligned pointer");
+  if (workspace_bytes < wedge_mlp_train_workspace(rows, per_row_batch))
+    return set_error(WEDGE_EWORKSPACE, "wedge_mlp_train: workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  MlpState* S = (MlpState*)d_state;
+  const uint64_t n = (uint64_t)rows * per_row_batch;
+  float* partial = (float*)d_workspace;
+  float* grad = (float*)((char*)d_workspace + wedge_mlp_grad_workspace(n));
+  uint32_t t = t0;
+  for (uint32_t ep = 0; ep < epochs; ++ep) {
+    for (uint64_t j0 = 0; j0 < n_fit; j0 += per_row_batch) {
+      const bool last = ep + 1 == epochs && j0 + per_row_batch == n_fit;
+      int rc = grad_impl(S, d_x, stride, j0, per_row_batch, n, grad, last ? d_loss : nullptr,
+                         partial, st);
+      if (rc) return rc;
+      float c1, c2;
+      adam_consts(++t, beta1, beta2, &c1, &c2);
+      k_mlp_adam<<<(NPARAM + 255) / 256, 256, 0, st>>>(S, grad, lr, beta1, beta2, eps, c1, c2);
+      WEDGE_LAUNCH_CHECK("k_mlp_adam");
+    }
+  }
+  return WEDGE_OK;
+}
+
+extern "C" int wedge_cv_moments(const wedge_feature_rec* d_x, const float* d_g, uint32_t rows,
+                                uint64_t stride, uint64_t n_per_row, const uint64_t* h_counts,
+                                int64_t* d_mom, void* stream) {
+  clear_error();
+  if (rows == 0) return WEDGE_OK;
   if (!d_x || !d_g || !d_mom) return set_error(WEDGE_EINVAL, "wedge_cv_moments: null pointer");
-  if (n_per_row > stride) return set_error(WEDGE_ERANGE, "wedge_cv_moments: n_per_row > stride");
-  uint64_t bx = (n_per_row + 255) / 256;
-  if (bx > 1024) bx = 1024;
-  dim3 grid((unsigned)bx, rows);
-  k_cv_moments<<<grid, 256, 0, (hipStream_t)stream>>>(d_x, d_g, stride, n_per_row,
-                                                     (long long*)d_mom);
-  WEDGE_LAUNCH_CHECK("k_cv_moments");
+  uint64_t most = 0;
+  for (uint32_t r = 0; r < rows; ++r) {
+    const uint64_t c = h_counts ? h_counts[r] : n_per_row;
+    if (c > stride) return set_error(WEDGE_ERANGE, "wedge_cv_moments: count of row %u > stride", r);
+    most = c > most ? c : most;
+  }
+  if (most == 0) return WEDGE_OK;
+  uint64_t bx = (most + 4095) / 4096;  // about 16 records per thread
+  if (bx > 512) bx = 512;
+  for (uint32_t r0 = 0; r0 < rows; r0 += kMomRows) {
+    const uint32_t nr = rows - r0 < (uint32_t)kMomRows ? rows - r0 : (uint32_t)kMomRows;
+    RowCounts rc;
+    for (int j = 0; j < kMomRows; ++j)
+      rc.n[j] = j < (int)nr ? (h_counts ? h_counts[r0 + j] : n_per_row) : 0;
+    dim3 grid((unsigned)bx, nr);
+    k_cv_moments<<<grid, 256, 0, (hipStream_t)stream>>>(d_x, d_g, stride, r0, rc,
+                                                       (long long*)d_mom);
+    WEDGE_LAUNCH_CHECK("k_cv_moments");
+  }
   return WEDGE_OK;
 }

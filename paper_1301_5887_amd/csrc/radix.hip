@@ -186,4 +186,263 @@ int radix_sort(uint64_t* keys, uint64_t* alt, uint64_t N, const int* shifts, int
   return WEDGE_OK;
 }
 
+
+// ------------------------------------------------------------------ onesweep
+
+struct OsShifts {
+  int s[kOsMaxPasses];
+  int npass;
+};
+
+__device__ inline uint32_t os_graph_of_edge(const uint64_t* __restrict__ eoff, uint32_t G,
+                                            uint64_t i) {
+  uint32_t lo = 0, hi = G;  // last g with eoff[g] <= i
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (eoff[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Key g of the edge list (see EdgeSource); *bad marks an id out of range.
+__device__ inline uint64_t edge_key(const EdgeSource& E, uint64_t g, bool* bad) {
+  const uint64_t i = g >> 1;
+  uint64_t u = E.src[i], w = E.dst[i];
+  uint64_t base = 0, lim = E.n;
+  if (E.G > 1) {
+    const uint32_t gg = os_graph_of_edge(E.eoff, E.G, i);
+    base = E.voff[gg];
+    lim = E.voff[gg + 1] - base;
+  }
+  *bad = u >= lim || w >= lim;
+  if (*bad) {
+    u = w = 0;
+  } else {
+    u += base;
+    w += base;
+  }
+  return (g & 1) ? ((w << 32) | u) : ((u << 32) | w);
+}
+
+// Counts of every digit of every pass over all keys, and the rejected edges.
+__global__ __launch_bounds__(kOsWG) void k_os_hist_edges(EdgeSource E, OsShifts S,
+                                                         uint64_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[kOsMaxPasses][256];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kOsMaxPasses * 256; i += kOsWG) (&s_h[0][0])[i] = 0;
+  __syncthreads();
+  unsigned long long bad_edges = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * kOsWG;
+  for (uint64_t i = (uint64_t)blockIdx.x * kOsWG + tid; i < E.m_in; i += stride) {
+    bool bad;
+    const uint64_t k0 = edge_key(E, 2 * i, &bad);
+    const uint64_t k1 = edge_key(E, 2 * i + 1, &bad);
+    bad_edges += bad ? 1 : 0;
+    for (int p = 0; p < S.npass; ++p) {
+      atomicAdd(&s_h[p][(k0 >> S.s[p]) & 255], 1u);
+      atomicAdd(&s_h[p][(k1 >> S.s[p]) & 255], 1u);
+    }
+  }
+  bad_edges = wave_sum<unsigned long long>(bad_edges);
+  if ((tid & 63) == 0 && bad_edges) atomicAdd(E.rejected, bad_edges);
+  __syncthreads();
+  for (int i = tid; i < S.npass * 256; i += kOsWG) {
+    const uint32_t c = (&s_h[0][0])[i];
+    if (c) atomicAdd((unsigned long long*)&hist[i], (unsigned long long)c);
+  }
+}
+
+// base[p][d] = number of keys whose digit p is below d.
+__global__ __launch_bounds__(256) void k_os_base(const uint64_t* __restrict__ hist,
+                                                 uint64_t* __restrict__ base, int npass) {
+  __shared__ uint64_t s_w[4];
+  const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
+  for (int p = 0; p < npass; ++p) {
+    const uint64_t c = hist[p * 256 + d];
+    const uint64_t incl = wave_incl_scan(c, lane);
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint64_t before = 0;
+    for (int w = 0; w < wave; ++w) before += s_w[w];
+    base[p * 256 + d] = before + incl - c;
+    __syncthreads();
+  }
+}
+
+__device__ inline unsigned long long os_load(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void os_store(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One digit pass.  kEdges: the input keys are made from the edge list.
+template <bool kEdges>
+__global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t* __restrict__ in,
+                                                   uint64_t* __restrict__ out, uint64_t N,
+                                                   int shift, uint64_t tag,
+                                                   const uint64_t* __restrict__ base,
+                                                   unsigned long long* __restrict__ status,
+                                                   unsigned long long* __restrict__ ticket) {
+  constexpr int kWaves = kOsWG / 64;
+  __shared__ uint64_t s_keys[kOsTile];
+  __shared__ uint32_t s_cnt[kWaves][256];
+  __shared__ uint32_t s_tile_off[256];
+  __shared__ uint64_t s_glob[256];
+  __shared__ uint32_t s_wsum[kWaves];
+  __shared__ uint64_t s_tile;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < kWaves * 256; i += kOsWG) (&s_cnt[0][0])[i] = 0;
+  if (tid == 0) s_tile = atomicAdd(ticket, 1ULL);
+  __syncthreads();
+  const uint64_t tile = s_tile;
+  const uint64_t tbase = tile * kOsTile;
+
+  // stable ranking inside the tile (see k_radix_scatter)
+  uint64_t key[kOsItems];
+  uint32_t rank[kOsItems];
+  const uint64_t lt_mask = (1ULL << lane) - 1;
+#pragma unroll
+  for (int it = 0; it < kOsItems; ++it) {
+    const uint64_t g = tbase + (uint64_t)wave * 64 * kOsItems + (uint64_t)it * 64 + lane;
+    const bool valid = g < N;
+    if (kEdges) {
+      bool bad;
+      key[it] = valid ? edge_key(E, g, &bad) : 0;
+    } else {
+      key[it] = valid ? in[g] : 0;
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < kOsItems; ++it) {
+    const uint64_t g = tbase + (uint64_t)wave * 64 * kOsItems + (uint64_t)it * 64 + lane;
+    const bool valid = g < N;
+    const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t before = 0;
+    if (valid) before = s_cnt[wave][d];
+    rank[it] = before + (uint32_t)__popcll(peers & lt_mask);
+    if (valid && (peers & lt_mask) == 0) s_cnt[wave][d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  uint32_t cnt = 0;  // keys of digit tid in the tile
+  if (tid < 256) {
+    const int d = tid;
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = s_cnt[w][d];
+      s_cnt[w][d] = run;
+      run += c;
+    }
+    cnt = run;
+    // publish this tile's count before looking back
+    unsigned long long* mine = status + tile * 256 + d;
+    os_store(mine, tag | (tile == 0 ? kOsInc : kOsAgg) | (uint64_t)cnt);
+  }
+  // tile-local exclusive offsets of the digits (waves 0..3 hold digits)
+  {
+    const uint32_t incl = wave_incl_scan(cnt, lane);
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    if (tid < 256) {
+      uint32_t off = incl - cnt;
+      for (int w = 0; w < wave; ++w) off += s_wsum[w];
+      s_tile_off[tid] = off;
+    }
+  }
+  if (tid < 256) {
+    const int d = tid;
+    uint64_t excl = 0;
+    if (tile > 0) {
+      uint64_t t = tile - 1;
+      uint32_t spins = 0;
+      for (;;) {
+        const unsigned long long x = os_load(status + t * 256 + d);
+        if ((x & ~(kOsValue | kOsAgg | kOsInc)) != tag || (x & (kOsAgg | kOsInc)) == 0) {
+          // every earlier tile is running and publishes without waiting, so
+          // this ends; the bound only guarantees that the wave exits
+          if (++spins > (1u << 24)) {
+            atomicAdd(ticket + kOsMaxPasses, 1ULL);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += x & kOsValue;
+        if (x & kOsInc) break;
+        --t;
+      }
+      os_store(status + tile * 256 + d, tag | kOsInc | (excl + cnt));
+    }
+    s_glob[d] = base[d] + excl - s_tile_off[d];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kOsItems; ++it) {
+    const uint64_t g = tbase + (uint64_t)wave * 64 * kOsItems + (uint64_t)it * 64 + lane;
+    if (g < N) {
+      const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
+      s_keys[s_tile_off[d] + s_cnt[wave][d] + rank[it]] = key[it];
+    }
+  }
+  __syncthreads();
+  const uint64_t valid_n = (N - tbase) < (uint64_t)kOsTile ? (N - tbase) : (uint64_t)kOsTile;
+  for (int j = tid; j < (int)valid_n; j += kOsWG) {
+    const uint64_t k = s_keys[j];
+    const uint32_t d = (uint32_t)(k >> shift) & 255;
+    const uint64_t at = s_glob[d] + (uint64_t)j;
+    if (at < N) out[at] = k;
+  }
+}
+
+int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int* shifts,
+                        int npass, OsScratch sc, hipStream_t st, uint64_t** result) {
+  const uint64_t N = 2 * E.m_in;
+  *result = a;
+  if (N == 0 || npass <= 0) return WEDGE_OK;
+  if (npass > kOsMaxPasses) return set_error(WEDGE_ERANGE, "onesweep: too many passes");
+  const uint64_t nt = os_tiles(N);
+  OsShifts S;
+  S.npass = npass;
+  for (int p = 0; p < kOsMaxPasses; ++p) S.s[p] = p < npass ? shifts[p] : 0;
+  int rc = fill<uint64_t>(sc.hist, kOsMaxPasses * 256, 0, st);
+  if (rc) return rc;
+  if ((rc = fill<unsigned long long>(sc.tickets, kOsMaxPasses + 1, 0, st))) return rc;
+  if ((rc = fill<unsigned long long>(sc.status, nt * 256, 0, st))) return rc;
+  {
+    uint64_t blocks = ceil_div(E.m_in, (uint64_t)kOsWG * 16);
+    if (blocks > 2048) blocks = 2048;
+    if (blocks == 0) blocks = 1;
+    k_os_hist_edges<<<(unsigned)blocks, kOsWG, 0, st>>>(E, S, sc.hist);
+    WEDGE_LAUNCH_CHECK("k_os_hist_edges");
+  }
+  k_os_base<<<1, 256, 0, st>>>(sc.hist, sc.base, npass);
+  WEDGE_LAUNCH_CHECK("k_os_base");
+  uint64_t* src = nullptr;
+  uint64_t* dst = a;
+  for (int p = 0; p < npass; ++p) {
+    const uint64_t tag = (uint64_t)(p + 1) << 56;
+    if (p == 0)
+      k_os_pass<true><<<(unsigned)nt, kOsWG, 0, st>>>(E, nullptr, dst, N, shifts[p], tag,
+                                                       sc.base + p * 256, sc.status,
+                                                       sc.tickets + p);
+    else
+      k_os_pass<false><<<(unsigned)nt, kOsWG, 0, st>>>(E, src, dst, N, shifts[p], tag,
+                                                        sc.base + p * 256, sc.status,
+                                                        sc.tickets + p);
+    WEDGE_LAUNCH_CHECK("k_os_pass");
+    src = dst;
+    dst = (dst == a) ? b : a;
+  }
+  *result = src;
+  return WEDGE_OK;
+}
 }  // namespace wedge

@@ -53,3 +53,75 @@ int radix_sort(uint64_t* keys, uint64_t* alt, uint64_t N, const int* shifts, int
                RadixScratch sc, hipStream_t st, uint64_t** result);
 
 }  // namespace wedge
+
+namespace wedge {
+
+// ------------------------------------------------------------------ onesweep
+// LSD radix sort with one read and one write of the keys per digit: every
+// digit's global histogram comes from a single counting pass, and each tile
+// finds the keys of its digit in earlier tiles by a decoupled look-back
+// (each tile publishes its own digit counts, then walks back over earlier
+// tiles' published counts until it meets an inclusive prefix).  Tiles are
+// handed out by a ticket counter, so every tile a look-back waits on is
+// already running and publishes without waiting on anything.
+constexpr int kOsWG = 512;
+constexpr int kOsItems = 16;
+constexpr int kOsTile = kOsWG * kOsItems;  // 8192 keys, 64 KB in LDS
+constexpr int kOsMaxPasses = 8;
+
+// Status word of (tile, digit): pass tag (8 bits) | flag (2) | count (54).
+constexpr uint64_t kOsAgg = 1ULL << 54;
+constexpr uint64_t kOsInc = 2ULL << 54;
+constexpr uint64_t kOsValue = (1ULL << 54) - 1;
+
+struct OsScratch {
+  uint64_t* hist;                // [kOsMaxPasses][256] global digit counts
+  uint64_t* base;                // [kOsMaxPasses][256] exclusive prefix over digits
+  unsigned long long* tickets;   // [kOsMaxPasses] per pass, then a count of stalled look-backs
+  unsigned long long* status;    // [tiles][256]
+};
+
+inline uint64_t os_tiles(uint64_t N) { return ceil_div(N, kOsTile); }
+inline size_t os_scratch_bytes(uint64_t N) {
+  uint64_t t = os_tiles(N);
+  if (t == 0) t = 1;
+  return round_up(kOsMaxPasses * 256 * 8, 256) * 2 + 256 + round_up(t * 256 * 8, 256);
+}
+inline OsScratch os_scratch(void* p, uint64_t N) {
+  uint64_t t = os_tiles(N);
+  if (t == 0) t = 1;
+  (void)t;
+  char* c = (char*)p;
+  OsScratch s;
+  s.hist = (uint64_t*)c;
+  c += round_up(kOsMaxPasses * 256 * 8, 256);
+  s.base = (uint64_t*)c;
+  c += round_up(kOsMaxPasses * 256 * 8, 256);
+  s.tickets = (unsigned long long*)c;
+  c += 256;
+  s.status = (unsigned long long*)c;
+  return s;
+}
+
+// Directed keys of an edge list: key 2i = u<<32|w and key 2i+1 = w<<32|u of
+// edge i = (u, w); in a batch (G > 1) ids are local to their graph and are
+// shifted by its vertex offset; an edge with an id out of range becomes the
+// self-loop 0<<32|0 (dropped later) and is counted once.
+struct EdgeSource {
+  const uint32_t* src;
+  const uint32_t* dst;
+  uint64_t m_in;
+  uint32_t n;
+  const uint64_t* eoff;  // [G + 1] edge offsets (G > 1)
+  const uint32_t* voff;  // [G + 1] vertex offsets (G > 1)
+  uint32_t G;
+  unsigned long long* rejected;
+};
+
+// Sorts the 2 m_in keys of the edges by the digits at `shifts` (least
+// significant first).  Pass 0 reads the edges and writes a, later passes
+// ping-pong between a and b; *result receives the buffer with the output.
+int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int* shifts,
+                        int npass, OsScratch sc, hipStream_t st, uint64_t** result);
+
+}  // namespace wedge

@@ -57,7 +57,8 @@ __device__ inline uint32_t bin_of_degree(uint64_t d, uint32_t tau, uint64_t omeg
 // One tile: samples [s0, s1) of index row f (graph g, bin word bword).
 template <int U>
 __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint32_t bword,
-                            uint64_t gword, uint64_t s0, uint64_t s1, uint64_t fslot) {
+                            uint64_t gword, uint64_t s0, uint64_t s1, uint64_t fslot,
+                            uint64_t sbase) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const BinMeta M = A.ix.bins[f];
@@ -219,13 +220,13 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       cnt1 += cls == 1;
       cnt2 += cls == 2;
       cnt3 += cls == 3;
-      if (A.dump && s[u] - A.s_begin < A.dump_per_bin) {
+      if (A.dump && s[u] - sbase < A.dump_per_bin) {
         wedge_sample_rec rec;
         rec.v = v[u];
         rec.a = a[u];
         rec.c = c[u];
         rec.cls = cls;
-        A.dump[f * A.dump_per_bin + (s[u] - A.s_begin)] = rec;
+        A.dump[f * A.dump_per_bin + (s[u] - sbase)] = rec;
       }
       if (A.feat) {
         wedge_feature_rec fr;
@@ -235,7 +236,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
         fr.bin = (uint16_t)bin_of_degree(d[u], A.tau, A.omega, A.max_bins);
         fr.closed = found[u] ? 1 : 0;
         fr.cls = (uint8_t)cls;
-        A.feat[fslot * A.feat_stride + (s[u] - A.s_begin)] = fr;
+        A.feat[fslot * A.feat_stride + (s[u] - sbase)] = fr;
       }
     }
   }
@@ -273,14 +274,16 @@ __global__ __launch_bounds__(kSampWG) void k_sample_close(const SamplerCtx A, co
   int e = 0;
   for (int i = 1; i < (int)T.ntask; ++i)
     if (T.task[i].tile_begin <= tile) e = i;
-  const uint64_t s0 = A.s_begin + (tile - T.task[e].tile_begin) * A.spt;
-  const uint64_t s1 = min(s0 + A.spt, A.s_begin + T.task[e].k);
+  const uint64_t sbase = T.task[e].s_begin;
+  const uint64_t s0 = sbase + (tile - T.task[e].tile_begin) * A.spt;
+  const uint64_t s1 = min(s0 + A.spt, sbase + T.task[e].k);
   if (s0 >= s1) return;
   if (!header_ok(A)) {
     if (threadIdx.x == 0) atomicAdd((unsigned long long*)&A.ix.hdr->mismatch, 1ULL);
     return;
   }
-  sample_tile<U>(A, sm, T.task[e].row, T.task[e].bword, T.graph_word, s0, s1, T.task[e].slot);
+  sample_tile<U>(A, sm, T.task[e].row, T.task[e].bword, T.graph_word, s0, s1, T.task[e].slot,
+                 sbase);
 }
 
 // Persistent form: tiles of all (graph, row) pairs of a batch come from a
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(kSampWG) void k_sample_persistent(const SamplerCtx 
     if (s0 >= s1) continue;
     const uint32_t g = (uint32_t)(f / rows_per_graph);
     const uint32_t row = (uint32_t)(f % rows_per_graph);
-    sample_tile<U>(A, sm, f, row == A.max_bins ? kGlobalWord : row, g, s0, s1, f);
+    sample_tile<U>(A, sm, f, row == A.max_bins ? kGlobalWord : row, g, s0, s1, f, A.s_begin);
   }
 }
 
@@ -446,6 +449,7 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
     K.row = b;
     K.bword = glob ? kGlobalWord : b;
     K.k = k;
+    K.s_begin = 0;
     K.slot = b;
     if (T.ntask == kMaxTasks) {
       if ((rc = launch_tasks(A, T, t.U, st))) return rc;
@@ -488,7 +492,7 @@ extern "C" int wedge_sample_close_tuned(const uint64_t* d_rowptr, const uint32_t
 extern "C" int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
                                      uint64_t m, const void* d_index, uint32_t max_bins,
                                      uint32_t tau, uint64_t omega, const uint64_t* h_k,
-                                     uint64_t s_begin, uint64_t seed, uint32_t domain,
+                                     const uint64_t* h_s_begin, uint64_t seed, uint32_t domain,
                                      uint32_t graph_id, int closure, wedge_feature_rec* d_out,
                                      uint64_t out_stride, uint64_t* d_q, void* stream) {
   clear_error();
@@ -502,11 +506,12 @@ extern "C" int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d
   if (!aligned(d_rowptr, 8) || !aligned(d_index, 256) || !aligned(d_out, 16) ||
       !aligned(d_col, 4) || !aligned(d_q, 8))
     return set_error(WEDGE_EINVAL, "wedge_sample_features: misaligned pointer");
-  if (s_begin > (1ULL << 48)) return set_error(WEDGE_ERANGE, "wedge_sample_features: s_begin");
   uint64_t total = 0;
   for (uint32_t r = 0; r <= max_bins; ++r) {
     if (h_k[r] > out_stride)
       return set_error(WEDGE_ERANGE, "wedge_sample_features: k[%u] > out_stride", r);
+    if (h_s_begin && h_s_begin[r] + h_k[r] > (1ULL << 48))
+      return set_error(WEDGE_ERANGE, "wedge_sample_features: s_begin[%u] + k beyond 2^48", r);
     total += h_k[r];
   }
   if (total > 0 && (m == 0 || !d_col))
@@ -532,7 +537,7 @@ extern "C" int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d
   A.max_bins = max_bins;
   A.num_graphs = 1;
   A.domain = domain;
-  A.s_begin = s_begin;
+  A.s_begin = 0;
   A.feat = d_out;
   A.feat_stride = out_stride;
   A.omega = omega;
@@ -548,6 +553,7 @@ extern "C" int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d
     K.row = b;
     K.bword = (b == max_bins) ? kGlobalWord : b;
     K.k = h_k[b];
+    K.s_begin = h_s_begin ? h_s_begin[b] : 0;
     K.slot = slot++;
     if (T.ntask == kMaxTasks) {
       if ((rc = launch_tasks(A, T, t.U, st))) return rc;

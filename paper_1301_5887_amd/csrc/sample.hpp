@@ -25,9 +25,9 @@ struct SamplerCtx {
   uint32_t num_graphs;
   // stream selection and the feature output of the control variate
   uint64_t domain;        // Philox key word 1 (1 = plain sampling)
-  uint64_t s_begin;       // first sample index of every row of this launch
+  uint64_t s_begin;       // first sample index of every row (persistent form)
   wedge_feature_rec* feat;  // nullable: record of sample s of a task at
-  uint64_t feat_stride;     //   slot * feat_stride + (s - s_begin)
+  uint64_t feat_stride;     //   slot * feat_stride + (s - the task's s_begin)
   uint64_t omega;           // binning, for the centre's bin in a record
   uint32_t tau;
   int closure;              // 0: skip the closure search (feature-only draws)
@@ -36,7 +36,8 @@ struct SamplerCtx {
 struct Task {
   uint32_t row;    // index row (bin id, or max_bins for the global stream)
   uint32_t bword;  // Philox counter word 1: bin id, or 0xFFFFFFFF
-  uint64_t k;      // samples
+  uint64_t k;      // samples s_begin .. s_begin + k - 1
+  uint64_t s_begin;
   uint64_t tile_begin;
   uint64_t slot;   // feature-record row of this task
 };

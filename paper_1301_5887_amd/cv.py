@@ -49,15 +49,19 @@ def records_to_numpy(t: torch.Tensor) -> np.ndarray:
     return t.cpu().numpy().view(np.uint8).reshape(-1).view(FEATURE_DTYPE)
 
 
-def sample_features(g: W.Csr, bi: W.BinIndex, h_k: np.ndarray, s_begin: int, seed: int,
+def sample_features(g: W.Csr, bi: W.BinIndex, h_k: np.ndarray, s_begin, seed: int,
                     domain: int, closure: bool, out: torch.Tensor, stride: int,
                     graph_id: int = 0, stream=None):
-    """wedge_sample_features into out (int32 tensor viewed as records)."""
+    """wedge_sample_features into out (int32 tensor viewed as records);
+    s_begin is one first sample index for every row or an array of them."""
     hk = np.ascontiguousarray(h_k, dtype=np.uint64)
     assert hk.shape[0] == bi.max_bins + 1
+    sb = np.zeros(bi.max_bins + 1, dtype=np.uint64)
+    sb[:] = np.asarray(s_begin, dtype=np.uint64)
     W._check(_L().wedge_sample_features(W._ptr(g.rowptr), W._ptr(g.col), g.n, g.m,
                                         W._ptr(bi.index), bi.max_bins, bi.tau, bi.omega,
-                                        hk.ctypes.data_as(W._vp), s_begin, seed, domain, graph_id,
+                                        hk.ctypes.data_as(W._vp), sb.ctypes.data_as(W._vp),
+                                        seed, domain, graph_id,
                                         int(closure), W._ptr(out), stride, None,
                                         W._stream(stream)))
 
@@ -102,6 +106,16 @@ class Mlp:
                                      W._ptr(self.grad), W._ptr(self.loss), W._ptr(ws),
                                      ws.numel(), W._stream(stream)))
 
+    def train(self, rec: torch.Tensor, rows: int, stride: int, n_fit: int, per_row_batch: int,
+              epochs: int, lr=2e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        """wedge_mlp_train: every minibatch step queued by the library."""
+        ws = self.ws.get(int(_L().wedge_mlp_train_workspace(rows, per_row_batch)))
+        W._check(_L().wedge_mlp_train(W._ptr(self.state), W._ptr(rec), rows, stride, n_fit,
+                                      per_row_batch, epochs, self.t, lr, b1, b2, eps,
+                                      W._ptr(self.loss), W._ptr(ws), ws.numel(),
+                                      W._stream(stream)))
+        self.t += epochs * (n_fit // per_row_batch)
+
     def adam(self, lr=2e-3, b1=0.9, b2=0.999, eps=1e-8, grad: torch.Tensor | None = None,
              stream=None):
         self.t += 1
@@ -111,13 +125,18 @@ class Mlp:
 
 
 def moments(rec: torch.Tensor, gv: torch.Tensor, rows: int, stride: int, per_row: int,
-            out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+            out: torch.Tensor | None = None, counts=None, stream=None) -> torch.Tensor:
     """Integer moment sums [rows, 5] (count, sum X, 2^32 sum g, 2^32 sum g^2,
-    2^32 sum X g), accumulated into `out`."""
+    2^32 sum X g), accumulated into `out`; `counts` (per row) overrides
+    per_row."""
     if out is None:
         out = torch.zeros(rows * 5, dtype=torch.int64, device=rec.device)
-    W._check(_L().wedge_cv_moments(W._ptr(rec), W._ptr(gv), rows, stride, per_row, W._ptr(out),
-                                   W._stream(stream)))
+    cp = None
+    if counts is not None:
+        ca = np.ascontiguousarray(counts, dtype=np.uint64)
+        cp = ca.ctypes.data_as(W._vp)
+    W._check(_L().wedge_cv_moments(W._ptr(rec), W._ptr(gv), rows, stride, per_row, cp,
+                                   W._ptr(out), W._stream(stream)))
     return out
 
 
@@ -130,7 +149,7 @@ class Census:
     def __init__(self, g: W.Csr, bi: W.BinIndex, stream=None):
         dev = g.rowptr.device
         self.bi = bi
-        self.buf = W._empty_bytes(int(_L().wedge_cv_census_bytes(bi.max_bins)), dev)
+        self.buf = W._empty_bytes(int(_L().wedge_cv_census_bytes(g.n, g.m, bi.max_bins)), dev)
         W._check(_L().wedge_cv_census(W._ptr(g.rowptr), W._ptr(g.col), g.n, g.m,
                                       W._ptr(bi.index), bi.max_bins, bi.tau, bi.omega,
                                       W._ptr(self.buf), self.buf.numel(), W._stream(stream)))
@@ -246,6 +265,36 @@ def cv_row_estimate(st: RowStats, beta: float, delta_i: float, use_aux: bool,
     return est, e_eval + e_aux
 
 
+def eb_samples_needed(var: float, R: float, delta: float, eps: float,
+                      n_max: int = 1 << 40) -> int:
+    """Smallest n with an empirical-Bernstein half-width <= eps at variance
+    `var` (bisection over the closed form)."""
+    if eb_halfwidth(n_max, var, R, delta) > eps:
+        return n_max
+    lo, hi = 2, 2
+    while eb_halfwidth(hi, var, R, delta) > eps:
+        lo, hi = hi, hi * 2
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if eb_halfwidth(mid, var, R, delta) <= eps:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def row_variances(m, beta: float):
+    """(Var X, Var(X - beta g)) from integer moments [n, sx, sg, sg2, sxg]."""
+    n, sx, sg, sg2, sxg = (int(v) for v in m)
+    if n < 2:
+        return 0.25, 0.25
+    mx, mg = sx / n, sg / Q32 / n
+    vx = (sx - n * mx * mx) / (n - 1)
+    vg = (sg2 / Q32 - n * mg * mg) / (n - 1)
+    cxg = (sxg / Q32 - n * mx * mg) / (n - 1)
+    return vx, max(vx - 2 * beta * cxg + beta * beta * vg, 0.0)
+
+
 @dataclass
 class SequentialResult:
     estimates: dict = field(default_factory=dict)     # row -> estimate
@@ -264,46 +313,60 @@ class SequentialResult:
         return int(sum(self.aux_samples.values()))
 
 
+def _moments_per_row(recs, gv, counts, stride, dev):
+    """Moments of the first counts[j] records of every row j."""
+    A = len(counts)
+    mom = moments(recs, gv, A, stride, 0, counts=counts)
+    return W.to_host_u64(mom).view(np.int64).reshape(A, 5)
+
+
 def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: float, seed: int,
                net: Mlp | None, beta: dict | None, n0: int = 1 << 14,
                max_per_row: int = 1 << 26, exact_means: dict | None = None,
+               first: dict | None = None, growth: float = 2.0,
                stream=None) -> SequentialResult:
-    """EVAL (and, with a network and no exact means, AUX) blocks of
-    doubling size until every row's half-width at delta_i = delta / (i (i+1))
-    is <= eps."""
+    """EVAL (and, with a network and no exact means, AUX) draws in rounds:
+    row r's running total after round i is first[r] * growth^(i-1) (n0 for
+    every row without a plan), until every row's half-width at
+    delta_i = delta / (i (i+1)) is <= eps.  The plan must not depend on the
+    EVAL draws (a pilot from TRAIN draws, or a constant)."""
     dev = g.rowptr.device
     B = bi.max_bins
     rows = sorted(rows)
     t0 = time.perf_counter()
     res = SequentialResult()
     stats = {r: RowStats() for r in rows}
+    done = {r: 0 for r in rows}
     active = list(rows)
-    done_at = 0
     i = 0
     while active:
         i += 1
-        n_target = min(n0 << (i - 1), max_per_row)
-        blk = n_target - done_at
-        if blk <= 0:
-            break
         hk = np.zeros(B + 1, dtype=np.uint64)
+        sb = np.zeros(B + 1, dtype=np.uint64)
+        incs = []
         for r in active:
-            hk[r] = blk
+            base = first.get(r, n0) if first else n0
+            target = min(int(math.ceil(base * growth ** (i - 1))), max_per_row)
+            inc = max(target - done[r], 0)
+            hk[r], sb[r] = inc, done[r]
+            incs.append(inc)
+        if max(incs) == 0:
+            break
         A = len(active)   # records are compact: row j is active[j]
-        recs = new_records(A, blk, dev)
-        sample_features(g, bi, hk, done_at, seed, DOMAIN_EVAL, True, recs, blk, stream=stream)
-        gv = torch.zeros(A * blk, dtype=torch.float32, device=dev)
+        stride = max(incs)
+        recs = new_records(A, stride, dev)
+        sample_features(g, bi, hk, sb, seed, DOMAIN_EVAL, True, recs, stride, stream=stream)
+        gv = torch.zeros(A * stride, dtype=torch.float32, device=dev)
         if net is not None:
-            net.forward(recs, A * blk, gv, stream=stream)
-        m = W.to_host_u64(moments(recs, gv, A, blk, blk)).view(np.int64).reshape(A, 5)
+            net.forward(recs, A * stride, gv, stream=stream)
+        m = _moments_per_row(recs, gv, incs, stride, dev)
         am = None
         if net is not None and exact_means is None:
-            arecs = new_records(A, blk, dev)
-            sample_features(g, bi, hk, done_at, seed, DOMAIN_AUX, False, arecs, blk,
-                            stream=stream)
-            agv = torch.zeros(A * blk, dtype=torch.float32, device=dev)
-            net.forward(arecs, A * blk, agv, stream=stream)
-            am = W.to_host_u64(moments(arecs, agv, A, blk, blk)).view(np.int64).reshape(A, 5)
+            arecs = new_records(A, stride, dev)
+            sample_features(g, bi, hk, sb, seed, DOMAIN_AUX, False, arecs, stride, stream=stream)
+            agv = torch.zeros(A * stride, dtype=torch.float32, device=dev)
+            net.forward(arecs, A * stride, agv, stream=stream)
+            am = _moments_per_row(arecs, agv, incs, stride, dev)
         delta_i = delta / (i * (i + 1))
         still = []
         for j, r in enumerate(active):
@@ -312,16 +375,16 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             st.sg2 += int(m[j, 3]); st.sxg += int(m[j, 4])
             if am is not None:
                 st.an += int(am[j, 0]); st.ag += int(am[j, 2]); st.ag2 += int(am[j, 3])
+            done[r] += incs[j]
             b = beta.get(r, 0.0) if beta else 0.0
             em = exact_means.get(r) if (exact_means is not None and net is not None) else None
             est, hw = cv_row_estimate(st, b, delta_i, use_aux=net is not None, exact_mean=em)
             res.estimates[r], res.halfwidth[r] = est, hw
             res.eval_samples[r] = st.n
             res.aux_samples[r] = st.an
-            if hw > eps and n_target < max_per_row:
+            if hw > eps and done[r] < max_per_row:
                 still.append(r)
         active = still
-        done_at = n_target
         res.rounds = i
     torch.cuda.synchronize()
     res.seconds = time.perf_counter() - t0
@@ -345,6 +408,7 @@ class TrainResult:
     train_samples: int
     seconds: float
     rho2: dict = field(default_factory=dict)
+    holdout: dict = field(default_factory=dict)   # row -> moments of the held-out draws
 
 
 def train(g: W.Csr, bi: W.BinIndex, rows: list[int], n_train: int, seed: int,
@@ -367,11 +431,8 @@ def train(g: W.Csr, bi: W.BinIndex, rows: list[int], n_train: int, seed: int,
     net.init(init_seed, stream=stream)
     losses = []
     R = len(rows)   # records are compact: row j of `recs` is rows[j]
-    for ep in range(epochs):
-        for j0 in range(0, n_fit, per_row_batch):
-            net.grad_of(recs, R, per_row, j0, per_row_batch, stream=stream)
-            net.adam(lr=lr, stream=stream)
-        losses.append(float(net.loss.item()))
+    net.train(recs, R, per_row, n_fit, per_row_batch, epochs, lr=lr, stream=stream)
+    losses.append(float(net.loss.item()))
     # beta from the held-out draws (columns n_fit .. per_row of every row)
     gv = torch.zeros(R * per_row, dtype=torch.float32, device=dev)
     net.forward(recs, R * per_row, gv, stream=stream)
@@ -381,57 +442,82 @@ def train(g: W.Csr, bi: W.BinIndex, rows: list[int], n_train: int, seed: int,
     rho2 = {r: rho2_from_moments(mom[i]) for i, r in enumerate(rows)}
     torch.cuda.synchronize()
     return TrainResult(net=net, beta=beta, losses=losses, train_samples=per_row * R,
-                       seconds=time.perf_counter() - t0, rho2=rho2)
+                       seconds=time.perf_counter() - t0, rho2=rho2,
+                       holdout={r: mom[i].copy() for i, r in enumerate(rows)})
+
+
+def plans(tr: TrainResult, eps: float, delta: float):
+    """First-round sample counts per row from the held-out TRAIN draws: the
+    empirical-Bernstein n at delta / 2 (the first round's share) for plain
+    sampling (variance of X, range 1) and for the control variate (variance
+    of X - beta g, range 1 + |beta|).  They use no EVAL draw."""
+    plain, cv = {}, {}
+    for r, m in tr.holdout.items():
+        vx, vz = row_variances(m, tr.beta[r])
+        plain[r] = eb_samples_needed(vx, 1.0, delta / 2, eps)
+        cv[r] = eb_samples_needed(vz, 1.0 + abs(tr.beta[r]), delta / 2, eps)
+    return plain, cv
 
 
 def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, seed: int = 11,
-            n_train: int = 10_000_000, epochs: int = 2, per_row_batch: int = 1024,
-            lr: float = 2e-3, n0: int = 1 << 16) -> dict:
+            n_train: int = 10_000_000, epochs: int = 2, per_row_batch: int = 4096,
+            lr: float = 4e-3, growth: float = 1.1, aux_form: bool = True) -> dict:
     """Samples and wall time to reach a half-width <= eps at confidence
     1 - delta on every sampled bin and on the global stream, for plain
     sampling with the empirical-Bernstein stopping rule and for the learned
-    control variate with the same rule.  TRAIN draws count as closure
-    checks of the control-variate form; AUX draws (no closure test) are
-    reported separately."""
+    control variate with the same rule.  Both follow round plans from the
+    held-out TRAIN draws (first round at the predicted n, then growing by
+    `growth`).  TRAIN draws count as closure checks of the control-variate
+    form; AUX draws (no closure test) are reported separately."""
     B = bi.max_bins
     rows = [r for r in range(B) if bi.h_p_b[r] > 0] + [B]
     torch.cuda.synchronize()
-    pe = sequential(g, bi, rows, eps, delta, seed, None, None, n0=n0)
     tr = train(g, bi, rows, n_train, seed, epochs=epochs, per_row_batch=per_row_batch, lr=lr)
-    cvr = sequential(g, bi, rows, eps, delta, seed, tr.net, tr.beta, n0=n0)
+    plan_plain, plan_cv = plans(tr, eps, delta)
+    pe = sequential(g, bi, rows, eps, delta, seed, None, None, first=plan_plain, growth=growth)
     t0 = time.perf_counter()
     census = Census(g, bi)
     means = census.means(tr.net)
     torch.cuda.synchronize()
     t_census = time.perf_counter() - t0
-    cvx = sequential(g, bi, rows, eps, delta, seed, tr.net, tr.beta, n0=n0, exact_means=means)
+    cvx = sequential(g, bi, rows, eps, delta, seed, tr.net, tr.beta, first=plan_cv,
+                     growth=growth, exact_means=means)
+    cvr = None
+    if aux_form:
+        cvr = sequential(g, bi, rows, eps, delta, seed, tr.net, tr.beta, first=plan_cv,
+                         growth=growth)
     per_row = {}
     for r in rows:
         name = "global" if r == B else str(r)
-        per_row[name] = {"beta": round(tr.beta[r], 5), "rho2": round(tr.rho2[r], 5),
-                         "plain_eb_samples": pe.eval_samples[r],
-                         "cv_eval_samples": cvr.eval_samples[r],
-                         "cv_aux_samples": cvr.aux_samples[r],
-                         "cv_exact_eval_samples": cvx.eval_samples[r],
-                         "exact_mean_g": means.get(r),
-                         "plain_eb_estimate": pe.estimates[r], "cv_estimate": cvr.estimates[r],
-                         "cv_exact_estimate": cvx.estimates[r],
-                         "plain_eb_halfwidth": pe.halfwidth[r], "cv_halfwidth": cvr.halfwidth[r],
-                         "cv_exact_halfwidth": cvx.halfwidth[r]}
-    cv_checks = cvr.total_eval + tr.train_samples
-    return {
-        "eps": eps, "delta": delta, "rows": len(rows),
+        row = {"beta": round(tr.beta[r], 5), "rho2": round(tr.rho2[r], 5),
+               "plan_plain": plan_plain[r], "plan_cv": plan_cv[r],
+               "plain_eb_samples": pe.eval_samples[r],
+               "cv_exact_eval_samples": cvx.eval_samples[r],
+               "exact_mean_g": means.get(r),
+               "plain_eb_estimate": pe.estimates[r], "cv_exact_estimate": cvx.estimates[r],
+               "plain_eb_halfwidth": pe.halfwidth[r], "cv_exact_halfwidth": cvx.halfwidth[r]}
+        if cvr is not None:
+            row.update({"cv_aux_eval_samples": cvr.eval_samples[r],
+                        "cv_aux_samples": cvr.aux_samples[r], "cv_aux_estimate": cvr.estimates[r],
+                        "cv_aux_halfwidth": cvr.halfwidth[r]})
+        per_row[name] = row
+    out = {
+        "eps": eps, "delta": delta, "rows": len(rows), "growth": growth,
+        "train": {"closure_checks": tr.train_samples, "seconds": tr.seconds,
+                  "final_loss": tr.losses[-1], "epochs": epochs,
+                  "minibatch": per_row_batch * len(rows)},
         "plain_eb": {"closure_checks": pe.total_eval, "seconds": pe.seconds, "rounds": pe.rounds},
-        "learned_cv": {"closure_checks": cv_checks, "eval_checks": cvr.total_eval,
-                       "train_checks": tr.train_samples, "aux_draws": cvr.total_aux,
-                       "seconds": cvr.seconds + tr.seconds, "train_seconds": tr.seconds,
-                       "rounds": cvr.rounds, "final_train_loss": tr.losses[-1]},
         "learned_cv_exact_mean": {"closure_checks": cvx.total_eval + tr.train_samples,
                                   "eval_checks": cvx.total_eval,
                                   "train_checks": tr.train_samples,
                                   "seconds": cvx.seconds + tr.seconds + t_census,
-                                  "census_seconds": t_census, "rounds": cvx.rounds},
-        "network_gain_eval_checks": pe.total_eval / max(cvr.total_eval, 1),
-        "network_gain_eval_checks_exact_mean": pe.total_eval / max(cvx.total_eval, 1),
+                                  "eval_seconds": cvx.seconds, "census_seconds": t_census,
+                                  "train_seconds": tr.seconds, "rounds": cvx.rounds},
+        "network_gain_eval_checks": pe.total_eval / max(cvx.total_eval, 1),
         "per_row": per_row,
     }
+    if cvr is not None:
+        out["learned_cv_aux"] = {"closure_checks": cvr.total_eval + tr.train_samples,
+                                 "eval_checks": cvr.total_eval, "aux_draws": cvr.total_aux,
+                                 "seconds": cvr.seconds + tr.seconds, "rounds": cvr.rounds}
+    return out

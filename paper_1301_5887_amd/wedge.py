@@ -99,7 +99,7 @@ SIGNATURES = {
                                             ctypes.c_size_t, ctypes.POINTER(ctypes.c_float),
                                             ctypes.POINTER(ctypes.c_int), _vp]),
     "wedge_sample_features": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _c_u32,
-                                             _c_u64, _vp, _c_u64, _c_u64, _c_u32, _c_u32,
+                                             _c_u64, _vp, _vp, _c_u64, _c_u32, _c_u32,
                                              ctypes.c_int, _vp, _c_u64, _vp, _vp]),
     "wedge_mlp_state_bytes": (ctypes.c_size_t, []),
     "wedge_mlp_set": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -111,10 +111,14 @@ SIGNATURES = {
                                       ctypes.c_size_t, _vp]),
     "wedge_mlp_adam": (ctypes.c_int, [_vp, _vp, _c_u32, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, _vp]),
-    "wedge_cv_moments": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _c_u64, _vp, _vp]),
+    "wedge_mlp_train_workspace": (ctypes.c_size_t, [_c_u32, _c_u64]),
+    "wedge_mlp_train": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _c_u64, _c_u64, _c_u32, _c_u32,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, _vp, _vp, ctypes.c_size_t, _vp]),
+    "wedge_cv_moments": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _c_u64, _vp, _vp, _vp]),
     "wedge_eb_halfwidth": (ctypes.c_double, [_c_u64, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double]),
-    "wedge_cv_census_bytes": (ctypes.c_size_t, [_c_u32]),
+    "wedge_cv_census_bytes": (ctypes.c_size_t, [_c_u32, _c_u64, _c_u32]),
     "wedge_cv_census": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _c_u32, _c_u64,
                                        _vp, ctypes.c_size_t, _vp]),
     "wedge_cv_census_keys": (ctypes.c_int, [_vp, _c_u32, ctypes.POINTER(_c_u32), _vp, _vp,

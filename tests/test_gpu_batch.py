@@ -143,3 +143,52 @@ def test_batch_graph500_recipe_reduced_scales():
     ref = oracle_batch(graphs, tau, omega, B, k, k, seed, delta)
     check_batch(h, ref, B)
     bt.destroy_graph()
+
+
+def test_batch_full_recipe_sampled_oracle():
+    """The batched workload at its full size: 512 R-MAT graphs (Graph500
+    parameters, scales 10..20 and edge factors 8..32 drawn from the batch seed,
+    seeds 100..611), 20,000 samples per bin and per global stream, the launch
+    shape picked by the autotuner, the whole pipeline captured into one HIP
+    graph and replayed; every 16th graph (and the largest) is compared
+    bit-exact with the oracle run on that graph alone."""
+    import time
+    shapes = gen.batch_shapes(512, seed=100)
+    graphs = []
+    for g, (s, ef) in enumerate(shapes):
+        n, src, dst = gen.rmat_graph500(s, ef, seed=100 + g)
+        graphs.append((n, src, dst))
+    m_tot = sum(len(x[1]) for x in graphs)
+    tau, omega, B, k, seed, delta = 2, 2, 24, 20_000, 5, 1e-3
+    print(f"[batch-full] G=512 edges={m_tot} B={B} k={k}", flush=True)
+    bt = W.Batch(graphs, tau=tau, omega=omega, max_bins=B, k_per_bin=k, k_global=k, seed=seed)
+    bt.prepare()
+    cands = [W.make_shape(4, 4096, 0), W.make_shape(2, 2048, 0), W.make_shape(8, 8192, 0),
+             W.make_shape(4, 16384, 2048), W.make_shape(4, 4096, 1024)]
+    best, ms = bt.autotune(cands, reps=2)
+    print(f"[batch-full] autotune ms={['%.3f' % t for t in ms]} best={best.lanes_in_flight},"
+          f"{best.samples_per_tile},{best.workgroups}", flush=True)
+    bt.capture(best, delta=delta)
+    bt.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.replay()
+    torch.cuda.synchronize()
+    print(f"[batch-full] one replay of the whole pipeline: {time.perf_counter() - t0:.4f} s",
+          flush=True)
+    h = bt.host()
+    largest = int(np.argmax([len(x[1]) for x in graphs]))
+    pick = sorted(set(range(0, 512, 16)) | {largest})
+    for g in pick:
+        n, src, dst = graphs[g]
+        og = O.build_graph(src, dst, n)
+        n_b, p_b = O.bins(og, tau, omega, B)
+        kb = O.k_for_bins(p_b, k)
+        kgg = k if int(p_b.sum()) > 0 else 0
+        s = O.sample(og, tau, omega, B, kb, kgg, seed, graph_id=g)
+        per_bin, glob = O.estimate(p_b, s.q, kb, kgg, delta)
+        assert (h["n_b"][g] == n_b).all() and (h["p_b"][g] == p_b).all(), g
+        assert (h["q"][g] == s.q).all(), g
+        for j in range(6):
+            assert abs(h["est_glob"][g][j] - glob[j]) <= REL * max(1.0, abs(glob[j])), (g, j)
+    bt.destroy_graph()

@@ -59,6 +59,35 @@ def test_feature_stream_matches_oracle(c1):
                 assert (r["closed"][j] == 0).all()
 
 
+def test_feature_stream_per_row_starts(c1):
+    """Rows drawn from different sample indices and in different numbers in
+    one launch: each row matches the oracle's stream at its own start."""
+    g, bi, og = c1
+    B = bi.max_bins
+    rows = [r for r in range(B) if bi.h_p_b[r] > 0] + [B]
+    hk = np.zeros(B + 1, dtype=np.uint64)
+    sb = np.zeros(B + 1, dtype=np.uint64)
+    for j, r in enumerate(rows):
+        hk[r] = 500 + 97 * j
+        sb[r] = 1000 + 4099 * j
+    stride = int(hk.max())
+    print(f"[cv] per-row starts rows={len(rows)} stride={stride}", flush=True)
+    recs = C.new_records(len(rows), stride)
+    C.sample_features(g, bi, hk, sb, 5, C.DOMAIN_EVAL, True, recs, stride)
+    torch.cuda.synchronize()
+    r = C.records_to_numpy(recs).reshape(len(rows), stride)
+    deg = og.degrees().astype(np.int64)
+    for j, row in enumerate(rows):
+        k1 = np.zeros(B + 1, dtype=np.uint64)
+        k1[row] = hk[row]
+        s = O.sample(og, 2, 2, B, k1[:B], int(k1[B]), 5, dump_per_bin=int(hk[row]),
+                     domain=C.DOMAIN_EVAL, s_begin=int(sb[row]))
+        k = int(hk[row])
+        assert (r["dv"][j][:k] == deg[s.v[row]]).all()
+        assert (r["closed"][j][:k] == (s.cls[row] > 0)).all()
+        assert (r["cls"][j][:k] == s.cls[row]).all()
+
+
 def make_records(n, seed):
     rng = np.random.default_rng(seed)
     rec = np.zeros(n, dtype=C.FEATURE_DTYPE)
@@ -135,6 +164,24 @@ def test_minibatch_view_selects_rows():
     assert np.allclose(g1, g2, rtol=1e-5, atol=1e-9)
 
 
+def test_train_loop_equals_step_by_step_calls():
+    """wedge_mlp_train queues exactly the grad + Adam steps a caller would."""
+    rows, per_row, batch = 3, 2048, 256
+    rec = make_records(rows * per_row, 31)
+    x = upload_records(rec)
+    theta = M.init_params(5)
+    a, b = net_with(theta), net_with(theta)
+    a.train(x, rows, per_row, 1536, batch, 2, lr=3e-3)
+    for ep in range(2):
+        for j0 in range(0, 1536, batch):
+            b.grad_of(x, rows, per_row, j0, batch)
+            b.adam(lr=3e-3)
+    torch.cuda.synchronize()
+    assert a.t == b.t == 12
+    assert torch.equal(a.get(), b.get())
+    assert torch.equal(a.loss, b.loss)
+
+
 def test_adam_step_matches_oracle():
     theta = M.init_params(8)
     net = net_with(theta)
@@ -166,6 +213,17 @@ def test_moments_are_exact_integers():
     g2q = np.rint(gv * gv * 2.0 ** 32).astype(np.int64)
     ref = np.stack([np.full(5, 997), X.sum(1), gq.sum(1), g2q.sum(1), (X * gq).sum(1)], 1)
     assert (got == ref).all()
+    # a count per row, as the sequential rounds use
+    cnt = [1000, 0, 17, 640, 999]
+    mom = C.moments(d, g, 5, 1000, 0, counts=cnt)
+    got = W.to_host_u64(mom).view(np.int64).reshape(5, 5)
+    gv = g.cpu().numpy().astype(np.float64).reshape(5, 1000)
+    X = rec["closed"].reshape(5, 1000).astype(np.int64)
+    for r, c in enumerate(cnt):
+        gq = np.rint(gv[r, :c] * 2.0 ** 32).astype(np.int64)
+        g2q = np.rint(gv[r, :c] * gv[r, :c] * 2.0 ** 32).astype(np.int64)
+        ref = [c, X[r, :c].sum(), gq.sum(), g2q.sum(), (X[r, :c] * gq).sum()]
+        assert list(got[r]) == ref, r
 
 
 def test_constant_network_equals_plain(c1):
@@ -218,9 +276,23 @@ def small_graphs():
         rng.integers(0, 300, 3000).astype(np.uint32)
     n, src, dst = gen.chung_lu_c1(1)
     yield "chung_lu", n, src, dst
+    # every census mode: hubs above 2048 neighbours, medium centres, and a
+    # low-degree background
+    rng = np.random.default_rng(13)
+    n = 6000
+    s = [rng.integers(0, n, 12000)]
+    d = [rng.integers(0, n, 12000)]
+    for h, k in [(0, 3500), (1, 2600), (2, 2100)]:
+        s.append(np.full(k, h))
+        d.append(rng.choice(n, k, replace=False))
+    for h in range(10, 40):
+        k = int(rng.integers(40, 1500))
+        s.append(np.full(k, h))
+        d.append(rng.choice(n, k, replace=False))
+    yield "hubs", n, np.concatenate(s).astype(np.uint32), np.concatenate(d).astype(np.uint32)
 
 
-@pytest.mark.parametrize("case", ["worked_example", "random", "chung_lu"])
+@pytest.mark.parametrize("case", ["worked_example", "random", "chung_lu", "hubs"])
 def test_census_matches_oracle(case):
     name, n, src, dst = next(c for c in small_graphs() if c[0] == case)
     print(f"[cv] census {name}", flush=True)
@@ -308,3 +380,25 @@ def test_exact_mean_cv_unbiased_and_tighter(c1):
         assert abs(e.mean() - c_true) <= 3.5 * se + 1e-9, (r, e.mean(), c_true, se)
         worse += e.std(ddof=1) > np.std(pl[r], ddof=1)
     assert worse <= len(rows) // 2
+
+
+def test_compare_reaches_the_interval(c1):
+    """The estimator comparison end to end on the small graph: every row of
+    plain-EB and of the exact-mean control variate stops with a half-width
+    <= eps, and each estimate lies within a few eps of the exact c_b."""
+    g, bi, og = c1
+    B = bi.max_bins
+    P = O.exact(og, 2, 2, B)
+    eps = 0.01
+    print("[cv] compare on the Chung-Lu graph, eps=0.01", flush=True)
+    res = C.compare(g, bi, eps=eps, delta=1e-3, seed=17, n_train=200_000, epochs=2,
+                    per_row_batch=512, lr=3e-3, aux_form=False)
+    wedges = P.sum(axis=1)
+    closed = P[:, 1:].sum(axis=1)
+    c_glob = float(closed.sum()) / float(wedges.sum())
+    for name, row in res["per_row"].items():
+        c_true = c_glob if name == "global" else float(closed[int(name)]) / float(wedges[int(name)])
+        assert row["plain_eb_halfwidth"] <= eps and row["cv_exact_halfwidth"] <= eps, name
+        assert abs(row["plain_eb_estimate"] - c_true) <= 3 * eps, name
+        assert abs(row["cv_exact_estimate"] - c_true) <= 3 * eps, name
+    assert res["learned_cv_exact_mean"]["train_checks"] > 0

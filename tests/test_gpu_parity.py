@@ -209,3 +209,20 @@ def test_deterministic_repeat():
     b = run_both(src, dst, n, B=30, k=40_000, seed=1, dpb=0)
     assert (a["q"] == b["q"]).all()
     assert W.to_host_u64(a["so"].probe_loads)[0] == W.to_host_u64(b["so"].probe_loads)[0]
+
+
+def test_csr_many_tiles_ragged_tail():
+    """The CSR build over about a thousand sort tiles with a ragged last tile
+    (and a batch-free edge list with repeats, self-loops and bad ids)."""
+    scale, m_in = 18, 16 * (1 << 18) + 12_345
+    src, dst = gen.rmat(scale, m_in, 23)
+    n = 1 << scale
+    src[:100] = dst[:100]                 # self-loops
+    src[100:110] = n + 5                  # ids out of range
+    print(f"[parity] csr scale={scale} m_in={m_in}", flush=True)
+    g = W.build_csr(dev(src), dev(dst), n)
+    torch.cuda.synchronize()
+    og = O.build_graph(src, dst, n)
+    assert g.m == og.m and g.rejected == og.rejected == 10
+    assert (W.to_host_u64(g.rowptr) == og.rowptr).all()
+    assert (g.col[: 2 * g.m].cpu().numpy().view(np.uint32) == og.col).all()
