@@ -31,9 +31,13 @@ sys.path.insert(0, ROOT)
 METRIC = "closure checks/s + s per M edges at fixed CI; learned-CV vs plain samples"
 PEAK_HBM_GBS = 8000.0
 # bytes the sampler must read per sample besides its search: the centre's
-# adjacency start (8), the two neighbour ids (8), rowptr of both endpoints
-# and their successors (32); plus 4 bytes per adjacency word the search reads.
-BYTES_PER_SAMPLE = 48
+# adjacency start (8), the two neighbour ids (8), the degree codes of both
+# endpoints (2), the row bounds of the endpoint whose row is searched (16);
+# the other endpoint's row bounds (16) only for a closed sample of a bin
+# (its class needs both degrees); plus 4 bytes per adjacency word the search
+# reads (counted by the kernel).
+BYTES_PER_SAMPLE = 34
+BYTES_PER_CLOSED_BIN_SAMPLE = 16
 BYTES_PER_PROBE = 4
 PMC_FILE = os.path.join(ROOT, "profiles", "sample_close_rmat_s24_counters.json")
 SAMPLER_SRC = os.path.join(ROOT, "paper_1301_5887_amd", "csrc", "sample.hip")
@@ -69,7 +73,16 @@ def main():
     ap.add_argument("--cv-train", type=int, default=10_000_000)
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="after timing, run one device copy of this size (counter calibration)")
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the sampler's HBM traffic from two rocprofv3 --pmc runs of "
+                         "this bench (FETCH_SIZE, WRITE_SIZE, each with --calibrate-copy-gib)")
+    ap.add_argument("--pmc-k", type=int, default=0, help="closure checks of the profiled run")
+    ap.add_argument("--pmc-copy-gib", type=float, default=1.0)
     args = ap.parse_args()
+    if args.pmc_summarize:
+        pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], args.pmc_k,
+                      args.pmc_copy_gib)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -163,7 +176,10 @@ def main():
     avg = {kx: float(np.mean(vx)) for kx, vx in phase.items()}
 
     # roofline of the sampler (dominant kernel of the hot path)
-    alg_bytes = BYTES_PER_SAMPLE * K + BYTES_PER_PROBE * probes
+    qh = h_q.numpy().view(np.uint64).reshape(B + 1, 4)
+    closed_bins = int(qh[:B, 1:].sum())
+    alg_bytes = (BYTES_PER_SAMPLE * K + BYTES_PER_CLOSED_BIN_SAMPLE * closed_bins +
+                 BYTES_PER_PROBE * probes)
     achieved = alg_bytes / (avg["sample_close"] / 1000.0) / 1e9
     traffic = None
     if os.path.exists(PMC_FILE):
@@ -174,7 +190,8 @@ def main():
     roofline = {"kernel": "k_sample_close", "bound": "hbm", "achieved": round(achieved, 2),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 5),
                 "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
-                "probe_loads": probes}
+                "probe_loads": probes, "closed_bin_samples": closed_bins,
+                "amplification": (round(traffic / alg_bytes, 2) if traffic else None)}
 
     if args.calibrate_copy_gib > 0:
         nbytes = int(args.calibrate_copy_gib * (1 << 30))
@@ -236,6 +253,42 @@ def main():
                       "t_global": est.glob["t_global"], "eps": est.glob["eps_global"]},
         "paper_context": "Hadoop, 32 nodes: 225 s + 0.33 s per million edges",
     }
+    print(json.dumps(out))
+
+
+def _pmc_rows(d: str, counter: str):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "*counter_collection.csv")):
+        with open(f) as fh:
+            rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+    return rows
+
+
+def pmc_summarize(fetch_dir: str, write_dir: str, workload_k: int, copy_gib: float):
+    """Per-launch HBM bytes of the sampler from FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch), each scaled by the ratio of the known size of the
+    calibration copy to what the same counter read for it."""
+    copy_kib = copy_gib * (1 << 20)
+    out = {"sampler_hash": sampler_hash(), "workload_K": workload_k}
+    total = 0.0
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _pmc_rows(d, name)
+        samp = [float(r["Counter_Value"]) for r in rows if "k_sample_close" in r["Kernel_Name"]]
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not samp or not copies:
+            raise SystemExit(f"no sampler or calibration copy dispatch under {d}")
+        cal = max(copies)
+        factor = copy_kib / cal
+        per_launch = sum(samp) / len(samp) * factor * 1024.0
+        out[name.lower()] = {"kib_per_dispatch": sum(samp) / len(samp), "dispatches": len(samp),
+                             "copy_kib_read": cal, "scale": factor,
+                             "bytes_per_launch": per_launch}
+        total += per_launch
+    out["hbm_bytes_per_launch"] = total
+    with open(PMC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
     print(json.dumps(out))
 
 

@@ -49,6 +49,8 @@ static size_t index_layout(uint64_t n_total, uint64_t m_total, uint32_t G, uint3
   off += round_up(cap * 4, 256);
   if (v) v->cls_cumw = (uint64_t*)(c + off);
   off += round_up(cap * 8, 256);
+  if (v) v->vcode = (uint8_t*)(c + off);
+  off += round_up((size_t)n_total, 256);
   return off;
 }
 
@@ -79,13 +81,25 @@ __device__ inline uint32_t bin_of(uint64_t d, uint32_t tau, uint64_t omega, uint
   return b;
 }
 
+// Degree code floor(8 L(d)), L Mitchell's piecewise-linear log2 (0 for
+// d = 0): monotone in d, so comparing codes picks the shorter of two rows
+// whenever the codes differ.
+__device__ inline uint8_t degree_code(uint64_t d) {
+  if (d == 0) return 0;
+  const uint32_t e = 63 - (uint32_t)__builtin_clzll(d);
+  const uint32_t k = 8 * e + (uint32_t)(((d - (1ULL << e)) * 8) >> e);
+  return (uint8_t)(k < 255 ? k : 255);
+}
+
 __global__ void k_deg_keys(const uint64_t* __restrict__ rowptr, uint32_t n,
                            const uint32_t* __restrict__ voff, uint32_t G, int gshift,
-                           uint64_t dmask, uint64_t* __restrict__ keys) {
+                           uint64_t dmask, uint64_t* __restrict__ keys,
+                           uint8_t* __restrict__ vcode) {
   uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; v < n; v += stride) {
     uint64_t d = rowptr[v + 1] - rowptr[v];
+    vcode[v] = degree_code(d);
     if (d > dmask) d = dmask;
     uint64_t key = (d << 32) | v;
     if (G > 1) key |= (uint64_t)graph_of(voff, G, (uint32_t)v) << gshift;
@@ -286,7 +300,7 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
     uint64_t blocks = ceil_div(n, 256);
     if (blocks > 65536) blocks = 65536;
     k_deg_keys<<<(unsigned)blocks, 256, 0, st>>>(d_rowptr, (uint32_t)n, d_voff, G, gshift, dmask,
-                                                 w.keys_a);
+                                                 w.keys_a, ix.vcode);
     WEDGE_LAUNCH_CHECK("k_deg_keys");
   }
   // sort by the degree digits, then by the graph digits; ids stay ascending

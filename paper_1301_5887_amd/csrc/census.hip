@@ -32,7 +32,7 @@ constexpr uint32_t kLdsBuckets = 160;  // degrees below 2^20
 constexpr uint32_t kLdsPairs = kLdsBuckets * (kLdsBuckets + 1) / 2;  // 12880
 constexpr uint32_t kCensusWG = 512;
 constexpr uint32_t kCensusWaves = kCensusWG / 64;
-constexpr uint32_t kLaneMaxDeg = 32;    // a lane per centre up to this degree
+constexpr uint32_t kLaneMaxDeg = 64;    // a lane per centre up to this degree
 constexpr uint32_t kWaveMaxDeg = 2048;  // a wave per centre up to this degree
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kCensusWG) void k_census(const uint64_t* __restrict
   __shared__ uint32_t s_hist[kCensusWaves][kBuckets];           // 8 KB
   __shared__ uint16_t s_list[kCensusWaves][kBuckets];           // 4 KB
   __shared__ uint32_t s_cnt[kCensusWaves][kBuckets];            // 8 KB
-  __shared__ uint8_t s_lane[kLaneMaxDeg][kCensusWG];            // 16 KB
+  __shared__ uint8_t s_lane[kLaneMaxDeg][kCensusWG];            // 32 KB
   __shared__ uint64_t s_seg[3];
   __shared__ uint32_t s_wsum[kCensusWaves];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -309,7 +309,18 @@ __global__ __launch_bounds__(kCensusWG) void k_census(const uint64_t* __restrict
         const uint64_t r0 = ix.vrow[pos];
         const uint32_t v = ix.vlist[pos];
         const uint32_t d = (uint32_t)(rowptr[v + 1] - r0);
-        for (uint32_t x = 0; x < d; ++x) s_lane[x][tid] = C.vbucket[col[r0 + x]];
+        // neighbour buckets, eight independent gathers at a time
+        for (uint32_t x0 = 0; x0 < d; x0 += 8) {
+          uint32_t nb[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) nb[q] = x0 + q < d ? col[r0 + x0 + q] : 0;
+          uint8_t bk[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) bk[q] = x0 + q < d ? C.vbucket[nb[q]] : 0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (x0 + q < d) s_lane[x0 + q][tid] = bk[q];
+        }
         for (uint32_t x = 1; x < d; ++x) {
           const uint32_t bx = s_lane[x][tid];
           for (uint32_t y = 0; y < x; ++y) add_pair(s_tab, gtab, s_lane[y][tid], bx, 1);
@@ -321,8 +332,18 @@ __global__ __launch_bounds__(kCensusWG) void k_census(const uint64_t* __restrict
         const uint64_t r0 = ix.vrow[pos];
         const uint32_t v = ix.vlist[pos];
         const uint64_t r1 = rowptr[v + 1];
-        for (uint64_t x = r0 + lane; x < r1; x += 64)
-          atomicAdd(&s_hist[wave][C.vbucket[col[x]]], 1u);
+        // four independent gathers per lane at a time
+        for (uint64_t x0 = r0 + lane; x0 < r1; x0 += 4 * 64) {
+          uint32_t nb[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) nb[q] = x0 + 64 * q < r1 ? col[x0 + 64 * q] : 0;
+          uint32_t bk[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bk[q] = x0 + 64 * q < r1 ? C.vbucket[nb[q]] : 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (x0 + 64 * q < r1) atomicAdd(&s_hist[wave][bk[q]], 1u);
+        }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_s_waitcnt(0);
         // compact the non-empty buckets in increasing order
@@ -358,17 +379,28 @@ __global__ __launch_bounds__(kCensusWG) void k_census(const uint64_t* __restrict
         __builtin_amdgcn_wave_barrier();
       }
     } else {
-      // the whole workgroup per centre (hubs); the histogram is row 0
+      // the whole workgroup per centre (hubs): each wave fills its own
+      // histogram row and the rows are summed
       for (uint64_t pos = seg; pos < seg_end; ++pos) {
         const uint64_t r0 = ix.vrow[pos];
         const uint32_t v = ix.vlist[pos];
         const uint64_t r1 = rowptr[v + 1];
-        for (uint64_t x = r0 + tid; x < r1; x += kCensusWG)
-          atomicAdd(&s_hist[0][C.vbucket[col[x]]], 1u);
+        for (uint64_t x0 = r0 + tid; x0 < r1; x0 += 4 * kCensusWG) {
+          uint32_t nb[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            nb[q] = x0 + kCensusWG * q < r1 ? col[x0 + kCensusWG * q] : 0;
+          uint32_t bk[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bk[q] = x0 + kCensusWG * q < r1 ? C.vbucket[nb[q]] : 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (x0 + kCensusWG * q < r1) atomicAdd(&s_hist[wave][bk[q]], 1u);
+        }
         __syncthreads();
         uint32_t h = 0, nz = 0;
         if (tid < (int)kBuckets) {
-          h = s_hist[0][tid];
+          for (int w = 0; w < (int)kCensusWaves; ++w) h += s_hist[w][tid];
           nz = h > 0;
         }
         const uint32_t pre = wave_incl_scan(nz, lane);
@@ -384,7 +416,7 @@ __global__ __launch_bounds__(kCensusWG) void k_census(const uint64_t* __restrict
             s_list[1][before + pre - 1] = (uint16_t)tid;
             s_cnt[1][before + pre - 1] = h;
           }
-          s_hist[0][tid] = 0;
+          for (int w = 0; w < (int)kCensusWaves; ++w) s_hist[w][tid] = 0;
         }
         __syncthreads();
         const uint32_t np = u * (u + 1) / 2;

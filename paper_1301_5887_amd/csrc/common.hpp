@@ -77,6 +77,7 @@ struct IndexView {
   uint32_t* cls_deg;  // [class_cap] degree of class j (ascending)
   uint32_t* cls_start;// [class_cap] first position of class j in vlist
   uint64_t* cls_cumw; // [class_cap] inclusive prefix of count_j * C(d_j, 2)
+  uint8_t* vcode;     // [n] degree code floor(8 L(d)) per vertex id (monotone in d)
 };
 
 // Upper bound on the number of distinct (graph, degree) pairs of G simple

@@ -27,6 +27,8 @@ struct MlpState {
   uint16_t bf[kPad];
   float m[kPad];
   float v[kPad];
+  uint16_t w2t[kH * kH];  // BF16 W2^T in MFMA A-operand order [m][kk][lane][j]
+  uint16_t w2a[kH * kH];  // BF16 W2 in MFMA A-operand order [m][kk][lane][j]
 };
 
 typedef short s4 __attribute__((ext_vector_type(4)));
@@ -54,11 +56,41 @@ __device__ inline s4 pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
 }
 
 
+// Writes parameter p: FP32 master, BF16 copy and, for W2, its place in the
+// transposed operand tiles (W2[o][i] is element j = o % 4 of lane
+// 16 ((o % 16) / 4) + i % 16 of tile (m, kk) = (i / 16, o / 16)).
+__device__ inline void store_param(MlpState* S, int p, float w) {
+  S->master[p] = w;
+  const uint16_t b = f2bf(w);
+  S->bf[p] = b;
+  if (p >= OFF_W2 && p < OFF_W2 + kH * kH) {
+    const int o = (p - OFF_W2) / kH, i = (p - OFF_W2) % kH;
+    const int lane_t = 16 * ((o % 16) / 4) + i % 16;
+    S->w2t[(((i / 16) * 4 + o / 16) * 64 + lane_t) * 4 + o % 4] = b;
+    // W2[o][i] is element j = i % 4 of lane 16 ((i % 16) / 4) + o % 16 of
+    // tile (m, kk) = (o / 16, i / 16) of the forward product
+    const int lane_a = 16 * ((i % 16) / 4) + o % 16;
+    S->w2a[(((o / 16) * 4 + i / 16) * 64 + lane_a) * 4 + i % 4] = b;
+  }
+}
+
 // GELU(a) = a Phi(a) with Phi the standard normal CDF; its derivative is
 // Phi(a) + a phi(a).  The forward pass keeps Phi for the backward pass.
-__device__ inline float norm_cdf(float a) { return 0.5f * (1.0f + erff(a * 0.70710678118654752f)); }
+// erf is the branch-free rational approximation 7.1.26 of Abramowitz and
+// Stegun (Handbook of Mathematical Functions, 1964): for x >= 0,
+// erf x = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p x), with
+// absolute error below 1.5e-7, far inside the BF16 rounding of the network.
+__device__ inline float norm_cdf(float a) {
+  const float x = fabsf(a) * 0.70710678118654752f;
+  const float t = 1.0f / (1.0f + 0.3275911f * x);
+  const float poly =
+      t * (0.254829592f +
+           t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float erf_x = 1.0f - poly * __expf(-x * x);
+  return 0.5f + 0.5f * (a < 0.f ? -erf_x : erf_x);
+}
 __device__ inline float gelu_grad_from(float a, float cdf) {
-  return cdf + a * (expf(-0.5f * a * a) * 0.39894228040143268f);
+  return cdf + a * (__expf(-0.5f * a * a) * 0.39894228040143268f);
 }
 
 // Log-degree bucket K(d) = floor(8 L(d)), L Mitchell's log2, in integers.
@@ -131,8 +163,19 @@ struct RegBias {
   __device__ float b3() const { return W.b3; }
 };
 
-template <class Bias>
-__device__ inline void forward_tile(const s4 (&w1)[4], const s4 (&w2)[4][4], const Bias& Bs,
+// Layer-2 A operands held in registers (forward kernel) or read from LDS.
+struct RegW2 {
+  const s4 (&w)[4][4];
+  __device__ s4 operator()(int m, int kk) const { return w[m][kk]; }
+};
+struct LdsW2 {
+  const s4 (*w)[4][64];
+  int lane;
+  __device__ s4 operator()(int m, int kk) const { return w[m][kk][lane]; }
+};
+
+template <class Bias, class W2>
+__device__ inline void forward_tile(const s4 (&w1)[4], const W2& w2, const Bias& Bs,
                                     const float x[4], int kb, TileAct& T) {
   const s4 xb = kb == 0 ? pack4(f2bf(x[0]), f2bf(x[1]), f2bf(x[2]), f2bf(x[3])) : pack4(0, 0, 0, 0);
 #pragma unroll
@@ -155,7 +198,7 @@ __device__ inline void forward_tile(const s4 (&w1)[4], const s4 (&w2)[4][4], con
   for (int m = 0; m < 4; ++m) {
     f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) acc = mfma16(w2[m][kk], T.h1[kk], acc);
+    for (int kk = 0; kk < 4; ++kk) acc = mfma16(w2(m, kk), T.h1[kk], acc);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const float a = acc[t] + Bs.b2(m, t);
@@ -184,7 +227,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const MlpState* __restrict_
     float xf[4] = {0.f, 0.f, 0.f, 0.f};
     if (valid) features(x[i], xf);
     TileAct T;
-    forward_tile(W.w1, W.w2, RegBias{W}, xf, kb, T);
+    forward_tile(W.w1, RegW2{W.w2}, RegBias{W}, xf, kb, T);
     if (kb == 0 && valid) g[i] = 1.0f / (1.0f + expf(-T.z));
   }
 }
@@ -211,70 +254,6 @@ struct GradSmem {
   uint16_t x[16][16];    // X     [s][f], f >= 4 zero
 };
 
-// LDS ordering between lanes of one wave
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// Gradient accumulators of one wave (lane-distributed as the MFMA outputs).
-struct GradAcc {
-  f4 dW2[4][4];
-  f4 dW1[4];
-  float gW3[4][4], gb2[4][4], gb1[4][4];
-  float gb3, lsum;
-};
-
-// Adds (first = false) or stores (first = true) a wave's accumulators into
-// the parameter-ordered array P; lanes touch disjoint entries, so a whole
-// wave's update needs no atomics.
-__device__ inline void acc_to(const GradAcc& A, float* P, int sl, int kb, int lane, bool first) {
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-#pragma unroll
-    for (int nn = 0; nn < 4; ++nn)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        float& dst = P[OFF_W2 + (16 * m + 4 * kb + t) * kH + 16 * nn + sl];
-        dst = first ? A.dW2[m][nn][t] : dst + A.dW2[m][nn][t];
-      }
-    if (sl < 4)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        float& dst = P[OFF_W1 + (16 * m + 4 * kb + t) * 4 + sl];
-        dst = first ? A.dW1[m][t] : dst + A.dW1[m][t];
-      }
-  }
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      float a = A.gW3[m][t], b = A.gb2[m][t], c = A.gb1[m][t];
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-        c += __shfl_xor(c, off, 64);
-      }
-      if (sl == 0) {
-        const int h = 16 * m + 4 * kb + t;
-        P[OFF_W3 + h] = first ? a : P[OFF_W3 + h] + a;
-        P[OFF_B2 + h] = first ? b : P[OFF_B2 + h] + b;
-        P[OFF_B1 + h] = first ? c : P[OFF_B1 + h] + c;
-      }
-    }
-  float gb3 = A.gb3, lsum = A.lsum;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    gb3 += __shfl_xor(gb3, off, 64);
-    lsum += __shfl_xor(lsum, off, 64);
-  }
-  if (lane == 0) {
-    P[OFF_B3] = first ? gb3 : P[OFF_B3] + gb3;
-    P[NPARAM] = first ? lsum : P[NPARAM] + lsum;  // loss sum in the padding
-  }
-}
-
 // Biases and output weights read from LDS (gradient kernel).
 struct LdsBias {
   const float* pb1;
@@ -290,74 +269,79 @@ struct LdsBias {
 
 // Gradient of the mean BCE over minibatch records [kGradChunk*wg, +kGradChunk)
 // into partial[wg][kPad] (entry NPARAM holds the loss sum).  Four waves per
-// workgroup, each on its own 16-record tiles; the waves' sums are combined in
-// LDS in wave order, so the result does not depend on scheduling.
-__global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const MlpState* __restrict__ S,
-                                                              RowView x, uint64_t n, float inv_n,
-                                                              float* __restrict__ partial) {
-  __shared__ GradSmem s_w[kGradWaves];
-  __shared__ float s_p[kPad];
-  __shared__ float s_b1[kH], s_b2[kH], s_w3[kH], s_b3;
-  __shared__ s4 s_w2t[4][4][64];  // A tiles of W2^T [m][kk][lane]
+// workgroup work in rounds: each wave carries its own 16-record tile through
+// the network and leaves dA2^T, H1^T, dA1^T and X in LDS; then wave w forms
+// rows 16w .. 16w+15 of dW2 and dW1 from all four tiles, so every weight
+// gradient has one owner and no cross-wave sum.  The bias and W3 sums are
+// added up at the end in a fixed order (waves, then sample columns), so the
+// result does not depend on scheduling.
+__global__ __launch_bounds__(64 * kGradWaves, 2) void k_mlp_grad(const MlpState* __restrict__ S,
+                                                                 RowView x, uint64_t n,
+                                                                 float inv_n,
+                                                                 float* __restrict__ partial) {
+  struct LoopSmem {
+    GradSmem w[kGradWaves];
+    float b1[kH], b2[kH], w3[kH], b3;
+    s4 w2t[4][4][64];  // A tiles of W2^T [m][kk][lane]
+    s4 w2[4][4][64];   // A tiles of W2 [m][kk][lane]
+  };
+  struct EndSmem {
+    float col[kGradWaves][3][kH][16];  // W3, b2, b1 sums per sample column
+    float sc[kGradWaves][2][64];       // b3 and loss per lane
+  };
+  __shared__ union {
+    LoopSmem loop;
+    EndSmem end;
+  } u;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sl = lane & 15, kb = lane >> 4;
-  GradSmem& sm = s_w[wave];
-  // operand tiles of W1 and W2 stay in registers; biases, W3 and the W2^T
-  // tiles of the backward product come from LDS
-  s4 w1[4], w2[4][4];
+  GradSmem& sm = u.loop.w[wave];
+  s4 w1[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int r = 16 * m + sl;
     w1[m] = kb == 0 ? pack4(S->bf[OFF_W1 + r * 4 + 0], S->bf[OFF_W1 + r * 4 + 1],
                             S->bf[OFF_W1 + r * 4 + 2], S->bf[OFF_W1 + r * 4 + 3])
                     : pack4(0, 0, 0, 0);
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int c = OFF_W2 + r * kH + 16 * kk + 4 * kb;
-      w2[m][kk] = pack4(S->bf[c], S->bf[c + 1], S->bf[c + 2], S->bf[c + 3]);
-    }
   }
   if (tid < kH) {
-    s_b1[tid] = S->master[OFF_B1 + tid];
-    s_b2[tid] = S->master[OFF_B2 + tid];
-    s_w3[tid] = bf2f(S->bf[OFF_W3 + tid]);
-    if (tid == 0) s_b3 = S->master[OFF_B3];
+    u.loop.b1[tid] = S->master[OFF_B1 + tid];
+    u.loop.b2[tid] = S->master[OFF_B2 + tid];
+    u.loop.w3[tid] = bf2f(S->bf[OFF_W3 + tid]);
+    if (tid == 0) u.loop.b3 = S->master[OFF_B3];
   }
   for (int e = tid; e < 16 * 64; e += 64 * kGradWaves) {
-    const int m = e >> 8, kk = (e >> 6) & 3, l = e & 63;
-    const int o = 16 * kk + 4 * (l >> 4), i = 16 * m + (l & 15);
-    s_w2t[m][kk][l] = pack4(S->bf[OFF_W2 + (o + 0) * kH + i], S->bf[OFF_W2 + (o + 1) * kH + i],
-                            S->bf[OFF_W2 + (o + 2) * kH + i], S->bf[OFF_W2 + (o + 3) * kH + i]);
+    (&u.loop.w2t[0][0][0])[e] = reinterpret_cast<const s4*>(S->w2t)[e];
+    (&u.loop.w2[0][0][0])[e] = reinterpret_cast<const s4*>(S->w2a)[e];
   }
   __syncthreads();
-  const LdsBias Bs{s_b1, s_b2, s_w3, s_b3, kb};
-  GradAcc A;
+  const LdsBias Bs{u.loop.b1, u.loop.b2, u.loop.w3, u.loop.b3, kb};
+  const LdsW2 W2{u.loop.w2, lane};
+  f4 dW2[4], dW1 = {0.f, 0.f, 0.f, 0.f};  // rows 16 wave + 4 kb + t of the products
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    A.dW1[m] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int nn = 0; nn < 4; ++nn) dW2[nn] = f4{0.f, 0.f, 0.f, 0.f};
+  float gW3[4][4], gb2[4][4], gb1[4][4];
 #pragma unroll
-    for (int nn = 0; nn < 4; ++nn) A.dW2[m][nn] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) A.gW3[m][t] = A.gb2[m][t] = A.gb1[m][t] = 0.f;
-  }
-  A.gb3 = 0.f;
-  A.lsum = 0.f;
+    for (int t = 0; t < 4; ++t) gW3[m][t] = gb2[m][t] = gb1[m][t] = 0.f;
+  float gb3 = 0.f, lsum = 0.f;
 
   const uint64_t begin = (uint64_t)blockIdx.x * kGradChunk;
   const uint64_t end = min(begin + kGradChunk, n);
-  // the next tile's record is loaded while the current tile is computed
+  // the next round's record is loaded while the current tile is computed
   wedge_feature_rec next{};
   {
     const uint64_t i0 = begin + 16 * (uint64_t)wave + sl;
     if (i0 < end) next = x[i0];
   }
-  for (uint64_t base = begin + 16 * (uint64_t)wave; base < end; base += 16 * kGradWaves) {
-    const uint64_t i = base + sl;
+  for (int round = 0; round < kGradTilesPerWave; ++round) {
+    const uint64_t i = begin + 16 * ((uint64_t)round * kGradWaves + wave) + sl;
     const bool valid = i < end;
     const wedge_feature_rec r = next;
     {
       const uint64_t i2 = i + 16 * kGradWaves;
-      if (i2 < end) next = x[i2];
+      if (round + 1 < kGradTilesPerWave && i2 < end) next = x[i2];
     }
     float xf[4] = {0.f, 0.f, 0.f, 0.f};
     float y = 0.f;
@@ -366,12 +350,12 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const MlpState* __
       y = r.closed ? 1.f : 0.f;
     }
     TileAct T;
-    forward_tile(w1, w2, Bs, xf, kb, T);
+    forward_tile(w1, W2, Bs, xf, kb, T);
     const float gz = 1.0f / (1.0f + expf(-T.z));
     const float dz = valid ? (gz - y) * inv_n : 0.f;
     if (kb == 0) {
-      A.gb3 += dz;
-      if (valid) A.lsum += fmaxf(T.z, 0.f) + log1pf(expf(-fabsf(T.z))) - y * T.z;
+      gb3 += dz;
+      if (valid) lsum += fmaxf(T.z, 0.f) + log1pf(expf(-fabsf(T.z))) - y * T.z;
     }
     float da2[4][4];
 #pragma unroll
@@ -379,81 +363,147 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const MlpState* __
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int h = 16 * m + 4 * kb + t;
-        A.gW3[m][t] += dz * (T.a2[m][t] * T.c2[m][t]);
+        gW3[m][t] += dz * (T.a2[m][t] * T.c2[m][t]);
         da2[m][t] = dz * Bs.w3(m, t) * gelu_grad_from(T.a2[m][t], T.c2[m][t]);
-        A.gb2[m][t] += da2[m][t];
+        gb2[m][t] += da2[m][t];
         sm.da2[h][sl] = f2bf(da2[m][t]);
         sm.h1[h][sl] = (uint16_t)T.h1[m][t];
       }
 #pragma unroll
     for (int j = 0; j < 4; ++j) sm.x[sl][4 * kb + j] = kb == 0 ? f2bf(xf[j]) : (uint16_t)0;
-    wave_lds_sync();
-    // dW2[o][i] += sum_s dA2^T[o][s] H1^T[i][s]
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const s4 a = *reinterpret_cast<const s4*>(&sm.da2[16 * m + sl][4 * kb]);
-#pragma unroll
-      for (int nn = 0; nn < 4; ++nn) {
-        const s4 b = *reinterpret_cast<const s4*>(&sm.h1[16 * nn + sl][4 * kb]);
-        A.dW2[m][nn] = mfma16(a, b, A.dW2[m][nn]);
-      }
-    }
     // dH1^T = W2^T dA2^T; dA1^T = dH1^T * GELU'(A1^T)
+    s4 bda2[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      bda2[kk] = pack4(f2bf(da2[kk][0]), f2bf(da2[kk][1]), f2bf(da2[kk][2]), f2bf(da2[kk][3]));
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const s4 b = pack4(f2bf(da2[kk][0]), f2bf(da2[kk][1]), f2bf(da2[kk][2]), f2bf(da2[kk][3]));
-        acc = mfma16(s_w2t[m][kk][lane], b, acc);
-      }
+      for (int kk = 0; kk < 4; ++kk) acc = mfma16(u.loop.w2t[m][kk][lane], bda2[kk], acc);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const float da1 = acc[t] * gelu_grad_from(T.a1[m][t], T.c1[m][t]);
-        A.gb1[m][t] += da1;
+        gb1[m][t] += da1;
         sm.da1[16 * m + 4 * kb + t][sl] = f2bf(da1);
       }
     }
-    wave_lds_sync();
-    // dW1[i][f] += sum_s dA1^T[i][s] X[s][f]
+    __syncthreads();
+    // rows 16 wave .. +15 of dW2[o][i] += sum_s dA2^T[o][s] H1^T[i][s] and of
+    // dW1[i][f] += sum_s dA1^T[i][s] X[s][f], over the four tiles
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const s4 a = *reinterpret_cast<const s4*>(&sm.da1[16 * m + sl][4 * kb]);
-      const s4 b = pack4(sm.x[4 * kb + 0][sl], sm.x[4 * kb + 1][sl], sm.x[4 * kb + 2][sl],
-                         sm.x[4 * kb + 3][sl]);
-      A.dW1[m] = mfma16(a, b, A.dW1[m]);
+    for (int j = 0; j < kGradWaves; ++j) {
+      const GradSmem& tj = u.loop.w[j];
+      const s4 a2 = *reinterpret_cast<const s4*>(&tj.da2[16 * wave + sl][4 * kb]);
+#pragma unroll
+      for (int nn = 0; nn < 4; ++nn) {
+        const s4 b = *reinterpret_cast<const s4*>(&tj.h1[16 * nn + sl][4 * kb]);
+        dW2[nn] = mfma16(a2, b, dW2[nn]);
+      }
+      const s4 a1 = *reinterpret_cast<const s4*>(&tj.da1[16 * wave + sl][4 * kb]);
+      const s4 bx = pack4(tj.x[4 * kb + 0][sl], tj.x[4 * kb + 1][sl], tj.x[4 * kb + 2][sl],
+                          tj.x[4 * kb + 3][sl]);
+      dW1 = mfma16(a1, bx, dW1);
     }
-    wave_lds_sync();
-  }
-  // waves in order: 0 stores, 1..3 add
-  for (int w = 0; w < kGradWaves; ++w) {
-    if (wave == w) acc_to(A, s_p, sl, kb, lane, w == 0);
     __syncthreads();
   }
   float* P = partial + (uint64_t)blockIdx.x * kPad;
-  for (int p = tid; p <= NPARAM; p += 64 * kGradWaves) P[p] = s_p[p];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int o = 16 * wave + 4 * kb + t;
+#pragma unroll
+    for (int nn = 0; nn < 4; ++nn) P[OFF_W2 + o * kH + 16 * nn + sl] = dW2[nn][t];
+    if (sl < 4) P[OFF_W1 + o * 4 + sl] = dW1[t];
+  }
+  EndSmem& E = u.end;  // the loop's LDS is free after the last barrier
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int h = 16 * m + 4 * kb + t;
+      E.col[wave][0][h][sl] = gW3[m][t];
+      E.col[wave][1][h][sl] = gb2[m][t];
+      E.col[wave][2][h][sl] = gb1[m][t];
+    }
+  E.sc[wave][0][lane] = kb == 0 ? gb3 : 0.f;
+  E.sc[wave][1][lane] = kb == 0 ? lsum : 0.f;
+  __syncthreads();
+  // b1, b2, W3 (64 each), b3 and the loss sum: added in a fixed order
+  for (int q = tid; q < 3 * kH + 2; q += 64 * kGradWaves) {
+    float v = 0.f;
+    int p;
+    if (q < 3 * kH) {
+      const int which = q / kH, h = q % kH;  // 0: W3, 1: b2, 2: b1
+      for (int w = 0; w < kGradWaves; ++w)
+        for (int c = 0; c < 16; ++c) v += E.col[w][which][h][c];
+      p = (which == 0 ? OFF_W3 : which == 1 ? OFF_B2 : OFF_B1) + h;
+    } else {
+      const int j = q - 3 * kH;  // 0: b3, 1: loss (kept in the padding entry NPARAM)
+      for (int w = 0; w < kGradWaves; ++w)
+        for (int l = 0; l < 64; ++l) v += E.sc[w][j][l];
+      p = OFF_B3 + j;
+    }
+    P[p] = v;
+  }
 }
 
 // Sum of the partial gradients (deterministic: wave q of a block sums the
-// workgroups w = q mod 4 in order, and the four sums are added in q order);
+// workgroups w = q mod 16 in order, and the 16 sums are added in q order);
 // the padding entry NPARAM carries the loss sum.
-__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ partial,
-                                                    uint32_t nwg, float* __restrict__ grad,
-                                                    float inv_n, float* __restrict__ loss) {
-  __shared__ float s_q[4][64];
-  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int p = blockIdx.x * 64 + lane;
+constexpr int kRedSplit = 16;
+__device__ inline float reduce_param(const float* __restrict__ partial, uint32_t nwg, int p,
+                                     float (*s_q)[64], int lane, int q) {
   float s = 0.f;
   if (p <= NPARAM) {
 #pragma unroll 4
-    for (uint32_t w = q; w < nwg; w += 4) s += partial[(uint64_t)w * kPad + p];
+    for (uint32_t w = q; w < nwg; w += kRedSplit) s += partial[(uint64_t)w * kPad + p];
   }
   s_q[q][lane] = s;
   __syncthreads();
+  float t = 0.f;
+  if (q == 0)
+    for (int j = 0; j < kRedSplit; ++j) t += s_q[j][lane];
+  return t;
+}
+
+__global__ __launch_bounds__(64 * kRedSplit) void k_mlp_reduce(const float* __restrict__ partial,
+                                                               uint32_t nwg,
+                                                               float* __restrict__ grad,
+                                                               float inv_n,
+                                                               float* __restrict__ loss) {
+  __shared__ float s_q[kRedSplit][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
+  const float t = reduce_param(partial, nwg, p, s_q, lane, q);
   if (q == 0 && p <= NPARAM) {
-    const float t = ((s_q[0][lane] + s_q[1][lane]) + s_q[2][lane]) + s_q[3][lane];
     if (p < NPARAM)
       grad[p] = t;
+    else if (loss)
+      *loss = t * inv_n;
+  }
+}
+
+__device__ inline void adam_update(MlpState* S, int p, float g, float lr, float b1, float b2,
+                                   float eps, float c1, float c2) {
+  const float m = b1 * S->m[p] + (1.f - b1) * g;
+  const float v = b2 * S->v[p] + (1.f - b2) * g * g;
+  S->m[p] = m;
+  S->v[p] = v;
+  const float mh = m / c1, vh = v / c2;
+  store_param(S, p, S->master[p] - lr * mh / (sqrtf(vh) + eps));
+}
+
+// The reduction above followed by the Adam step of each parameter.
+__global__ __launch_bounds__(64 * kRedSplit) void k_mlp_reduce_adam(
+    const float* __restrict__ partial, uint32_t nwg, MlpState* __restrict__ S, float inv_n,
+    float* __restrict__ loss, float lr, float b1, float b2, float eps, float c1, float c2) {
+  __shared__ float s_q[kRedSplit][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
+  const float t = reduce_param(partial, nwg, p, s_q, lane, q);
+  if (q == 0 && p <= NPARAM) {
+    if (p < NPARAM)
+      adam_update(S, p, t, lr, b1, b2, eps, c1, c2);
     else if (loss)
       *loss = t * inv_n;
   }
@@ -463,23 +513,13 @@ __global__ void k_mlp_adam(MlpState* __restrict__ S, const float* __restrict__ g
                            float b1, float b2, float eps, float c1, float c2) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= NPARAM) return;
-  const float g = grad[p];
-  const float m = b1 * S->m[p] + (1.f - b1) * g;
-  const float v = b2 * S->v[p] + (1.f - b2) * g * g;
-  S->m[p] = m;
-  S->v[p] = v;
-  const float mh = m / c1, vh = v / c2;
-  const float w = S->master[p] - lr * mh / (sqrtf(vh) + eps);
-  S->master[p] = w;
-  S->bf[p] = f2bf(w);
+  adam_update(S, p, grad[p], lr, b1, b2, eps, c1, c2);
 }
 
 __global__ void k_mlp_set(MlpState* __restrict__ S, const float* __restrict__ params) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= kPad) return;
-  const float w = p < NPARAM ? params[p] : 0.f;
-  S->master[p] = w;
-  S->bf[p] = f2bf(w);
+  store_param(S, p, p < NPARAM ? params[p] : 0.f);
   S->m[p] = 0.f;
   S->v[p] = 0.f;
 }
@@ -499,8 +539,7 @@ __global__ void k_mlp_init(MlpState* __restrict__ S, uint64_t seed) {
     const double u = (double)(o.w[0] >> 11) * (1.0 / 9007199254740992.0);
     w = (float)((2.0 * u - 1.0) / sqrt((double)fan));
   }
-  S->master[p] = w;
-  S->bf[p] = f2bf(w);
+  store_param(S, p, w);
   S->m[p] = 0.f;
   S->v[p] = 0.f;
 }
@@ -567,7 +606,8 @@ static int grad_impl(const MlpState* S, const wedge_feature_rec* d_x, uint64_t s
   RowView view{d_x, stride, j0, per_row};
   k_mlp_grad<<<nwg, 64 * kGradWaves, 0, st>>>(S, view, n, inv_n, partial);
   WEDGE_LAUNCH_CHECK("k_mlp_grad");
-  k_mlp_reduce<<<(NPARAM + 1 + 63) / 64, 256, 0, st>>>(partial, nwg, d_grad, inv_n, d_loss);
+  k_mlp_reduce<<<(NPARAM + 1 + 63) / 64, 64 * kRedSplit, 0, st>>>(partial, nwg, d_grad, inv_n,
+                                                                  d_loss);
   WEDGE_LAUNCH_CHECK("k_mlp_reduce");
   return WEDGE_OK;
 }
@@ -695,18 +735,20 @@ extern "C" int wedge_mlp_train(void* d_state, const wedge_feature_rec* d_x, uint
   MlpState* S = (MlpState*)d_state;
   const uint64_t n = (uint64_t)rows * per_row_batch;
   float* partial = (float*)d_workspace;
-  float* grad = (float*)((char*)d_workspace + wedge_mlp_grad_workspace(n));
   uint32_t t = t0;
   for (uint32_t ep = 0; ep < epochs; ++ep) {
     for (uint64_t j0 = 0; j0 < n_fit; j0 += per_row_batch) {
       const bool last = ep + 1 == epochs && j0 + per_row_batch == n_fit;
-      int rc = grad_impl(S, d_x, stride, j0, per_row_batch, n, grad, last ? d_loss : nullptr,
-                         partial, st);
-      if (rc) return rc;
+      const uint32_t nwg = grad_groups(n);
+      const float inv_n = 1.0f / (float)n;
+      RowView view{d_x, stride, j0, per_row_batch};
+      k_mlp_grad<<<nwg, 64 * kGradWaves, 0, st>>>(S, view, n, inv_n, partial);
+      WEDGE_LAUNCH_CHECK("k_mlp_grad");
       float c1, c2;
       adam_consts(++t, beta1, beta2, &c1, &c2);
-      k_mlp_adam<<<(NPARAM + 255) / 256, 256, 0, st>>>(S, grad, lr, beta1, beta2, eps, c1, c2);
-      WEDGE_LAUNCH_CHECK("k_mlp_adam");
+      k_mlp_reduce_adam<<<(NPARAM + 1 + 63) / 64, 64 * kRedSplit, 0, st>>>(
+          partial, nwg, S, inv_n, last ? d_loss : nullptr, lr, beta1, beta2, eps, c1, c2);
+      WEDGE_LAUNCH_CHECK("k_mlp_reduce_adam");
     }
   }
   return WEDGE_OK;

@@ -191,6 +191,7 @@ int radix_sort(uint64_t* keys, uint64_t* alt, uint64_t N, const int* shifts, int
 
 struct OsShifts {
   int s[kOsMaxPasses];
+  int mirror[kOsMaxPasses];  // pass whose histogram equals this one's, or -1
   int npass;
 };
 
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(kOsWG) void k_os_hist_edges(EdgeSource E, OsShifts 
     const uint64_t k1 = edge_key(E, 2 * i + 1, &bad);
     bad_edges += bad ? 1 : 0;
     for (int p = 0; p < S.npass; ++p) {
+      if (S.mirror[p] >= 0) continue;
       atomicAdd(&s_h[p][(k0 >> S.s[p]) & 255], 1u);
       atomicAdd(&s_h[p][(k1 >> S.s[p]) & 255], 1u);
     }
@@ -254,11 +256,12 @@ __global__ __launch_bounds__(kOsWG) void k_os_hist_edges(EdgeSource E, OsShifts 
 
 // base[p][d] = number of keys whose digit p is below d.
 __global__ __launch_bounds__(256) void k_os_base(const uint64_t* __restrict__ hist,
-                                                 uint64_t* __restrict__ base, int npass) {
+                                                 uint64_t* __restrict__ base, OsShifts S) {
   __shared__ uint64_t s_w[4];
   const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
-  for (int p = 0; p < npass; ++p) {
-    const uint64_t c = hist[p * 256 + d];
+  for (int p = 0; p < S.npass; ++p) {
+    const int hp = S.mirror[p] >= 0 ? S.mirror[p] : p;
+    const uint64_t c = hist[hp * 256 + d];
     const uint64_t incl = wave_incl_scan(c, lane);
     if (lane == 63) s_w[wave] = incl;
     __syncthreads();
@@ -298,25 +301,35 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
   const uint64_t tile = s_tile;
   const uint64_t tbase = tile * kOsTile;
 
-  // stable ranking inside the tile (see k_radix_scatter)
+  // stable ranking inside the tile (see k_radix_scatter).  The first pass
+  // may take its keys in any order (the edge list has none), so each lane
+  // reads whole edges and holds both keys of an edge.
   uint64_t key[kOsItems];
   uint32_t rank[kOsItems];
+  bool ok[kOsItems];
   const uint64_t lt_mask = (1ULL << lane) - 1;
+  if (kEdges) {
+    const uint64_t ebase = tile * (kOsTile / 2);
 #pragma unroll
-  for (int it = 0; it < kOsItems; ++it) {
-    const uint64_t g = tbase + (uint64_t)wave * 64 * kOsItems + (uint64_t)it * 64 + lane;
-    const bool valid = g < N;
-    if (kEdges) {
+    for (int it = 0; it < kOsItems / 2; ++it) {
+      const uint64_t e = ebase + (uint64_t)wave * 64 * (kOsItems / 2) + (uint64_t)it * 64 + lane;
+      const bool valid = e < E.m_in;
       bool bad;
-      key[it] = valid ? edge_key(E, g, &bad) : 0;
-    } else {
-      key[it] = valid ? in[g] : 0;
+      key[2 * it] = valid ? edge_key(E, 2 * e, &bad) : 0;
+      key[2 * it + 1] = valid ? edge_key(E, 2 * e + 1, &bad) : 0;
+      ok[2 * it] = ok[2 * it + 1] = valid;
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < kOsItems; ++it) {
+      const uint64_t g = tbase + (uint64_t)wave * 64 * kOsItems + (uint64_t)it * 64 + lane;
+      ok[it] = g < N;
+      key[it] = ok[it] ? in[g] : 0;
     }
   }
 #pragma unroll
   for (int it = 0; it < kOsItems; ++it) {
-    const uint64_t g = tbase + (uint64_t)wave * 64 * kOsItems + (uint64_t)it * 64 + lane;
-    const bool valid = g < N;
+    const bool valid = ok[it];
     const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -362,23 +375,38 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
     const int d = tid;
     uint64_t excl = 0;
     if (tile > 0) {
+      // walk back four tiles per step (four status loads in flight), adding
+      // published counts in order until an inclusive prefix is met
       uint64_t t = tile - 1;
       uint32_t spins = 0;
-      for (;;) {
-        const unsigned long long x = os_load(status + t * 256 + d);
-        if ((x & ~(kOsValue | kOsAgg | kOsInc)) != tag || (x & (kOsAgg | kOsInc)) == 0) {
-          // every earlier tile is running and publishes without waiting, so
-          // this ends; the bound only guarantees that the wave exits
+      bool done = false;
+      while (!done) {
+        const uint64_t nload = t + 1 < 4 ? t + 1 : 4;
+        unsigned long long xs[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xs[j] = (uint64_t)j < nload ? os_load(status + (t - j) * 256 + d) : 0;
+        uint64_t used = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (done || used != (uint64_t)j || (uint64_t)j >= nload) continue;
+          const unsigned long long x = xs[j];
+          if ((x & ~(kOsValue | kOsAgg | kOsInc)) != tag || (x & (kOsAgg | kOsInc)) == 0) continue;
+          excl += x & kOsValue;
+          ++used;
+          if (x & kOsInc) done = true;
+        }
+        if (done) break;
+        t -= used;
+        if (used < nload) {
+          // tile t has not published yet: every earlier tile is running and
+          // publishes without waiting, so this ends; the bound only
+          // guarantees that the wave exits
           if (++spins > (1u << 24)) {
             atomicAdd(ticket + kOsMaxPasses, 1ULL);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
-          continue;
         }
-        excl += x & kOsValue;
-        if (x & kOsInc) break;
-        --t;
       }
       os_store(status + tile * 256 + d, tag | kOsInc | (excl + cnt));
     }
@@ -387,8 +415,7 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < kOsItems; ++it) {
-    const uint64_t g = tbase + (uint64_t)wave * 64 * kOsItems + (uint64_t)it * 64 + lane;
-    if (g < N) {
+    if (ok[it]) {
       const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
       s_keys[s_tile_off[d] + s_cnt[wave][d] + rank[it]] = key[it];
     }
@@ -413,6 +440,14 @@ int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int
   OsShifts S;
   S.npass = npass;
   for (int p = 0; p < kOsMaxPasses; ++p) S.s[p] = p < npass ? shifts[p] : 0;
+  // both keys of every edge are sorted, so the src digit at bit 32 + s has
+  // the same histogram as the dst digit at bit s: count it once
+  for (int p = 0; p < kOsMaxPasses; ++p) {
+    S.mirror[p] = -1;
+    if (p >= npass || S.s[p] < 32) continue;
+    for (int q = 0; q < npass; ++q)
+      if (S.s[q] == S.s[p] - 32) S.mirror[p] = q;
+  }
   int rc = fill<uint64_t>(sc.hist, kOsMaxPasses * 256, 0, st);
   if (rc) return rc;
   if ((rc = fill<unsigned long long>(sc.tickets, kOsMaxPasses + 1, 0, st))) return rc;
@@ -424,7 +459,7 @@ int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int
     k_os_hist_edges<<<(unsigned)blocks, kOsWG, 0, st>>>(E, S, sc.hist);
     WEDGE_LAUNCH_CHECK("k_os_hist_edges");
   }
-  k_os_base<<<1, 256, 0, st>>>(sc.hist, sc.base, npass);
+  k_os_base<<<1, 256, 0, st>>>(sc.hist, sc.base, S);
   WEDGE_LAUNCH_CHECK("k_os_base");
   uint64_t* src = nullptr;
   uint64_t* dst = a;

@@ -162,23 +162,31 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       a[u] = act[u] ? col[rp[u] + ia[u]] : 0;
       c[u] = act[u] ? col[rp[u] + ic[u]] : 0;
     }
-    // 4. closure: search the endpoint in the shorter of the two rows
+    // 4. closure: search one endpoint in the row of the other, the row with
+    //    the smaller degree code (a byte per vertex; tie: the row of a), so
+    //    only one endpoint's row bounds are read up front
     uint64_t da[U], dc[U];
+    bool in_a[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      uint64_t ra0 = 0, ra1 = 0, rc0 = 0, rc1 = 0;
+      uint32_t ca = 0, cc = 0;
       if (act[u]) {
-        ra0 = rowptr[a[u]];
-        ra1 = rowptr[a[u] + 1];
-        rc0 = rowptr[c[u]];
-        rc1 = rowptr[c[u] + 1];
+        ca = A.ix.vcode[a[u]];
+        cc = A.ix.vcode[c[u]];
       }
-      da[u] = ra1 - ra0;
-      dc[u] = rc1 - rc0;
-      const bool in_a = da[u] <= dc[u];
-      lo[u] = in_a ? ra0 : rc0;
-      len[u] = (act[u] && A.closure) ? (in_a ? da[u] : dc[u]) : 0;
-      key[u] = in_a ? c[u] : a[u];
+      in_a[u] = ca <= cc;
+      const uint32_t x = in_a[u] ? a[u] : c[u];
+      uint64_t r0 = 0, r1 = 0;
+      if (act[u]) {
+        r0 = rowptr[x];
+        r1 = rowptr[x + 1];
+      }
+      const uint64_t dx = r1 - r0;
+      da[u] = in_a[u] ? dx : 0;
+      dc[u] = in_a[u] ? 0 : dx;
+      lo[u] = r0;
+      len[u] = (act[u] && A.closure) ? dx : 0;
+      key[u] = in_a[u] ? c[u] : a[u];
       found[u] = false;
     }
     bool more = true;
@@ -204,6 +212,16 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
           }
           more |= len[u] > 0;
         }
+      }
+    }
+    // the other endpoint's degree: for the class of a closed bin sample, and
+    // for every feature record
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (act[u] && (A.feat || (found[u] && !global))) {
+        const uint32_t y = in_a[u] ? c[u] : a[u];
+        const uint64_t dy = rowptr[y + 1] - rowptr[y];
+        if (in_a[u]) dc[u] = dy; else da[u] = dy;
       }
     }
     // 5. class and tallies
@@ -268,7 +286,7 @@ __device__ inline bool header_ok(const SamplerCtx& A) {
 }
 
 template <int U>
-__global__ __launch_bounds__(kSampWG) void k_sample_close(const SamplerCtx A, const TaskTable T) {
+__global__ __launch_bounds__(kSampWG, U == 1 ? 8 : 1) void k_sample_close(const SamplerCtx A, const TaskTable T) {
   __shared__ TileSmem sm;
   const uint64_t tile = blockIdx.x;
   int e = 0;
@@ -291,7 +309,7 @@ __global__ __launch_bounds__(kSampWG) void k_sample_close(const SamplerCtx A, co
 // of rows f (tile_begin[nrows] = total).  Every workgroup leaves the loop
 // once the ticket passes the total.
 template <int U>
-__global__ __launch_bounds__(kSampWG) void k_sample_persistent(const SamplerCtx A,
+__global__ __launch_bounds__(kSampWG, U == 1 ? 8 : 1) void k_sample_persistent(const SamplerCtx A,
                                                                const uint64_t* __restrict__ task_k,
                                                                const uint64_t* __restrict__ tile_begin,
                                                                uint64_t nrows,
@@ -332,16 +350,15 @@ __global__ __launch_bounds__(kSampWG) void k_sample_persistent(const SamplerCtx 
   }
 }
 
+// One sample per lane and one pass per workgroup: the closure search is a
+// chain of dependent loads, and the most waves in flight (the fewest
+// registers per lane) hide it best; measured on R-MAT scale 24 this beats
+// several samples per lane and longer tiles.
 SampleTuning default_tuning(uint64_t total) {
+  (void)total;
   SampleTuning t;
-  t.U = 4;
-  // about 16 tiles per CU of the 256 on the chip, within [1024, 16384]
-  uint64_t spt = total / (256 * 16);
-  const uint64_t unit = (uint64_t)kSampWG * t.U;
-  spt = (spt / unit) * unit;
-  if (spt < unit) spt = unit;
-  if (spt > 16384) spt = 16384;
-  t.spt = spt;
+  t.U = 1;
+  t.spt = (uint64_t)kSampWG;
   t.workgroups = 256 * 8;
   return t;
 }

@@ -391,15 +391,6 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
     return res
 
 
-def _holdout_moments(recs, gv, R, stride, j0, n):
-    """Moments of columns j0 .. j0 + n - 1 of every row (record and g
-    buffers offset by j0 keep the row stride)."""
-    off_r = recs[j0 * 4:]
-    off_g = gv[j0:]
-    m = moments(off_r, off_g, R, stride, n)
-    return W.to_host_u64(m).view(np.int64).reshape(R, 5)
-
-
 @dataclass
 class TrainResult:
     net: Mlp
@@ -412,32 +403,36 @@ class TrainResult:
 
 
 def train(g: W.Csr, bi: W.BinIndex, rows: list[int], n_train: int, seed: int,
-          epochs: int = 2, per_row_batch: int = 256, lr: float = 2e-3, holdout: float = 0.2,
+          epochs: int = 1, per_row_batch: int = 4096, lr: float = 2e-2, holdout: float = 0.2,
           init_seed: int = 7, stream=None) -> TrainResult:
-    """TRAIN draws (exact labels) spread evenly over `rows`, Adam on
-    stratified minibatches, then beta per row from the held-out draws."""
+    """TRAIN draws (exact labels) spread evenly over `rows`: the first
+    columns of every row fit the network (Adam on minibatches that hold every
+    row), the rest are held out for beta, the fitted correlation and the
+    round plans."""
     dev = g.rowptr.device
     B = bi.max_bins
     rows = sorted(rows)
+    R = len(rows)   # records are compact: row j is rows[j]
     t0 = time.perf_counter()
-    per_row = max(n_train // len(rows), 2 * per_row_batch)
-    hk = np.zeros(B + 1, dtype=np.uint64)
-    for r in rows:
-        hk[r] = per_row
-    recs = new_records(len(rows), per_row, dev)
-    sample_features(g, bi, hk, 0, seed, DOMAIN_TRAIN, True, recs, per_row, stream=stream)
+    per_row = max(n_train // R, 2 * per_row_batch)
     n_fit = int(per_row * (1 - holdout)) // per_row_batch * per_row_batch
+    n_hold = per_row - n_fit
+    hk = np.zeros(B + 1, dtype=np.uint64)
+    sb = np.zeros(B + 1, dtype=np.uint64)
+    hk[rows] = n_fit
+    fit = new_records(R, n_fit, dev)
+    sample_features(g, bi, hk, 0, seed, DOMAIN_TRAIN, True, fit, n_fit, stream=stream)
+    hk[rows] = n_hold
+    sb[rows] = n_fit
+    hold = new_records(R, n_hold, dev)
+    sample_features(g, bi, hk, sb, seed, DOMAIN_TRAIN, True, hold, n_hold, stream=stream)
     net = Mlp(dev)
     net.init(init_seed, stream=stream)
-    losses = []
-    R = len(rows)   # records are compact: row j of `recs` is rows[j]
-    net.train(recs, R, per_row, n_fit, per_row_batch, epochs, lr=lr, stream=stream)
-    losses.append(float(net.loss.item()))
-    # beta from the held-out draws (columns n_fit .. per_row of every row)
-    gv = torch.zeros(R * per_row, dtype=torch.float32, device=dev)
-    net.forward(recs, R * per_row, gv, stream=stream)
-    n_hold = per_row - n_fit
-    mom = _holdout_moments(recs, gv, R, per_row, n_fit, n_hold)
+    net.train(fit, R, n_fit, n_fit, per_row_batch, epochs, lr=lr, stream=stream)
+    losses = [float(net.loss.item())]
+    gv = torch.zeros(R * n_hold, dtype=torch.float32, device=dev)
+    net.forward(hold, R * n_hold, gv, stream=stream)
+    mom = W.to_host_u64(moments(hold, gv, R, n_hold, n_hold)).view(np.int64).reshape(R, 5)
     beta = {r: beta_from_moments(mom[i]) for i, r in enumerate(rows)}
     rho2 = {r: rho2_from_moments(mom[i]) for i, r in enumerate(rows)}
     torch.cuda.synchronize()
@@ -460,8 +455,8 @@ def plans(tr: TrainResult, eps: float, delta: float):
 
 
 def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, seed: int = 11,
-            n_train: int = 10_000_000, epochs: int = 2, per_row_batch: int = 4096,
-            lr: float = 4e-3, growth: float = 1.1, aux_form: bool = True) -> dict:
+            n_train: int = 10_000_000, epochs: int = 1, per_row_batch: int = 4096,
+            lr: float = 2e-2, growth: float = 1.1, aux_form: bool = True) -> dict:
     """Samples and wall time to reach a half-width <= eps at confidence
     1 - delta on every sampled bin and on the global stream, for plain
     sampling with the empirical-Bernstein stopping rule and for the learned

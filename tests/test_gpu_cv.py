@@ -248,7 +248,7 @@ def test_cv_unbiased_and_not_worse_than_plain(c1):
     B = bi.max_bins
     P = O.exact(og, 2, 2, B)
     rows = [r for r in range(B) if bi.h_p_b[r] > 0]
-    tr = C.train(g, bi, rows, 200_000, seed=3, epochs=2)
+    tr = C.train(g, bi, rows, 200_000, seed=3, epochs=2, per_row_batch=256, lr=5e-3)
     assert tr.losses[-1] < 0.69
     ests_cv = {r: [] for r in rows}
     ests_pl = {r: [] for r in rows}
@@ -361,7 +361,7 @@ def test_exact_mean_cv_unbiased_and_tighter(c1):
     B = bi.max_bins
     P = O.exact(og, 2, 2, B)
     rows = [r for r in range(B) if bi.h_p_b[r] > 0]
-    tr = C.train(g, bi, rows, 200_000, seed=4, epochs=2)
+    tr = C.train(g, bi, rows, 200_000, seed=4, epochs=2, per_row_batch=256, lr=5e-3)
     means = C.Census(g, bi).means(tr.net)
     ests, pl = {r: [] for r in rows}, {r: [] for r in rows}
     R, n = 24, 1 << 12
