@@ -210,8 +210,11 @@ def main():
         bi = W.BinIndex(n=n, m=int(m), tau=2, omega=2, max_bins=B, n_b=n_b, p_b=p_b,
                         index=index, h_n_b=h_nb.numpy().view(np.uint64).copy(),
                         h_p_b=h_pb.numpy().view(np.uint64).copy())
-        cvcmp = CV.compare(g, bi, eps=args.eps, delta=args.delta, seed=args.seed + 1000,
-                           n_train=args.cv_train)
+        # the first run pays one-time costs (kernel loading, buffer allocation);
+        # the second, identical run is the one reported
+        for _ in range(2):
+            cvcmp = CV.compare(g, bi, eps=args.eps, delta=args.delta, seed=args.seed + 1000,
+                               n_train=args.cv_train)
         cvcmp["plain_hoeffding"] = {"closure_checks": K,
                                     "seconds": avg["sample_close"] / 1000.0}
         log(f"[bench] estimator comparison: plain-Hoeffding {K} checks, plain-EB "
