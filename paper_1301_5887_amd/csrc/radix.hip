@@ -205,9 +205,9 @@ __device__ inline uint32_t os_graph_of_edge(const uint64_t* __restrict__ eoff, u
   return lo;
 }
 
-// Key g of the edge list (see EdgeSource); *bad marks an id out of range.
-__device__ inline uint64_t edge_key(const EdgeSource& E, uint64_t g, bool* bad) {
-  const uint64_t i = g >> 1;
+// The two keys of edge i of the edge list (see EdgeSource): *k0 = u<<32|w,
+// *k1 = w<<32|u; returns true when an id is out of range.
+__device__ inline bool edge_keys(const EdgeSource& E, uint64_t i, uint64_t* k0, uint64_t* k1) {
   uint64_t u = E.src[i], w = E.dst[i];
   uint64_t base = 0, lim = E.n;
   if (E.G > 1) {
@@ -215,14 +215,16 @@ __device__ inline uint64_t edge_key(const EdgeSource& E, uint64_t g, bool* bad) 
     base = E.voff[gg];
     lim = E.voff[gg + 1] - base;
   }
-  *bad = u >= lim || w >= lim;
-  if (*bad) {
+  const bool bad = u >= lim || w >= lim;
+  if (bad) {
     u = w = 0;
   } else {
     u += base;
     w += base;
   }
-  return (g & 1) ? ((w << 32) | u) : ((u << 32) | w);
+  *k0 = (u << 32) | w;
+  *k1 = (w << 32) | u;
+  return bad;
 }
 
 // Counts of every digit of every pass over all keys, and the rejected edges.
@@ -235,10 +237,8 @@ __global__ __launch_bounds__(kOsWG) void k_os_hist_edges(EdgeSource E, OsShifts 
   unsigned long long bad_edges = 0;
   const uint64_t stride = (uint64_t)gridDim.x * kOsWG;
   for (uint64_t i = (uint64_t)blockIdx.x * kOsWG + tid; i < E.m_in; i += stride) {
-    bool bad;
-    const uint64_t k0 = edge_key(E, 2 * i, &bad);
-    const uint64_t k1 = edge_key(E, 2 * i + 1, &bad);
-    bad_edges += bad ? 1 : 0;
+    uint64_t k0, k1;
+    bad_edges += edge_keys(E, i, &k0, &k1) ? 1 : 0;
     for (int p = 0; p < S.npass; ++p) {
       if (S.mirror[p] >= 0) continue;
       atomicAdd(&s_h[p][(k0 >> S.s[p]) & 255], 1u);
@@ -310,14 +310,44 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
   const uint64_t lt_mask = (1ULL << lane) - 1;
   if (kEdges) {
     const uint64_t ebase = tile * (kOsTile / 2);
+    const bool pairs = E.G == 1 && ((((uintptr_t)E.src) | ((uintptr_t)E.dst)) & 7) == 0;
+    if (pairs) {
+      // two consecutive edges per lane and load (8-byte loads of src and dst)
 #pragma unroll
-    for (int it = 0; it < kOsItems / 2; ++it) {
-      const uint64_t e = ebase + (uint64_t)wave * 64 * (kOsItems / 2) + (uint64_t)it * 64 + lane;
-      const bool valid = e < E.m_in;
-      bool bad;
-      key[2 * it] = valid ? edge_key(E, 2 * e, &bad) : 0;
-      key[2 * it + 1] = valid ? edge_key(E, 2 * e + 1, &bad) : 0;
-      ok[2 * it] = ok[2 * it + 1] = valid;
+      for (int it = 0; it < kOsItems / 4; ++it) {
+        const uint64_t e = ebase + (uint64_t)wave * 64 * (kOsItems / 2) + (uint64_t)it * 128 +
+                           2 * (uint64_t)lane;
+        uint2 su = {0, 0}, du = {0, 0};
+        if (e + 1 < E.m_in) {
+          su = *reinterpret_cast<const uint2*>(E.src + e);
+          du = *reinterpret_cast<const uint2*>(E.dst + e);
+        } else if (e < E.m_in) {
+          su.x = E.src[e];
+          du.x = E.dst[e];
+        }
+        const uint32_t us[2] = {su.x, su.y}, ws[2] = {du.x, du.y};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bool valid = e + h < E.m_in;
+          uint64_t u = us[h], w = ws[h];
+          if (u >= E.n || w >= E.n) u = w = 0;  // counted by the histogram pass
+          key[4 * it + 2 * h] = valid ? ((u << 32) | w) : 0;
+          key[4 * it + 2 * h + 1] = valid ? ((w << 32) | u) : 0;
+          ok[4 * it + 2 * h] = ok[4 * it + 2 * h + 1] = valid;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < kOsItems / 2; ++it) {
+        const uint64_t e =
+            ebase + (uint64_t)wave * 64 * (kOsItems / 2) + (uint64_t)it * 64 + lane;
+        const bool valid = e < E.m_in;
+        uint64_t k0 = 0, k1 = 0;
+        if (valid) edge_keys(E, e, &k0, &k1);
+        key[2 * it] = k0;
+        key[2 * it + 1] = k1;
+        ok[2 * it] = ok[2 * it + 1] = valid;
+      }
     }
   } else {
 #pragma unroll

@@ -469,13 +469,18 @@ def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, se
     torch.cuda.synchronize()
     tr = train(g, bi, rows, n_train, seed, epochs=epochs, per_row_batch=per_row_batch, lr=lr)
     plan_plain, plan_cv = plans(tr, eps, delta)
+    # rows where the held-out draws predict fewer samples without the control
+    # variate (small rho^2: the wider range 1 + |beta| of the bound costs more
+    # than the variance it removes) keep beta = 0, i.e. plain sampling
+    beta_used = {r: (tr.beta[r] if plan_cv[r] < plan_plain[r] else 0.0) for r in rows}
+    plan_used = {r: min(plan_cv[r], plan_plain[r]) for r in rows}
     pe = sequential(g, bi, rows, eps, delta, seed, None, None, first=plan_plain, growth=growth)
     t0 = time.perf_counter()
     census = Census(g, bi)
     means = census.means(tr.net)
     torch.cuda.synchronize()
     t_census = time.perf_counter() - t0
-    cvx = sequential(g, bi, rows, eps, delta, seed, tr.net, tr.beta, first=plan_cv,
+    cvx = sequential(g, bi, rows, eps, delta, seed, tr.net, beta_used, first=plan_used,
                      growth=growth, exact_means=means)
     cvr = None
     if aux_form:
@@ -484,7 +489,8 @@ def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, se
     per_row = {}
     for r in rows:
         name = "global" if r == B else str(r)
-        row = {"beta": round(tr.beta[r], 5), "rho2": round(tr.rho2[r], 5),
+        row = {"beta": round(tr.beta[r], 5), "beta_used": round(beta_used[r], 5),
+               "rho2": round(tr.rho2[r], 5),
                "plan_plain": plan_plain[r], "plan_cv": plan_cv[r],
                "plain_eb_samples": pe.eval_samples[r],
                "cv_exact_eval_samples": cvx.eval_samples[r],
