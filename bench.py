@@ -78,10 +78,11 @@ def main():
                          "this bench (FETCH_SIZE, WRITE_SIZE, each with --calibrate-copy-gib)")
     ap.add_argument("--pmc-k", type=int, default=0, help="closure checks of the profiled run")
     ap.add_argument("--pmc-copy-gib", type=float, default=1.0)
+    ap.add_argument("--pmc-out", default=None, help="summary file (default: the scale-24 one)")
     args = ap.parse_args()
     if args.pmc_summarize:
         pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], args.pmc_k,
-                      args.pmc_copy_gib)
+                      args.pmc_copy_gib, args.pmc_out or PMC_FILE)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -269,7 +270,8 @@ def _pmc_rows(d: str, counter: str):
     return rows
 
 
-def pmc_summarize(fetch_dir: str, write_dir: str, workload_k: int, copy_gib: float):
+def pmc_summarize(fetch_dir: str, write_dir: str, workload_k: int, copy_gib: float,
+                  out_path: str):
     """Per-launch HBM bytes of the sampler from FETCH_SIZE and WRITE_SIZE (KiB
     per dispatch), each scaled by the ratio of the known size of the
     calibration copy to what the same counter read for it."""
@@ -290,7 +292,7 @@ def pmc_summarize(fetch_dir: str, write_dir: str, workload_k: int, copy_gib: flo
                              "bytes_per_launch": per_launch}
         total += per_launch
     out["hbm_bytes_per_launch"] = total
-    with open(PMC_FILE, "w") as f:
+    with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
 
