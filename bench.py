@@ -218,11 +218,11 @@ def main():
                                n_train=args.cv_train)
         cvcmp["plain_hoeffding"] = {"closure_checks": K,
                                     "seconds": avg["sample_close"] / 1000.0}
+        lc = cvcmp["learned_cv_centre"]
         log(f"[bench] estimator comparison: plain-Hoeffding {K} checks, plain-EB "
-            f"{cvcmp['plain_eb']['closure_checks']}, learned-CV "
-            f"{cvcmp['learned_cv_exact_mean']['closure_checks']} "
-            f"(eval {cvcmp['learned_cv_exact_mean']['eval_checks']}, "
-            f"{cvcmp['learned_cv_exact_mean']['seconds']:.4f} s)")
+            f"{cvcmp['plain_eb']['closure_checks']}, learned-CV with centre draws "
+            f"{lc['closure_checks']} (eval {lc['eval_checks']}, centre draws "
+            f"{lc['centre_draws']}, {lc['seconds']:.4f} s)")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -350,7 +350,7 @@ typedef struct {
 
 /* Philox key domains of the streams (key word 1). */
 enum { WEDGE_DOMAIN_SAMPLE = 1, WEDGE_DOMAIN_TRAIN = 2, WEDGE_DOMAIN_AUX = 3,
-       WEDGE_DOMAIN_EVAL = 4 };
+       WEDGE_DOMAIN_EVAL = 4, WEDGE_DOMAIN_CENTRE = 6 };
 
 /* The sampler of wedge_sample_close with key (seed, domain), samples
  * s = s_begin[r] .. s_begin[r] + h_k[r] - 1 of every row r (bins r < max_bins
@@ -411,7 +411,8 @@ int wedge_mlp_train(void* d_state, const wedge_feature_rec* d_x, uint32_t rows, 
 /* Moments of the control variate over records d_x (rows x stride, the first
  * n_per_row of each row used, or the first h_counts[r] of row r when the host
  * array h_counts is given) with network outputs d_g (same layout), added
- * into d_mom[rows][5] (int64, caller zeroes):
+ * into d_mom[rows][5] (int64, caller zeroes); d_x may be null (X = 0, for
+ * values without a closure label such as centre means):
  *   [0] count, [1] sum X, [2] round(2^32 sum g), [3] round(2^32 sum g^2),
  *   [4] round(2^32 sum X g)
  * with every term rounded to 2^-32 before summing, so sums are exact and
@@ -450,6 +451,36 @@ size_t wedge_cv_exact_mean_workspace(uint32_t max_bins);
 int wedge_cv_exact_mean(const void* d_state, const void* d_census, uint32_t max_bins,
                         double* d_key_sum, uint64_t* d_key_count, void* d_workspace,
                         size_t workspace_bytes, void* stream);
+
+/* Key list only (no census counts): fills the (bin, bucket) keys of a buffer
+ * of wedge_cv_census_bytes(n, m, max_bins) bytes, as wedge_cv_census does. */
+int wedge_cv_keys(void* d_census, uint32_t max_bins, uint32_t tau, uint64_t omega, void* stream);
+/* The network's g for every present key and every bucket pair (i <= j):
+ * d_gtable[key * 32896 + j (j + 1) / 2 + i] (FP32, room for 256 + max_bins + 1
+ * keys).  Reads the key count from the device first (synchronises the
+ * stream).  Workspace: wedge_cv_gtable_workspace(max_bins) bytes. */
+size_t wedge_cv_gtable_workspace(uint32_t max_bins);
+int wedge_cv_gtable(const void* d_state, const void* d_census, uint32_t max_bins, float* d_gtable,
+                    void* d_workspace, size_t workspace_bytes, void* stream);
+/* Centre draws for the control variate's mean: draw s of row r (s =
+ * s_begin[r] .. s_begin[r] + h_k[r] - 1, key (seed, domain)) picks a centre v
+ * with probability p_v / p_r exactly as the sampler picks a wedge's centre
+ * (Sec. 3.2), and d_out gets the mean of g over all C(d_v, 2) wedges at v,
+ *   gbar(v) = (1 / C(d_v, 2)) sum over neighbour pairs of g(key(v), K(d_lo), K(d_hi)),
+ * from the table of wedge_cv_gtable; E[gbar(v)] is the mean of g over the
+ * row's wedges.  Rows with h_k[r] > 0, in increasing r, fill output rows
+ * j = 0, 1, ...: draw s of the j-th such row goes to d_out[j * out_stride +
+ * (s - s_begin[r])], and its centre id to d_vout (nullable) at the same place.
+ * d_census holds the key list (wedge_cv_keys or wedge_cv_census).  Workspace:
+ * wedge_cv_centre_means_workspace(sum of h_k) bytes. */
+size_t wedge_cv_centre_means_workspace(uint64_t total_draws);
+int wedge_cv_centre_means(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
+                          const void* d_index, uint32_t max_bins, uint32_t tau, uint64_t omega,
+                          const uint64_t* h_k, const uint64_t* h_s_begin, uint64_t seed,
+                          uint32_t domain, uint32_t graph_id, const void* d_census,
+                          const float* d_gtable, float* d_out, uint64_t out_stride,
+                          uint32_t* d_vout, void* d_workspace, size_t workspace_bytes,
+                          void* stream);
 
 /* Empirical-Bernstein half-width (Maurer & Pontil 2009, Thm. 4, two-sided,
  * each side at delta/2) of the mean of n i.i.d. values in an interval of

@@ -564,6 +564,55 @@ extern "C" int wedge_cv_census_keys(const void* d_census, uint32_t max_bins, uin
   return WEDGE_OK;
 }
 
+namespace wedge {
+const uint32_t* census_key_of(const void* d_census, uint32_t max_bins) {
+  CensusView C;
+  census_layout(max_bins, 0, 0, &C, const_cast<void*>(d_census));
+  return C.key_of;
+}
+}  // namespace wedge
+
+extern "C" int wedge_cv_keys(void* d_census, uint32_t max_bins, uint32_t tau, uint64_t omega,
+                             void* stream) {
+  clear_error();
+  if (!d_census || !aligned(d_census, 256))
+    return set_error(WEDGE_EINVAL, "wedge_cv_keys: null or misaligned buffer");
+  if (max_bins == 0 || max_bins > 4096 || tau == 0 || omega < 2)
+    return set_error(WEDGE_ERANGE, "wedge_cv_keys: bad max_bins, tau or omega");
+  CensusView C;
+  census_layout(max_bins, 0, 0, &C, d_census);
+  k_census_keys<<<1, 256, 0, (hipStream_t)stream>>>(C, tau, omega, max_bins);
+  WEDGE_LAUNCH_CHECK("k_census_keys");
+  return WEDGE_OK;
+}
+
+extern "C" size_t wedge_cv_gtable_workspace(uint32_t max_bins) {
+  return round_up((uint64_t)census_cap(max_bins) * kPairs * sizeof(wedge_feature_rec), 256);
+}
+
+extern "C" int wedge_cv_gtable(const void* d_state, const void* d_census, uint32_t max_bins,
+                               float* d_gtable, void* d_workspace, size_t workspace_bytes,
+                               void* stream) {
+  clear_error();
+  if (!d_state || !d_census || !d_gtable || !d_workspace)
+    return set_error(WEDGE_EINVAL, "wedge_cv_gtable: null pointer");
+  if (workspace_bytes < wedge_cv_gtable_workspace(max_bins))
+    return set_error(WEDGE_EWORKSPACE, "wedge_cv_gtable: workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  CensusView C;
+  census_layout(max_bins, 0, 0, &C, const_cast<void*>(d_census));
+  uint32_t nk = 0;
+  WEDGE_HIP_TRY(hipMemcpyAsync(&nk, C.nkeys, 4, hipMemcpyDeviceToHost, st));
+  WEDGE_HIP_TRY(hipStreamSynchronize(st));
+  if (nk > C.cap) nk = C.cap;
+  const uint64_t recs = (uint64_t)nk * kPairs;
+  if (recs == 0) return WEDGE_OK;
+  wedge_feature_rec* rec = (wedge_feature_rec*)d_workspace;
+  k_census_records<<<(unsigned)ceil_div(recs, 256), 256, 0, st>>>(C, rec);
+  WEDGE_LAUNCH_CHECK("k_census_records");
+  return mlp_forward_impl(d_state, rec, recs, d_gtable, st);
+}
+
 extern "C" size_t wedge_cv_exact_mean_workspace(uint32_t max_bins) {
   const uint64_t recs = (uint64_t)census_cap(max_bins) * kPairs;
   return round_up(recs * sizeof(wedge_feature_rec), 256) + round_up(recs * 4, 256);

@@ -134,4 +134,8 @@ __host__ __device__ inline uint64_t bin_lo_deg(uint32_t b, uint32_t tau, uint64_
   return lo;
 }
 
+// Key id of every (bin, centre bucket) in a census buffer ([max_bins][256]
+// uint32, 0xFFFFFFFF where degrees >= 2 cannot take the pair).
+const uint32_t* census_key_of(const void* d_census, uint32_t max_bins);
+
 }  // namespace wedge

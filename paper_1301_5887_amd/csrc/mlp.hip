@@ -564,7 +564,7 @@ __global__ __launch_bounds__(256) void k_cv_moments(const wedge_feature_rec* __r
     const double gv = (double)g[at];
     const long long gq = llrint(gv * 4294967296.0);
     const long long g2q = llrint(gv * gv * 4294967296.0);
-    const int X = x[at].closed ? 1 : 0;
+    const int X = (x && x[at].closed) ? 1 : 0;
     c += 1;
     sx += X;
     sg += gq;
@@ -759,7 +759,7 @@ extern "C" int wedge_cv_moments(const wedge_feature_rec* d_x, const float* d_g, 
                                 int64_t* d_mom, void* stream) {
   clear_error();
   if (rows == 0) return WEDGE_OK;
-  if (!d_x || !d_g || !d_mom) return set_error(WEDGE_EINVAL, "wedge_cv_moments: null pointer");
+  if (!d_g || !d_mom) return set_error(WEDGE_EINVAL, "wedge_cv_moments: null pointer");
   uint64_t most = 0;
   for (uint32_t r = 0; r < rows; ++r) {
     const uint64_t c = h_counts ? h_counts[r] : n_per_row;

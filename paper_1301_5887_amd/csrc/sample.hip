@@ -54,6 +54,61 @@ __device__ inline uint32_t bin_of_degree(uint64_t d, uint32_t tau, uint64_t omeg
   return b;
 }
 
+// The row's cumulative-wedge table in LDS: one entry per class, or the last
+// class of every group of S when the row has more classes than LDS holds.
+struct StagedRow {
+  uint32_t S, ngroups, ncls;
+};
+
+__device__ inline StagedRow stage_row(const SamplerCtx& A, TileSmem& sm, const BinMeta& M) {
+  StagedRow R;
+  R.ncls = M.cls_hi - M.cls_lo;
+  R.S = (R.ncls + kLdsClasses - 1) / kLdsClasses;  // classes per staged group
+  R.ngroups = (R.ncls + R.S - 1) / R.S;
+  for (uint32_t i = threadIdx.x; i < R.ngroups; i += kSampWG) {
+    const uint32_t last = min((i + 1) * R.S, R.ncls) - 1;
+    sm.cumw[i] = A.ix.cls_cumw[M.cls_lo + last];
+    if (R.S == 1) {
+      sm.deg[i] = A.ix.cls_deg[M.cls_lo + i];
+      sm.start[i] = A.ix.cls_start[M.cls_lo + i];
+    }
+  }
+  return R;
+}
+
+// Centre of wedge index W of the row: the first staged group whose
+// cumulative count exceeds W, then (when groups hold several classes) the
+// class inside; the centre is the (W - wedges before the class) / C(d, 2)-th
+// vertex of the class.
+__device__ inline void centre_of(const SamplerCtx& A, const TileSmem& sm, const BinMeta& M,
+                                 const StagedRow& R, uint64_t W, uint64_t* d, uint64_t* vi) {
+  uint32_t l = 0, h = R.ngroups;
+  while (l < h) {
+    const uint32_t mid = (l + h) >> 1;
+    if (sm.cumw[mid] > W) h = mid; else l = mid + 1;
+  }
+  uint64_t dd, st, cprev;
+  if (R.S == 1) {
+    dd = sm.deg[l];
+    st = sm.start[l];
+    cprev = l > 0 ? sm.cumw[l - 1] : M.cumw_base;
+  } else {
+    uint32_t jl = l * R.S, jh = min((l + 1) * R.S, R.ncls);
+    while (jl < jh) {
+      const uint32_t mid = (jl + jh) >> 1;
+      if (A.ix.cls_cumw[M.cls_lo + mid] > W) jh = mid; else jl = mid + 1;
+    }
+    const uint64_t j = (uint64_t)M.cls_lo + jl;
+    dd = A.ix.cls_deg[j];
+    st = A.ix.cls_start[j];
+    cprev = j > 0 ? A.ix.cls_cumw[j - 1] : 0;
+  }
+  *d = dd;
+  uint64_t v = st + (W - cprev) / (dd * (dd - 1) / 2);
+  if (v >= A.n) v = A.n - 1;  // unreachable for a consistent index
+  *vi = v;
+}
+
 // One tile: samples [s0, s1) of index row f (graph g, bin word bword).
 template <int U>
 __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint32_t bword,
@@ -67,17 +122,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
     return;
   }
   const bool global = (bword == kGlobalWord);
-  const uint32_t ncls = M.cls_hi - M.cls_lo;
-  const uint32_t S = (ncls + kLdsClasses - 1) / kLdsClasses;  // classes per staged group
-  const uint32_t ngroups = (ncls + S - 1) / S;
-  for (uint32_t i = tid; i < ngroups; i += kSampWG) {
-    const uint32_t last = min((i + 1) * S, ncls) - 1;
-    sm.cumw[i] = A.ix.cls_cumw[M.cls_lo + last];
-    if (S == 1) {
-      sm.deg[i] = A.ix.cls_deg[M.cls_lo + i];
-      sm.start[i] = A.ix.cls_start[M.cls_lo + i];
-    }
-  }
+  const StagedRow R = stage_row(A, sm, M);
   if (tid < 5) sm.red[tid] = 0;
   __syncthreads();
 
@@ -106,35 +151,13 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
         x1[u] = o.w[1];
       }
     }
-    // 2. class of the centre: first staged group whose cumulative count
-    //    exceeds W, then (when groups hold several classes) the class inside
+    // 2. the centre: class by the staged table, then the vertex
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      uint32_t l = 0, h = ngroups;
-      while (l < h) {
-        const uint32_t mid = (l + h) >> 1;
-        if (sm.cumw[mid] > W[u]) h = mid; else l = mid + 1;
-      }
-      uint64_t dd, st, cprev;
-      if (S == 1) {
-        dd = sm.deg[l];
-        st = sm.start[l];
-        cprev = l > 0 ? sm.cumw[l - 1] : M.cumw_base;
-      } else {
-        uint32_t jl = l * S, jh = min((l + 1) * S, ncls);
-        while (jl < jh) {
-          const uint32_t mid = (jl + jh) >> 1;
-          if (A.ix.cls_cumw[M.cls_lo + mid] > W[u]) jh = mid; else jl = mid + 1;
-        }
-        const uint64_t j = (uint64_t)M.cls_lo + jl;
-        dd = A.ix.cls_deg[j];
-        st = A.ix.cls_start[j];
-        cprev = j > 0 ? A.ix.cls_cumw[j - 1] : 0;
-      }
-      d[u] = act[u] ? dd : 2;
-      const uint64_t pv = d[u] * (d[u] - 1) / 2;
-      vi[u] = st + (W[u] - cprev) / pv;
-      if (vi[u] >= A.n) vi[u] = A.n - 1;  // unreachable for a consistent index
+      uint64_t dd = 2, vv = 0;
+      if (act[u]) centre_of(A, sm, M, R, W[u], &dd, &vv);
+      d[u] = dd;
+      vi[u] = vv;
     }
     // the centre's adjacency start comes straight from the index; its id is
     // only needed for a dump
@@ -189,27 +212,61 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       key[u] = in_a[u] ? c[u] : a[u];
       found[u] = false;
     }
+    // Search [lo, lo + len) for key.  Ids are spread over [0, n) and a row
+    // holds them in ascending order, so in a long row of a single graph the
+    // first probe goes where the key's share of the id range points and the
+    // second a few standard deviations further, which leaves a short interval
+    // (one or two cache lines) for the bisection; a bad guess only costs the
+    // two probes.  Stage 0: interpolated probe; 1: window edge; 2: midpoints.
+    const float inv_n = 1.0f / (float)A.n;  // the guess needs no precision
+    uint32_t stage[U];
+    uint64_t win[U];
+    bool right[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool interp = A.num_graphs == 1 && len[u] > 64;
+      stage[u] = interp ? 0 : 2;
+      win[u] = interp ? 2 * (uint64_t)__fsqrt_rn((float)len[u]) + 8 : 0;
+      right[u] = true;
+    }
     bool more = true;
     while (more) {
       uint32_t x[U];
+      uint64_t h[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (len[u] > 0) x[u] = col[lo[u] + (len[u] >> 1)];
+      for (int u = 0; u < U; ++u) {
+        if (len[u] == 0) continue;
+        if (stage[u] == 0) {
+          h[u] = (uint64_t)((float)len[u] * ((float)key[u] * inv_n));
+        } else if (stage[u] == 1) {
+          // the key is just past the guess: the window edge on that side
+          if (right[u])
+            h[u] = win[u] < len[u] ? win[u] : len[u] - 1;
+          else
+            h[u] = len[u] > win[u] ? len[u] - 1 - win[u] : 0;
+        } else {
+          h[u] = len[u] >> 1;
+        }
+        if (h[u] >= len[u]) h[u] = len[u] - 1;
+        x[u] = col[lo[u] + h[u]];
+      }
       more = false;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (len[u] > 0) {
           ++probes;
-          const uint64_t h = len[u] >> 1;
           if (x[u] == key[u]) {
             found[u] = true;
             len[u] = 0;
           } else if (x[u] < key[u]) {
-            lo[u] += h + 1;
-            len[u] -= h + 1;
+            lo[u] += h[u] + 1;
+            len[u] -= h[u] + 1;
+            right[u] = true;
           } else {
-            len[u] = h;
+            len[u] = h[u];
+            right[u] = false;
           }
+          stage[u] = stage[u] < 2 ? stage[u] + 1 : 2;
           more |= len[u] > 0;
         }
       }
@@ -354,6 +411,166 @@ __global__ __launch_bounds__(kSampWG, U == 1 ? 8 : 1) void k_sample_persistent(c
 // chain of dependent loads, and the most waves in flight (the fewest
 // registers per lane) hide it best; measured on R-MAT scale 24 this beats
 // several samples per lane and longer tiles.
+// ------------------------------------------------------------ centre means
+// Mean of the control-variate network over all wedges of a drawn centre:
+// centre v is drawn with probability p_v / p_row exactly as a sample's
+// centre (word 0 of the draw's Philox block), and
+//   gbar(v) = (1 / C(d_v, 2)) sum over neighbour pairs {a, c} of
+//             G[key(v)][K(d_lo), K(d_hi)],
+// with G the network's output for every (key, bucket pair) and K(d) the
+// degree bucket (the index keeps it per vertex).  E[gbar(v)] is the mean of
+// g over the row's wedges, so these draws estimate the control variate's
+// mean without any closure test.  Centres up to kCentreLaneDeg neighbours
+// are done by one lane each; larger ones are queued for a wave each.
+constexpr uint32_t kCentreLaneDeg = 32;
+constexpr uint32_t kCentrePairs = 256 * 257 / 2;
+
+struct CentreArgs {
+  const uint32_t* key_of;     // [max_bins][256] key of (bin, centre bucket)
+  const float* gtable;        // [keys][kCentrePairs]
+  float* out;                 // [rows][stride]
+  uint32_t* vout;             // nullable: the drawn centre ids, same layout
+  uint64_t stride;
+  unsigned long long* queued; // [1] entries in `queue`
+  uint64_t* queue;            // [capacity][3]: out index, row start, d << 32 | key
+  uint64_t capacity;
+};
+
+__device__ inline uint32_t pair_at(uint32_t i, uint32_t j) {  // i <= j
+  return j * (j + 1) / 2 + i;
+}
+
+template <int Dummy>
+__global__ __launch_bounds__(kSampWG) void k_centre_means(const SamplerCtx A, const TaskTable T,
+                                                          const CentreArgs C) {
+  __shared__ TileSmem sm;
+  __shared__ uint8_t s_b[kCentreLaneDeg][kSampWG];
+  const int tid = threadIdx.x;
+  const uint64_t tile = blockIdx.x;
+  int e = 0;
+  for (int i = 1; i < (int)T.ntask; ++i)
+    if (T.task[i].tile_begin <= tile) e = i;
+  const uint64_t sbase = T.task[e].s_begin;
+  const uint64_t s0 = sbase + (tile - T.task[e].tile_begin) * A.spt;
+  const uint64_t s1 = min(s0 + A.spt, sbase + T.task[e].k);
+  if (s0 >= s1) return;
+  if (!header_ok(A)) {
+    if (tid == 0) atomicAdd((unsigned long long*)&A.ix.hdr->mismatch, 1ULL);
+    return;
+  }
+  const uint32_t f = T.task[e].row;
+  const uint64_t bw = T.task[e].bword;
+  const BinMeta M = A.ix.bins[f];
+  if (M.p_b == 0) {
+    if (tid == 0) atomicAdd((unsigned long long*)&A.ix.hdr->empty_bin_samples, s1 - s0);
+    return;
+  }
+  const StagedRow R = stage_row(A, sm, M);
+  __syncthreads();
+  for (uint64_t s = s0 + tid; s < s1; s += kSampWG) {
+    const U64x4 o = philox4x64_10(s, bw, T.graph_word, 0, A.seed, A.domain);
+    const uint64_t W =
+        M.cumw_base + below_from(o.w[0], M.p_b, A.seed, A.domain, s, bw, T.graph_word, 0);
+    uint64_t d, vi;
+    centre_of(A, sm, M, R, W, &d, &vi);
+    const uint64_t rp = A.ix.vrow[vi];
+    const uint64_t idx = T.task[e].slot * C.stride + (s - sbase);
+    if (C.vout) C.vout[idx] = A.ix.vlist[vi];
+    const uint32_t bin = bw == kGlobalWord ? bin_of_degree(d, A.tau, A.omega, A.max_bins) : f;
+    const uint32_t ke = 63 - (uint32_t)__builtin_clzll(d);
+    const uint32_t kb = 8 * ke + (uint32_t)(((d - (1ULL << ke)) * 8) >> ke);
+    const uint32_t key = bin < A.max_bins ? C.key_of[bin * 256 + (kb < 255 ? kb : 255)]
+                                          : 0xFFFFFFFFu;
+    if (key == 0xFFFFFFFFu) {  // unreachable for a consistent index and key list
+      C.out[idx] = 0.f;
+    } else if (d <= kCentreLaneDeg) {
+      for (uint32_t x = 0; x < d; ++x) s_b[x][tid] = A.ix.vcode[A.col[rp + x]];
+      const float* G = C.gtable + (uint64_t)key * kCentrePairs;
+      double acc = 0.0;
+      for (uint32_t x = 1; x < d; ++x) {
+        const uint32_t bx = s_b[x][tid];
+        for (uint32_t y = 0; y < x; ++y) {
+          const uint32_t by = s_b[y][tid];
+          acc += (double)G[bx < by ? pair_at(bx, by) : pair_at(by, bx)];
+        }
+      }
+      C.out[idx] = (float)(acc / (double)(d * (d - 1) / 2));
+    } else {
+      const uint64_t at = atomicAdd(C.queued, 1ULL);
+      if (at < C.capacity) {
+        C.queue[3 * at + 0] = idx;
+        C.queue[3 * at + 1] = rp;
+        C.queue[3 * at + 2] = (d << 32) | key;
+      }
+    }
+  }
+}
+
+// Queued centres, one wave each: bucket histogram of the neighbours, then
+// every pair of non-empty buckets with its count.
+__global__ __launch_bounds__(256) void k_centre_wide(const SamplerCtx A, const CentreArgs C) {
+  __shared__ uint32_t s_h[4][256];
+  __shared__ uint16_t s_list[4][256];
+  __shared__ uint32_t s_cnt[4][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t total = min((uint64_t)*C.queued, C.capacity);
+  const uint64_t nwaves = (uint64_t)gridDim.x * 4;
+  for (int i = lane; i < 256; i += 64) s_h[wave][i] = 0;
+  __builtin_amdgcn_wave_barrier();
+  for (uint64_t q = (uint64_t)blockIdx.x * 4 + wave; q < total; q += nwaves) {
+    const uint64_t idx = C.queue[3 * q + 0];
+    const uint64_t rp = C.queue[3 * q + 1];
+    const uint64_t dk = C.queue[3 * q + 2];
+    const uint64_t d = dk >> 32;
+    const uint32_t key = (uint32_t)dk;
+    for (uint64_t x = lane; x < d; x += 64) atomicAdd(&s_h[wave][A.ix.vcode[A.col[rp + x]]], 1u);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint32_t h[4], nz = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      h[t] = s_h[wave][lane * 4 + t];
+      nz += h[t] > 0;
+    }
+    uint32_t pre = nz;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(pre, off, 64);
+      if (lane >= off) pre += y;
+    }
+    const uint32_t u = __shfl(pre, 63, 64);
+    uint32_t at = pre - nz;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (h[t] > 0) {
+        s_list[wave][at] = (uint16_t)(lane * 4 + t);
+        s_cnt[wave][at] = h[t];
+        ++at;
+      }
+      s_h[wave][lane * 4 + t] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const float* G = C.gtable + (uint64_t)key * kCentrePairs;
+    double acc = 0.0;
+    const uint32_t np = u * (u + 1) / 2;
+    for (uint32_t t = lane; t < np; t += 64) {
+      uint32_t j = (uint32_t)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+      while (j * (j + 1) / 2 > t) --j;
+      while ((j + 1) * (j + 2) / 2 <= t) ++j;
+      const uint32_t i = t - j * (j + 1) / 2;
+      const uint64_t hi = s_cnt[wave][i], hj = s_cnt[wave][j];
+      const uint64_t cnt = (i == j) ? hi * (hi - 1) / 2 : hi * hj;
+      if (cnt) acc += (double)cnt * (double)G[pair_at(s_list[wave][i], s_list[wave][j])];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) C.out[idx] = (float)(acc / (double)(d * (d - 1) / 2));
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 SampleTuning default_tuning(uint64_t total) {
   (void)total;
   SampleTuning t;
@@ -477,6 +694,20 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
   return WEDGE_OK;
 }
 
+static int launch_centre_tasks(const SamplerCtx& A, TaskTable& T, const CentreArgs& C,
+                               hipStream_t st) {
+  uint64_t tiles = 0;
+  for (uint32_t i = 0; i < T.ntask; ++i) {
+    T.task[i].tile_begin = tiles;
+    tiles += ceil_div(T.task[i].k, A.spt);
+  }
+  if (tiles == 0) return WEDGE_OK;
+  if (tiles > 0x7FFFFFFFULL) return set_error(WEDGE_ERANGE, "centre means: too many tiles");
+  k_centre_means<0><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T, C);
+  WEDGE_LAUNCH_CHECK("k_centre_means");
+  return WEDGE_OK;
+}
+
 }  // namespace wedge
 
 using namespace wedge;
@@ -578,5 +809,95 @@ extern "C" int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d
     }
   }
   if (T.ntask > 0 && (rc = launch_tasks(A, T, t.U, st))) return rc;
+  return WEDGE_OK;
+}
+
+extern "C" size_t wedge_cv_centre_means_workspace(uint64_t total_draws) {
+  return 256 + round_up(total_draws * 24, 256);
+}
+
+extern "C" int wedge_cv_centre_means(const uint64_t* d_rowptr, const uint32_t* d_col,
+                                     uint32_t n, uint64_t m, const void* d_index,
+                                     uint32_t max_bins, uint32_t tau, uint64_t omega,
+                                     const uint64_t* h_k, const uint64_t* h_s_begin,
+                                     uint64_t seed, uint32_t domain, uint32_t graph_id,
+                                     const void* d_census, const float* d_gtable, float* d_out,
+                                     uint64_t out_stride, uint32_t* d_vout, void* d_workspace,
+                                     size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (n == 0) return set_error(WEDGE_ERANGE, "wedge_cv_centre_means: n must be >= 1");
+  if (max_bins == 0 || max_bins > 4096 || tau == 0 || omega < 2)
+    return set_error(WEDGE_ERANGE, "wedge_cv_centre_means: bad max_bins, tau or omega");
+  if (!d_rowptr || !d_index || !h_k || !d_census || !d_gtable || !d_out || !d_workspace)
+    return set_error(WEDGE_EINVAL, "wedge_cv_centre_means: null pointer");
+  if (!aligned(d_rowptr, 8) || !aligned(d_index, 256) || !aligned(d_census, 256) ||
+      !aligned(d_workspace, 256) || !aligned(d_out, 4))
+    return set_error(WEDGE_EINVAL, "wedge_cv_centre_means: misaligned pointer");
+  uint64_t total = 0;
+  for (uint32_t r = 0; r <= max_bins; ++r) {
+    if (h_k[r] > out_stride)
+      return set_error(WEDGE_ERANGE, "wedge_cv_centre_means: k[%u] > out_stride", r);
+    if (h_s_begin && h_s_begin[r] + h_k[r] > (1ULL << 48))
+      return set_error(WEDGE_ERANGE, "wedge_cv_centre_means: s_begin[%u] + k beyond 2^48", r);
+    total += h_k[r];
+  }
+  if (total == 0) return WEDGE_OK;
+  if (m == 0 || !d_col)
+    return set_error(WEDGE_EINVAL, "wedge_cv_centre_means: draws of a graph without edges");
+  if (workspace_bytes < wedge_cv_centre_means_workspace(total))
+    return set_error(WEDGE_EWORKSPACE, "wedge_cv_centre_means: workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  CentreArgs C;
+  C.key_of = census_key_of(d_census, max_bins);
+  C.gtable = d_gtable;
+  C.out = d_out;
+  C.vout = d_vout;
+  C.stride = out_stride;
+  C.queued = (unsigned long long*)d_workspace;
+  C.queue = (uint64_t*)((char*)d_workspace + 256);
+  C.capacity = total;
+  int rc = fill<unsigned long long>(C.queued, 1, 0, st);
+  if (rc) return rc;
+  SamplerCtx A;
+  A.rowptr = d_rowptr;
+  A.col = d_col;
+  A.ix = index_view(const_cast<void*>(d_index), n, m, 1, max_bins);
+  A.seed = seed;
+  A.spt = (uint64_t)kSampWG;
+  A.dump_per_bin = 0;
+  A.q = nullptr;
+  A.probe_loads = nullptr;
+  A.dump = nullptr;
+  A.class_cap = class_capacity(n, m, 1);
+  A.n = n;
+  A.max_bins = max_bins;
+  A.num_graphs = 1;
+  A.domain = domain;
+  A.s_begin = 0;
+  A.feat = nullptr;
+  A.feat_stride = 0;
+  A.omega = omega;
+  A.tau = tau;
+  A.closure = 0;
+  TaskTable T;
+  T.graph_word = graph_id;
+  T.ntask = 0;
+  uint64_t slot = 0;
+  for (uint32_t b = 0; b <= max_bins; ++b) {
+    if (h_k[b] == 0) continue;
+    Task& K = T.task[T.ntask++];
+    K.row = b;
+    K.bword = (b == max_bins) ? kGlobalWord : b;
+    K.k = h_k[b];
+    K.s_begin = h_s_begin ? h_s_begin[b] : 0;
+    K.slot = slot++;
+    if (T.ntask == kMaxTasks) {
+      if ((rc = launch_centre_tasks(A, T, C, st))) return rc;
+      T.ntask = 0;
+    }
+  }
+  if (T.ntask > 0 && (rc = launch_centre_tasks(A, T, C, st))) return rc;
+  k_centre_wide<<<1024, 256, 0, st>>>(A, C);
+  WEDGE_LAUNCH_CHECK("k_centre_wide");
   return WEDGE_OK;
 }

@@ -34,7 +34,7 @@ FEATURE_DTYPE = np.dtype([("dv", "<u4"), ("dlo", "<u4"), ("dhi", "<u4"), ("bin",
                           ("closed", "u1"), ("cls", "u1")])
 NPARAM = 4545
 Q32 = float(1 << 32)
-DOMAIN_SAMPLE, DOMAIN_TRAIN, DOMAIN_AUX, DOMAIN_EVAL = 1, 2, 3, 4
+DOMAIN_SAMPLE, DOMAIN_TRAIN, DOMAIN_AUX, DOMAIN_EVAL, DOMAIN_CENTRE = 1, 2, 3, 4, 6
 
 
 def _L():
@@ -128,9 +128,9 @@ def moments(rec: torch.Tensor, gv: torch.Tensor, rows: int, stride: int, per_row
             out: torch.Tensor | None = None, counts=None, stream=None) -> torch.Tensor:
     """Integer moment sums [rows, 5] (count, sum X, 2^32 sum g, 2^32 sum g^2,
     2^32 sum X g), accumulated into `out`; `counts` (per row) overrides
-    per_row."""
+    per_row.  rec=None takes X = 0 (moments of g alone)."""
     if out is None:
-        out = torch.zeros(rows * 5, dtype=torch.int64, device=rec.device)
+        out = torch.zeros(rows * 5, dtype=torch.int64, device=gv.device)
     cp = None
     if counts is not None:
         ca = np.ascontiguousarray(counts, dtype=np.uint64)
@@ -194,6 +194,42 @@ class Census:
         return out
 
 
+class CentreTable:
+    """The network's g for every (bin, centre bucket) key and endpoint bucket
+    pair (wedge_cv_keys + wedge_cv_gtable), for the centre draws."""
+
+    def __init__(self, g: W.Csr, bi: W.BinIndex, net: "Mlp", stream=None):
+        dev = g.rowptr.device
+        self.bi = bi
+        self.keys = W._empty_bytes(int(_L().wedge_cv_census_bytes(g.n, g.m, bi.max_bins)), dev)
+        W._check(_L().wedge_cv_keys(W._ptr(self.keys), bi.max_bins, bi.tau, bi.omega,
+                                    W._stream(stream)))
+        cap = 256 + bi.max_bins + 1
+        self.gtable = torch.empty(cap * KPAIRS, dtype=torch.float32, device=dev)
+        ws = W._empty_bytes(int(_L().wedge_cv_gtable_workspace(bi.max_bins)), dev)
+        W._check(_L().wedge_cv_gtable(W._ptr(net.state), W._ptr(self.keys), bi.max_bins,
+                                      W._ptr(self.gtable), W._ptr(ws), ws.numel(),
+                                      W._stream(stream)))
+
+
+def centre_means(g: W.Csr, bi: W.BinIndex, table: CentreTable, h_k, s_begin, seed: int,
+                 domain: int, out: torch.Tensor, stride: int, vout: torch.Tensor | None = None,
+                 stream=None):
+    """wedge_cv_centre_means into out (float32 [rows][stride])."""
+    hk = np.ascontiguousarray(h_k, dtype=np.uint64)
+    sb = np.zeros(bi.max_bins + 1, dtype=np.uint64)
+    sb[:] = np.asarray(s_begin, dtype=np.uint64)
+    ws = W._empty_bytes(int(_L().wedge_cv_centre_means_workspace(int(hk.sum()))),
+                        g.rowptr.device)
+    W._check(_L().wedge_cv_centre_means(W._ptr(g.rowptr), W._ptr(g.col), g.n, g.m,
+                                        W._ptr(bi.index), bi.max_bins, bi.tau, bi.omega,
+                                        hk.ctypes.data_as(W._vp), sb.ctypes.data_as(W._vp),
+                                        seed, domain, 0, W._ptr(table.keys),
+                                        W._ptr(table.gtable), W._ptr(out), stride,
+                                        W._ptr(vout) if vout is not None else None, W._ptr(ws),
+                                        ws.numel(), W._stream(stream)))
+
+
 def _table_offset(max_bins: int) -> int:
     cap = 256 + max_bins + 1
     r = lambda x: (x + 255) // 256 * 256  # noqa: E731
@@ -210,6 +246,9 @@ class RowStats:
     an: int = 0
     ag: int = 0
     ag2: int = 0
+    cn: int = 0     # centre draws: count, 2^32 sum gbar, 2^32 sum gbar^2
+    cg: int = 0
+    cg2: int = 0
 
 
 def rho2_from_moments(m) -> float:
@@ -237,10 +276,11 @@ def beta_from_moments(m) -> float:
 
 
 def cv_row_estimate(st: RowStats, beta: float, delta_i: float, use_aux: bool,
-                    exact_mean: float | None = None):
+                    exact_mean: float | None = None, centre: bool = False):
     """(estimate, half-width) of one row from its moments; with exact_mean
     the control variate's mean is known and the whole delta_i goes to the
-    EVAL bound."""
+    EVAL bound; with centre=True the mean comes from the centre draws (each
+    side of the bound at delta_i / 2), and beta = 0 is the plain form."""
     n = st.n
     if n < 2:
         return float("nan"), float("inf")
@@ -250,6 +290,16 @@ def cv_row_estimate(st: RowStats, beta: float, delta_i: float, use_aux: bool,
     vg = (st.sg2 / Q32 - n * mg * mg) / (n - 1)
     cxg = (st.sxg / Q32 - n * mx * mg) / (n - 1)
     vz = vx - 2 * beta * cxg + beta * beta * vg
+    if centre:
+        if beta == 0.0:
+            return mx, eb_halfwidth(n, vx, 1.0, delta_i)
+        if st.cn < 2:
+            return float("nan"), float("inf")
+        cm = st.cg / Q32 / st.cn
+        cv = (st.cg2 / Q32 - st.cn * cm * cm) / (st.cn - 1)
+        hw = (eb_halfwidth(n, vz, 1.0 + abs(beta), delta_i / 2)
+              + abs(beta) * eb_halfwidth(st.cn, cv, 1.0, delta_i / 2))
+        return (mx - beta * mg) + beta * cm, hw
     if exact_mean is not None:
         return (mx - beta * mg) + beta * exact_mean, eb_halfwidth(n, vz, 1.0 + abs(beta),
                                                                   delta_i)
@@ -324,12 +374,15 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
                net: Mlp | None, beta: dict | None, n0: int = 1 << 14,
                max_per_row: int = 1 << 26, exact_means: dict | None = None,
                first: dict | None = None, growth: float = 2.0,
+               centre: CentreTable | None = None, centre_first: dict | None = None,
                stream=None) -> SequentialResult:
     """EVAL (and, with a network and no exact means, AUX) draws in rounds:
     row r's running total after round i is first[r] * growth^(i-1) (n0 for
     every row without a plan), until every row's half-width at
     delta_i = delta / (i (i+1)) is <= eps.  The plan must not depend on the
-    EVAL draws (a pilot from TRAIN draws, or a constant)."""
+    EVAL draws (a pilot from TRAIN draws, or a constant).  With a centre
+    table, rows with beta != 0 take the control variate's mean from centre
+    draws instead, centre_first[r] * growth^(i-1) of them after round i."""
     dev = g.rowptr.device
     B = bi.max_bins
     rows = sorted(rows)
@@ -337,6 +390,8 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
     res = SequentialResult()
     stats = {r: RowStats() for r in rows}
     done = {r: 0 for r in rows}
+    cdone = {r: 0 for r in rows}
+    use_centre = centre is not None and net is not None
     active = list(rows)
     i = 0
     while active:
@@ -361,13 +416,35 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             net.forward(recs, A * stride, gv, stream=stream)
         m = _moments_per_row(recs, gv, incs, stride, dev)
         am = None
-        if net is not None and exact_means is None:
+        cm, crow = None, []
+        if use_centre:
+            hc = np.zeros(B + 1, dtype=np.uint64)
+            sc = np.zeros(B + 1, dtype=np.uint64)
+            for r in active:
+                if beta.get(r, 0.0) == 0.0:
+                    continue
+                target = min(int(math.ceil(centre_first[r] * growth ** (i - 1))), max_per_row)
+                if target > cdone[r]:
+                    hc[r], sc[r] = target - cdone[r], cdone[r]
+                    crow.append(r)
+            if crow:
+                cinc = [int(hc[r]) for r in crow]
+                cstride = max(cinc)
+                cout = torch.empty(len(crow) * cstride, dtype=torch.float32, device=dev)
+                centre_means(g, bi, centre, hc, sc, seed, DOMAIN_CENTRE, cout, cstride,
+                             stream=stream)
+                cm = _moments_per_row(None, cout, cinc, cstride, dev)
+        elif net is not None and exact_means is None:
             arecs = new_records(A, stride, dev)
             sample_features(g, bi, hk, sb, seed, DOMAIN_AUX, False, arecs, stride, stream=stream)
             agv = torch.zeros(A * stride, dtype=torch.float32, device=dev)
             net.forward(arecs, A * stride, agv, stream=stream)
             am = _moments_per_row(arecs, agv, incs, stride, dev)
         delta_i = delta / (i * (i + 1))
+        for j, r in enumerate(crow):
+            st = stats[r]
+            st.cn += int(cm[j, 0]); st.cg += int(cm[j, 2]); st.cg2 += int(cm[j, 3])
+            cdone[r] += int(cm[j, 0])
         still = []
         for j, r in enumerate(active):
             st = stats[r]
@@ -378,10 +455,11 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             done[r] += incs[j]
             b = beta.get(r, 0.0) if beta else 0.0
             em = exact_means.get(r) if (exact_means is not None and net is not None) else None
-            est, hw = cv_row_estimate(st, b, delta_i, use_aux=net is not None, exact_mean=em)
+            est, hw = cv_row_estimate(st, b, delta_i, use_aux=net is not None, exact_mean=em,
+                                      centre=use_centre)
             res.estimates[r], res.halfwidth[r] = est, hw
             res.eval_samples[r] = st.n
-            res.aux_samples[r] = st.an
+            res.aux_samples[r] = st.cn if use_centre else st.an
             if hw > eps and done[r] < max_per_row:
                 still.append(r)
         active = still
@@ -454,16 +532,91 @@ def plans(tr: TrainResult, eps: float, delta: float):
     return plain, cv
 
 
+# Centre draws of the pilot start at this sample index, far past any draw an
+# estimate uses, so the plan is independent of the draws it schedules.
+PILOT_BEGIN = 1 << 40
+# Cost of one centre draw in EVAL draws, 1 + a d^b for a centre of degree d
+# (fitted to launch times of both kinds of draw on R-MAT graphs: the lane
+# path's pair loop and the wave path's gathers grow slower than d).
+CENTRE_COST = (0.15, 0.7)
+
+
+def centre_pilot(g: W.Csr, bi: W.BinIndex, rows: list[int], table: CentreTable, seed: int,
+                 n: int = 4096, stream=None) -> dict:
+    """(mean, variance) of gbar over n centre draws per row from the pilot
+    range of the centre stream."""
+    B = bi.max_bins
+    rows = sorted(rows)
+    hk = np.zeros(B + 1, dtype=np.uint64)
+    hk[rows] = n
+    out = torch.empty(len(rows) * n, dtype=torch.float32, device=g.rowptr.device)
+    centre_means(g, bi, table, hk, PILOT_BEGIN, seed, DOMAIN_CENTRE, out, n, stream=stream)
+    m = _moments_per_row(None, out, [n] * len(rows), n, g.rowptr.device)
+    res = {}
+    for j, r in enumerate(rows):
+        cnt, sg, sg2 = int(m[j, 0]), m[j, 2] / Q32, m[j, 3] / Q32
+        mean = sg / cnt
+        res[r] = (mean, max((sg2 - cnt * mean * mean) / (cnt - 1), 0.0))
+    return res
+
+
+def centre_cost(bi: W.BinIndex, r: int, model=CENTRE_COST) -> float:
+    """Modelled cost of a centre draw of row r in EVAL draws; d is taken as
+    the degree whose C(d, 2) is the row's mean wedges per vertex."""
+    B = bi.max_bins
+
+    def deg(b):
+        n_b, p_b = float(bi.h_n_b[b]), float(bi.h_p_b[b])
+        return 0.5 + math.sqrt(0.25 + 2.0 * p_b / n_b) if n_b > 0 else 0.0
+
+    if r < B:
+        d = deg(r)
+    else:
+        p = np.asarray(bi.h_p_b[:B], dtype=np.float64)
+        d = float(sum(p[b] * deg(b) for b in range(B) if p[b] > 0) / max(p.sum(), 1.0))
+    return 1.0 + model[0] * d ** model[1]
+
+
+def plans_centre(tr: TrainResult, pilot: dict, bi: W.BinIndex, eps: float, delta: float,
+                 model=CENTRE_COST):
+    """First-round EVAL and centre draws and the beta of every row for the
+    centre form, from the held-out TRAIN draws and the centre pilot (a row
+    without a pilot entry is planned at zero gbar variance, the cheapest
+    case): the eps share of the centre term that minimises the modelled
+    cost, or the plain form (beta = 0, all of eps and delta_1 on the EVAL
+    draws) where that is cheaper."""
+    n_eval, n_centre, beta_used = {}, {}, {}
+    for r, m in tr.holdout.items():
+        b = tr.beta[r]
+        vx, vz = row_variances(m, b)
+        plain = eb_samples_needed(vx, 1.0, delta / 2, eps)
+        best = (float(plain), plain, 0, 0.0)
+        kap = centre_cost(bi, r, model)
+        vc = pilot[r][1] if r in pilot else 0.0
+        if b != 0.0:
+            for t in np.arange(0.02, 0.99, 0.02):
+                ne = eb_samples_needed(vz, 1.0 + abs(b), delta / 4, eps * (1.0 - t))
+                nc = eb_samples_needed(vc, 1.0, delta / 4, eps * t / abs(b))
+                cost = ne + kap * nc
+                if cost < best[0]:
+                    best = (cost, ne, nc, b)
+        _, n_eval[r], n_centre[r], beta_used[r] = best
+    return n_eval, n_centre, beta_used
+
+
 def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, seed: int = 11,
             n_train: int = 10_000_000, epochs: int = 1, per_row_batch: int = 4096,
-            lr: float = 2e-2, growth: float = 1.1, aux_form: bool = True) -> dict:
+            lr: float = 2e-2, growth: float = 1.1, aux_form: bool = True,
+            exact_form: bool = True, pilot: int = 4096) -> dict:
     """Samples and wall time to reach a half-width <= eps at confidence
     1 - delta on every sampled bin and on the global stream, for plain
     sampling with the empirical-Bernstein stopping rule and for the learned
     control variate with the same rule.  Both follow round plans from the
     held-out TRAIN draws (first round at the predicted n, then growing by
     `growth`).  TRAIN draws count as closure checks of the control-variate
-    form; AUX draws (no closure test) are reported separately."""
+    form; AUX draws (no closure test) are reported separately.  The control
+    variate's mean comes from centre draws (learned_cv_centre), from the
+    census (learned_cv_exact_mean, exact_form) or from AUX draws (aux_form)."""
     B = bi.max_bins
     rows = [r for r in range(B) if bi.h_p_b[r] > 0] + [B]
     torch.cuda.synchronize()
@@ -475,13 +628,33 @@ def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, se
     beta_used = {r: (tr.beta[r] if plan_cv[r] < plan_plain[r] else 0.0) for r in rows}
     plan_used = {r: min(plan_cv[r], plan_plain[r]) for r in rows}
     pe = sequential(g, bi, rows, eps, delta, seed, None, None, first=plan_plain, growth=growth)
+    # rows that could gain from centre draws even at zero gbar variance get a
+    # pilot; the others keep the plain form without spending any centre draw
     t0 = time.perf_counter()
-    census = Census(g, bi)
-    means = census.means(tr.net)
+    _, _, screen = plans_centre(tr, {}, bi, eps, delta)
+    prow = [r for r in rows if screen[r] != 0.0]
+    table, pil = None, {}
+    if prow:
+        table = CentreTable(g, bi, tr.net)
+        pil = centre_pilot(g, bi, prow, table, seed, n=pilot)
     torch.cuda.synchronize()
-    t_census = time.perf_counter() - t0
-    cvx = sequential(g, bi, rows, eps, delta, seed, tr.net, beta_used, first=plan_used,
-                     growth=growth, exact_means=means)
+    t_pilot = time.perf_counter() - t0
+    ce_eval, ce_centre, ce_beta = plans_centre(tr, pil, bi, eps, delta)
+    ce_beta = {r: (ce_beta[r] if r in pil else 0.0) for r in rows}
+    if table is not None:
+        cvc = sequential(g, bi, rows, eps, delta, seed, tr.net, ce_beta, first=ce_eval,
+                         growth=growth, centre=table, centre_first=ce_centre)
+    else:   # plain on every row: the same plan and draws as plain-EB
+        cvc = pe
+    means, cvx, t_census = {}, None, 0.0
+    if exact_form:
+        t0 = time.perf_counter()
+        census = Census(g, bi)
+        means = census.means(tr.net)
+        torch.cuda.synchronize()
+        t_census = time.perf_counter() - t0
+        cvx = sequential(g, bi, rows, eps, delta, seed, tr.net, beta_used, first=plan_used,
+                         growth=growth, exact_means=means)
     cvr = None
     if aux_form:
         cvr = sequential(g, bi, rows, eps, delta, seed, tr.net, tr.beta, first=plan_cv,
@@ -489,14 +662,21 @@ def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, se
     per_row = {}
     for r in rows:
         name = "global" if r == B else str(r)
-        row = {"beta": round(tr.beta[r], 5), "beta_used": round(beta_used[r], 5),
-               "rho2": round(tr.rho2[r], 5),
-               "plan_plain": plan_plain[r], "plan_cv": plan_cv[r],
-               "plain_eb_samples": pe.eval_samples[r],
-               "cv_exact_eval_samples": cvx.eval_samples[r],
-               "exact_mean_g": means.get(r),
-               "plain_eb_estimate": pe.estimates[r], "cv_exact_estimate": cvx.estimates[r],
-               "plain_eb_halfwidth": pe.halfwidth[r], "cv_exact_halfwidth": cvx.halfwidth[r]}
+        row = {"beta": round(tr.beta[r], 5), "rho2": round(tr.rho2[r], 5),
+               "plan_plain": plan_plain[r], "plain_eb_samples": pe.eval_samples[r],
+               "plain_eb_estimate": pe.estimates[r], "plain_eb_halfwidth": pe.halfwidth[r],
+               "centre_beta": round(ce_beta[r], 5), "centre_plan_eval": ce_eval[r],
+               "centre_plan_centre": ce_centre[r],
+               "centre_pilot_var": pil[r][1] if r in pil else None,
+               "centre_cost": round(centre_cost(bi, r), 3),
+               "cv_centre_eval_samples": cvc.eval_samples[r],
+               "cv_centre_draws": cvc.aux_samples[r], "cv_centre_estimate": cvc.estimates[r],
+               "cv_centre_halfwidth": cvc.halfwidth[r]}
+        if cvx is not None:
+            row.update({"beta_used": round(beta_used[r], 5), "plan_cv": plan_cv[r],
+                        "cv_exact_eval_samples": cvx.eval_samples[r],
+                        "exact_mean_g": means.get(r), "cv_exact_estimate": cvx.estimates[r],
+                        "cv_exact_halfwidth": cvx.halfwidth[r]})
         if cvr is not None:
             row.update({"cv_aux_eval_samples": cvr.eval_samples[r],
                         "cv_aux_samples": cvr.aux_samples[r], "cv_aux_estimate": cvr.estimates[r],
@@ -508,15 +688,23 @@ def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, se
                   "final_loss": tr.losses[-1], "epochs": epochs,
                   "minibatch": per_row_batch * len(rows)},
         "plain_eb": {"closure_checks": pe.total_eval, "seconds": pe.seconds, "rounds": pe.rounds},
-        "learned_cv_exact_mean": {"closure_checks": cvx.total_eval + tr.train_samples,
-                                  "eval_checks": cvx.total_eval,
-                                  "train_checks": tr.train_samples,
-                                  "seconds": cvx.seconds + tr.seconds + t_census,
-                                  "eval_seconds": cvx.seconds, "census_seconds": t_census,
-                                  "train_seconds": tr.seconds, "rounds": cvx.rounds},
-        "network_gain_eval_checks": pe.total_eval / max(cvx.total_eval, 1),
+        "learned_cv_centre": {"closure_checks": cvc.total_eval + tr.train_samples,
+                              "eval_checks": cvc.total_eval, "train_checks": tr.train_samples,
+                              "centre_draws": cvc.total_aux, "pilot_draws": pilot * len(pil),
+                              "seconds": cvc.seconds + tr.seconds + t_pilot,
+                              "eval_seconds": cvc.seconds, "table_pilot_seconds": t_pilot,
+                              "train_seconds": tr.seconds, "rounds": cvc.rounds,
+                              "rows_with_cv": int(sum(1 for r in rows if ce_beta[r] != 0.0))},
+        "network_gain_eval_checks": pe.total_eval / max(cvc.total_eval, 1),
         "per_row": per_row,
     }
+    if cvx is not None:
+        out["learned_cv_exact_mean"] = {"closure_checks": cvx.total_eval + tr.train_samples,
+                                        "eval_checks": cvx.total_eval,
+                                        "train_checks": tr.train_samples,
+                                        "seconds": cvx.seconds + tr.seconds + t_census,
+                                        "eval_seconds": cvx.seconds, "census_seconds": t_census,
+                                        "train_seconds": tr.seconds, "rounds": cvx.rounds}
     if cvr is not None:
         out["learned_cv_aux"] = {"closure_checks": cvr.total_eval + tr.train_samples,
                                  "eval_checks": cvr.total_eval, "aux_draws": cvr.total_aux,

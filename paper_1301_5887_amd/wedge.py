@@ -116,6 +116,13 @@ SIGNATURES = {
                                        ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, _vp, _vp, ctypes.c_size_t, _vp]),
     "wedge_cv_moments": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _c_u64, _vp, _vp, _vp]),
+    "wedge_cv_keys": (ctypes.c_int, [_vp, _c_u32, _c_u32, _c_u64, _vp]),
+    "wedge_cv_gtable_workspace": (ctypes.c_size_t, [_c_u32]),
+    "wedge_cv_gtable": (ctypes.c_int, [_vp, _vp, _c_u32, _vp, _vp, ctypes.c_size_t, _vp]),
+    "wedge_cv_centre_means_workspace": (ctypes.c_size_t, [_c_u64]),
+    "wedge_cv_centre_means": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _c_u32,
+                                             _c_u64, _vp, _vp, _c_u64, _c_u32, _c_u32, _vp,
+                                             _vp, _vp, _c_u64, _vp, _vp, ctypes.c_size_t, _vp]),
     "wedge_eb_halfwidth": (ctypes.c_double, [_c_u64, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double]),
     "wedge_cv_census_bytes": (ctypes.c_size_t, [_c_u32, _c_u64, _c_u32]),

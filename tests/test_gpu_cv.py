@@ -399,6 +399,141 @@ def test_compare_reaches_the_interval(c1):
     for name, row in res["per_row"].items():
         c_true = c_glob if name == "global" else float(closed[int(name)]) / float(wedges[int(name)])
         assert row["plain_eb_halfwidth"] <= eps and row["cv_exact_halfwidth"] <= eps, name
+        assert row["cv_centre_halfwidth"] <= eps, name
         assert abs(row["plain_eb_estimate"] - c_true) <= 3 * eps, name
         assert abs(row["cv_exact_estimate"] - c_true) <= 3 * eps, name
+        assert abs(row["cv_centre_estimate"] - c_true) <= 3 * eps, name
+        if row["centre_beta"] == 0.0:
+            assert row["cv_centre_draws"] == 0, name
     assert res["learned_cv_exact_mean"]["train_checks"] > 0
+    assert res["learned_cv_centre"]["train_checks"] > 0
+
+
+def centre_gbar(og, theta, centres):
+    """Mean of the network's g over every neighbour pair of each centre,
+    summed by endpoint bucket pair (the network sees the endpoints only
+    through their buckets); the grouping is checked against plain pair
+    enumeration on the small centres."""
+    deg = og.degrees().astype(np.int64)
+    parts, combos = {}, {}
+    for v in np.unique(centres):
+        v = int(v)
+        d = int(deg[v])
+        b = O.bin_id(d, 2, 2)
+        kv = int(M.bucket(np.array([d]))[0])
+        nb = og.col[int(og.rowptr[v]): int(og.rowptr[v + 1])]
+        h = np.bincount(M.bucket(deg[nb]), minlength=256).astype(np.float64)
+        nz = np.nonzero(h)[0]
+        pi, pj = np.meshgrid(nz, nz, indexing="ij")
+        up = pi <= pj
+        pi, pj = pi[up], pj[up]
+        w = np.where(pi == pj, h[pi] * (h[pi] - 1) / 2, h[pi] * h[pj])
+        idx = [combos.setdefault((kv, b, int(i), int(j)), len(combos)) for i, j in zip(pi, pj)]
+        parts[v] = (d, b, nb, np.array(idx), w)
+    keys = np.array(list(combos.keys()), dtype=np.float64)
+    x = np.stack([keys[:, 0] / 256.0, keys[:, 2] / 256.0, keys[:, 3] / 256.0,
+                  keys[:, 1] / 32.0], axis=1)
+    gk = M.forward(theta, x, rounding=True)[0]
+    out = {}
+    for v, (d, b, nb, idx, w) in parts.items():
+        out[v] = float((w * gk[idx]).sum()) / (d * (d - 1) / 2)
+        if d <= 12:
+            pa, pc = np.triu_indices(d, 1)
+            xd = M.features(np.full(pa.size, d), deg[nb[pa]], deg[nb[pc]], np.full(pa.size, b))
+            direct = M.forward(theta, xd, rounding=True)[0].mean()
+            assert abs(direct - out[v]) < 1e-12, (v, direct, out[v])
+    return out
+
+
+@pytest.mark.parametrize("case", ["chung_lu", "hubs"])
+def test_centre_draws_match_oracle(case, c1):
+    """Centres drawn from the centre stream equal the oracle sampler's centres
+    at the same indices (key (seed, 6)); gbar of every draw matches the mean of
+    the oracle network over all neighbour pairs of that centre."""
+    if case == "chung_lu":
+        g, bi, og = c1
+    else:
+        name, n, src, dst = next(c for c in small_graphs() if c[0] == case)
+        g = W.build_csr(dev(src), dev(dst), n)
+        bi = W.bin_counts(g, 2, 2, 24)
+        og = O.build_graph(src, dst, n)
+    B = bi.max_bins
+    theta = M.init_params(31)
+    net = net_with(theta)
+    table = C.CentreTable(g, bi, net)
+    rows = [r for r in range(B) if bi.h_p_b[r] > 0] + [B]
+    hk = np.zeros(B + 1, dtype=np.uint64)
+    sb = np.zeros(B + 1, dtype=np.uint64)
+    for j, r in enumerate(rows):
+        hk[r] = 300 + 37 * j
+        sb[r] = 5000 * j
+    stride = int(hk.max())
+    print(f"[cv] centre draws {case} rows={len(rows)} stride={stride}", flush=True)
+    out = torch.full((len(rows) * stride,), -1.0, dtype=torch.float32, device="cuda")
+    vout = torch.zeros(len(rows) * stride, dtype=torch.int32, device="cuda")
+    C.centre_means(g, bi, table, hk, sb, 3, C.DOMAIN_CENTRE, out, stride, vout=vout)
+    torch.cuda.synchronize()
+    gb = out.cpu().numpy().reshape(len(rows), stride).astype(np.float64)
+    vv = vout.cpu().numpy().view(np.uint32).reshape(len(rows), stride)
+    allv = []
+    for j, r in enumerate(rows):
+        k = int(hk[r])
+        k1 = np.zeros(B + 1, dtype=np.uint64)
+        k1[r] = k
+        s = O.sample(og, 2, 2, B, k1[:B], int(k1[B]), 3, dump_per_bin=k,
+                     domain=C.DOMAIN_CENTRE, s_begin=int(sb[r]))
+        assert (vv[j, :k] == s.v[r]).all(), r
+        assert (gb[j, k:] == -1.0).all()          # nothing past the row's draws
+        allv.append(s.v[r])
+    ref = centre_gbar(og, theta, np.concatenate(allv))
+    deg = og.degrees()
+    assert deg[np.concatenate(allv)].max() > 32 or case == "chung_lu"
+    err = max(abs(gb[j, i] - ref[int(vv[j, i])]) for j, r in enumerate(rows)
+              for i in range(int(hk[r])))
+    assert err < 2e-3, err
+
+
+def test_centre_mean_is_the_exact_mean(c1):
+    """E[gbar(v)] over centres drawn with probability p_v / p_b is the mean of
+    g over the bin's wedges: the centre-draw average agrees with the census's
+    exact mean within sampling error, per bin."""
+    g, bi, og = c1
+    B = bi.max_bins
+    net = net_with(M.init_params(21))
+    means = C.Census(g, bi).means(net)
+    table = C.CentreTable(g, bi, net)
+    rows = [r for r in range(B) if bi.h_p_b[r] > 0] + [B]
+    k = 1 << 15
+    hk = np.zeros(B + 1, dtype=np.uint64)
+    hk[rows] = k
+    out = torch.empty(len(rows) * k, dtype=torch.float32, device="cuda")
+    C.centre_means(g, bi, table, hk, 0, 12, C.DOMAIN_CENTRE, out, k)
+    gb = out.cpu().numpy().reshape(len(rows), k).astype(np.float64)
+    for j, r in enumerate(rows):
+        se = gb[j].std(ddof=1) / math.sqrt(k)
+        assert abs(gb[j].mean() - means[r]) <= 5 * se + 2e-6, (r, gb[j].mean(), means[r], se)
+
+
+def test_centre_cv_unbiased(c1):
+    """The centre-draw control variate over repeated seeds: its mean matches
+    the exact c_b within a few standard errors on every row it is used on."""
+    g, bi, og = c1
+    B = bi.max_bins
+    P = O.exact(og, 2, 2, B)
+    rows = [r for r in range(B) if bi.h_p_b[r] > 0]
+    tr = C.train(g, bi, rows, 200_000, seed=4, epochs=2, per_row_batch=256, lr=5e-3)
+    table = C.CentreTable(g, bi, tr.net)
+    ests = {r: [] for r in rows}
+    R, n = 24, 1 << 12
+    first = {r: n for r in rows}
+    for sd in range(R):
+        res = C.sequential(g, bi, rows, 1e-9, 1e-3, 500 + sd, tr.net, tr.beta, first=first,
+                           max_per_row=n, centre=table, centre_first=first)
+        for r in rows:
+            assert res.aux_samples[r] == (n if tr.beta[r] != 0.0 else 0)
+            ests[r].append(res.estimates[r])
+    for r in rows:
+        c_true = float(P[r, 1:].sum()) / float(bi.h_p_b[r])
+        e = np.array(ests[r])
+        se = max(e.std(ddof=1), 1e-6) / math.sqrt(R)
+        assert abs(e.mean() - c_true) <= 3.5 * se + 1e-9, (r, e.mean(), c_true, se)
