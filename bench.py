@@ -12,6 +12,11 @@ wedge_sample_close (samples and exact closure tests), wedge_estimate
 (FP64 summary), including the two small host reads the path needs (m, and
 the per-bin wedge counts that decide which bins are sampled).
 
+--graph bter runs the same step on a BTER-like community graph instead
+(power-law target degrees with exponent --bter-gamma on [--bter-dmin,
+--bter-dmax], dense blocks of d + 1 vertices of density 1/ln d, excess degree by
+Chung-Lu; n = --bter-n).
+
 Prints one JSON line.  value = closure checks per second of the whole step.
 """
 from __future__ import annotations
@@ -60,6 +65,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--graph", choices=["rmat", "bter"], default="rmat")
+    ap.add_argument("--bter-n", type=int, default=130_000_000)
+    ap.add_argument("--bter-gamma", type=float, default=2.1)
+    ap.add_argument("--bter-dmin", type=int, default=10)
+    ap.add_argument("--bter-dmax", type=int, default=1_000_000)
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--edgefactor", type=int, default=16)
     ap.add_argument("--seed", type=int, default=7)
@@ -97,9 +107,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     t0 = time.time()
-    n, src, dst = gen.rmat_graph500(args.scale, args.edgefactor, args.seed)
-    log(f"[bench] generated R-MAT s{args.scale} ef{args.edgefactor}: n={n} m_in={len(src)} "
-        f"in {time.time() - t0:.1f}s")
+    if args.graph == "bter":
+        n = args.bter_n
+        src, dst = gen.bter(n, args.bter_gamma, args.bter_dmin, args.bter_dmax, args.seed,
+                            progress=log)
+        workload = (f"BTER-like, n {n}, degree power law {args.bter_gamma:g} on "
+                    f"[{args.bter_dmin}, {args.bter_dmax}], seed {args.seed}")
+    else:
+        n, src, dst = gen.rmat_graph500(args.scale, args.edgefactor, args.seed)
+        workload = (f"R-MAT scale {args.scale}, edgefactor {args.edgefactor}, "
+                    f"Graph500 (0.57,0.19,0.19,0.05), seed {args.seed}")
+    log(f"[bench] generated {workload}: n={n} m_in={len(src)} in {time.time() - t0:.1f}s")
     d_src = torch.from_numpy(src.view(np.int32)).cuda()
     d_dst = torch.from_numpy(dst.view(np.int32)).cuda()
     m_in = len(src)
@@ -219,14 +237,17 @@ def main():
         cvcmp["plain_hoeffding"] = {"closure_checks": K,
                                     "seconds": avg["sample_close"] / 1000.0}
         lc = cvcmp["learned_cv_centre"]
+        lx = cvcmp.get("learned_cv_exact_mean")
         log(f"[bench] estimator comparison: plain-Hoeffding {K} checks, plain-EB "
             f"{cvcmp['plain_eb']['closure_checks']}, learned-CV with centre draws "
             f"{lc['closure_checks']} (eval {lc['eval_checks']}, centre draws "
-            f"{lc['centre_draws']}, {lc['seconds']:.4f} s)")
+            f"{lc['centre_draws']}, {lc['seconds']:.4f} s)"
+            + (f", learned-CV with exact mean {lx['closure_checks']} (eval "
+               f"{lx['eval_checks']}, {lx['seconds']:.4f} s)" if lx else ""))
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(src, dst, n, B, hk, kg, args, W, torch)
+        cpu = cpu_baseline(src, dst, n, B, hk, kg, args, W, torch, workload)
 
     out = {
         "metric": METRIC,
@@ -241,9 +262,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"R-MAT scale {args.scale}, edgefactor {args.edgefactor}, "
-                               f"Graph500 (0.57,0.19,0.19,0.05), seed {args.seed}; "
-                               f"tau=omega=2; eps=delta={args.eps:g}",
+        "config": {"workload": f"{workload}; tau=omega=2; eps=delta={args.eps:g}",
                    "n": n, "m": int(m), "m_in": m_in, "k_per_bin": k,
                    "bins_sampled": int((hk > 0).sum()), "k_global": kg, "closure_checks": K},
         "s_per_M_edges": (ms_step / 1000.0) / (m / 1e6),
@@ -297,7 +316,7 @@ def pmc_summarize(fetch_dir: str, write_dir: str, workload_k: int, copy_gib: flo
     print(json.dumps(out))
 
 
-def cpu_baseline(src, dst, n, B, hk, kg, args, W, torch):
+def cpu_baseline(src, dst, n, B, hk, kg, args, W, torch, workload):
     """The oracle, as it stands, on a bounded sample of the same workload:
     the first `cpu_samples_per_bin` samples of every sampled bin and of the
     global stream, all host threads.  Its class counts are compared with the
@@ -331,7 +350,7 @@ def cpu_baseline(src, dst, n, B, hk, kg, args, W, torch):
     return {"value": Ks / dt, "unit": "closure checks/s", "cores": threads, "kind": "oracle",
             "sample": f"first {args.cpu_samples_per_bin} samples of each of "
                       f"{int((ks > 0).sum())} bins and of the global stream ({Ks} checks) "
-                      f"on the same R-MAT scale-{args.scale} graph; oracle graph set-up "
+                      f"on the same graph ({workload}); oracle graph set-up "
                       f"{time.time() - t0 - dt:.1f}s not timed",
             "gpu_counts_match": match}
 

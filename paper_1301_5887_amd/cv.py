@@ -315,22 +315,18 @@ def cv_row_estimate(st: RowStats, beta: float, delta_i: float, use_aux: bool,
     return est, e_eval + e_aux
 
 
-def eb_samples_needed(var: float, R: float, delta: float, eps: float,
-                      n_max: int = 1 << 40) -> int:
-    """Smallest n with an empirical-Bernstein half-width <= eps at variance
-    `var` (bisection over the closed form)."""
-    if eb_halfwidth(n_max, var, R, delta) > eps:
-        return n_max
-    lo, hi = 2, 2
-    while eb_halfwidth(hi, var, R, delta) > eps:
-        lo, hi = hi, hi * 2
-    while hi - lo > 1:
-        mid = (lo + hi) // 2
-        if eb_halfwidth(mid, var, R, delta) <= eps:
-            hi = mid
-        else:
-            lo = mid
-    return hi
+def eb_samples_closed(var, R, delta: float, eps):
+    """Planning size for an empirical-Bernstein half-width <= eps (the bound
+    of wedge_eb_halfwidth with n - 1 taken as n, then one sample added):
+    the positive root of a x + b x^2 = eps in x = 1 / sqrt(n) with
+    a = sqrt(2 var ln(4/delta)), b = 7 R ln(4/delta) / 3.  Vectorised over
+    numpy arrays; a plan only, the stopping rule uses the exact bound."""
+    L = math.log(4.0 / delta)
+    a = np.sqrt(2.0 * np.maximum(var, 0.0) * L)
+    b = 7.0 * np.asarray(R, dtype=np.float64) * L / 3.0
+    e = np.asarray(eps, dtype=np.float64)
+    x = 2.0 * e / (a + np.sqrt(a * a + 4.0 * b * e))
+    return np.ceil(1.0 / (x * x)) + 1.0
 
 
 def row_variances(m, beta: float):
@@ -527,8 +523,8 @@ def plans(tr: TrainResult, eps: float, delta: float):
     plain, cv = {}, {}
     for r, m in tr.holdout.items():
         vx, vz = row_variances(m, tr.beta[r])
-        plain[r] = eb_samples_needed(vx, 1.0, delta / 2, eps)
-        cv[r] = eb_samples_needed(vz, 1.0 + abs(tr.beta[r]), delta / 2, eps)
+        plain[r] = int(eb_samples_closed(vx, 1.0, delta / 2, eps))
+        cv[r] = int(eb_samples_closed(vz, 1.0 + abs(tr.beta[r]), delta / 2, eps))
     return plain, cv
 
 
@@ -586,21 +582,21 @@ def plans_centre(tr: TrainResult, pilot: dict, bi: W.BinIndex, eps: float, delta
     cost, or the plain form (beta = 0, all of eps and delta_1 on the EVAL
     draws) where that is cheaper."""
     n_eval, n_centre, beta_used = {}, {}, {}
+    t = np.arange(0.01, 1.0, 0.01)      # share of eps given to the centre term
     for r, m in tr.holdout.items():
         b = tr.beta[r]
         vx, vz = row_variances(m, b)
-        plain = eb_samples_needed(vx, 1.0, delta / 2, eps)
-        best = (float(plain), plain, 0, 0.0)
-        kap = centre_cost(bi, r, model)
+        plain = int(eb_samples_closed(vx, 1.0, delta / 2, eps))
+        n_eval[r], n_centre[r], beta_used[r] = plain, 0, 0.0
+        if b == 0.0:
+            continue
         vc = pilot[r][1] if r in pilot else 0.0
-        if b != 0.0:
-            for t in np.arange(0.02, 0.99, 0.02):
-                ne = eb_samples_needed(vz, 1.0 + abs(b), delta / 4, eps * (1.0 - t))
-                nc = eb_samples_needed(vc, 1.0, delta / 4, eps * t / abs(b))
-                cost = ne + kap * nc
-                if cost < best[0]:
-                    best = (cost, ne, nc, b)
-        _, n_eval[r], n_centre[r], beta_used[r] = best
+        ne = eb_samples_closed(vz, 1.0 + abs(b), delta / 4, eps * (1.0 - t))
+        nc = eb_samples_closed(vc, 1.0, delta / 4, eps * t / abs(b))
+        cost = ne + centre_cost(bi, r, model) * nc
+        j = int(np.argmin(cost))
+        if cost[j] < plain:
+            n_eval[r], n_centre[r], beta_used[r] = int(ne[j]), int(nc[j]), b
     return n_eval, n_centre, beta_used
 
 
@@ -698,6 +694,8 @@ def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, se
         "network_gain_eval_checks": pe.total_eval / max(cvc.total_eval, 1),
         "per_row": per_row,
     }
+    if cvx is not None:
+        out["network_gain_eval_checks_exact_mean"] = pe.total_eval / max(cvx.total_eval, 1)
     if cvx is not None:
         out["learned_cv_exact_mean"] = {"closure_checks": cvx.total_eval + tr.train_samples,
                                         "eval_checks": cvx.total_eval,

@@ -5,6 +5,8 @@ import ctypes
 import os
 import subprocess
 
+import time
+
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -86,11 +88,15 @@ def chung_lu_c1(seed: int = 1):
     return n, src, dst
 
 
-def bter(n: int, gamma: float, dmin: int, dmax: int, seed: int):
-    """BTER-like community graph; returns (src, dst)."""
+def bter(n: int, gamma: float, dmin: int, dmax: int, seed: int, progress=None):
+    """BTER-like community graph; returns (src, dst).  `progress` (a print
+    function) gets a line after the counting pass."""
     need = np.zeros(1, dtype=np.uint64)
+    t0 = time.time()
     _L().synth_bter(n, gamma, dmin, dmax, seed, None, None, 0, need.ctypes.data_as(_u64p))
     cap = int(need[0])
+    if progress:
+        progress(f"[gen] BTER n={n}: {cap} edges counted in {time.time() - t0:.1f}s")
     src = np.empty(max(cap, 1), dtype=np.uint32)
     dst = np.empty(max(cap, 1), dtype=np.uint32)
     got = _L().synth_bter(n, gamma, dmin, dmax, seed, src.ctypes.data_as(_u32p),

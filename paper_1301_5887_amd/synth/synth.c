@@ -112,12 +112,40 @@ static void power_law_weights(uint32_t n, double gamma, uint32_t wmin, uint32_t 
   free(cdf);
 }
 
-static inline uint32_t pick_weighted(const uint64_t* cum, uint32_t n, uint64_t total, uint64_t r) {
-  uint64_t x = (uint64_t)(((u128)r * total) >> 64); /* in [0, total) */
-  uint32_t lo = 0, hi = n - 1;                      /* first v with cum[v] > x */
+/* Weighted vertex choice: the first v with cum[v] > x for x = floor(r total /
+ * 2^64).  A guide table over equal slices of [0, total) narrows the binary
+ * search to the vertices whose cumulative weight ends inside x's slice. */
+typedef struct {
+  const uint64_t* cum;
+  uint32_t n;
+  uint64_t total;
+  uint64_t step;
+  uint32_t* guide; /* [J + 1]: first v with cum[v] > j step (n - 1 past the end) */
+} Picker;
+
+static void picker_init(Picker* p, const uint64_t* cum, uint32_t n, uint64_t total) {
+  uint64_t J = n / 2 + 1;
+  if (J > (1u << 26)) J = 1u << 26;
+  p->cum = cum;
+  p->n = n;
+  p->total = total;
+  p->step = total / J + 1; /* J step > total */
+  p->guide = (uint32_t*)malloc(sizeof(uint32_t) * (J + 1));
+  uint32_t v = 0;
+  for (uint64_t j = 0; j <= J; ++j) {
+    const uint64_t t = j * p->step;
+    while (v < n - 1 && cum[v] <= t) ++v;
+    p->guide[j] = v;
+  }
+}
+
+static inline uint32_t pick_weighted(const Picker* p, uint64_t r) {
+  const uint64_t x = (uint64_t)(((u128)r * p->total) >> 64); /* in [0, total) */
+  const uint64_t j = x / p->step;
+  uint32_t lo = p->guide[j], hi = p->guide[j + 1];
   while (lo < hi) {
     uint32_t mid = lo + (hi - lo) / 2;
-    if (cum[mid] > x) hi = mid; else lo = mid + 1;
+    if (p->cum[mid] > x) hi = mid; else lo = mid + 1;
   }
   return lo;
 }
@@ -136,11 +164,14 @@ void synth_chung_lu(uint32_t n, double gamma, uint32_t wmin, uint32_t wmax, uint
     acc += w[v];
     cum[v] = acc;
   }
+  Picker pk;
+  picker_init(&pk, cum, n, acc);
 #pragma omp parallel for schedule(static)
   for (int64_t ei = 0; ei < (int64_t)M; ++ei) {
-    src[ei] = pick_weighted(cum, n, acc, rnd(seed, 11, 2 * (uint64_t)ei));
-    dst[ei] = pick_weighted(cum, n, acc, rnd(seed, 11, 2 * (uint64_t)ei + 1));
+    src[ei] = pick_weighted(&pk, rnd(seed, 11, 2 * (uint64_t)ei));
+    dst[ei] = pick_weighted(&pk, rnd(seed, 11, 2 * (uint64_t)ei + 1));
   }
+  free(pk.guide);
   free(cum);
   if (!weights_out) free(w);
 }
@@ -236,11 +267,14 @@ uint64_t synth_bter(uint32_t n, double gamma, uint32_t dmin, uint32_t dmax, uint
           }
     }
     if (acc > 0) {
+      Picker pk;
+      picker_init(&pk, cum, n, acc);
 #pragma omp parallel for schedule(static)
       for (int64_t ei = 0; ei < (int64_t)ncl; ++ei) {
-        src[nblock_edges + ei] = pick_weighted(cum, n, acc, rnd(seed, 22, 2 * (uint64_t)ei));
-        dst[nblock_edges + ei] = pick_weighted(cum, n, acc, rnd(seed, 22, 2 * (uint64_t)ei + 1));
+        src[nblock_edges + ei] = pick_weighted(&pk, rnd(seed, 22, 2 * (uint64_t)ei));
+        dst[nblock_edges + ei] = pick_weighted(&pk, rnd(seed, 22, 2 * (uint64_t)ei + 1));
       }
+      free(pk.guide);
     }
   }
   free(d); free(ord); free(bstart); free(bsize); free(excess); free(boff); free(cum); free(bcount);

@@ -121,6 +121,15 @@ def test_rmat_scale14_ragged_k():
     check_all(r)
 
 
+def test_bter_community_graph():
+    """BTER-like community graph (dense blocks of similar degree, Chung-Lu
+    excess): CSR, bins, every dumped sample and the estimates."""
+    n = 30_000
+    src, dst = gen.bter(n, 2.1, 10, 3_000, 11)
+    r = run_both(src, dst, n, tau=2, omega=2, B=40, k=40_000, kg=33_333, seed=9)
+    check_all(r)
+
+
 def test_two_level_class_search():
     """One bin holding > 1024 distinct degrees: the staged table keeps every
     2nd class and the final step searches HBM."""
