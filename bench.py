@@ -194,7 +194,7 @@ def main():
     probes = int(W.to_host_u64(probe)[0])
     avg = {kx: float(np.mean(vx)) for kx, vx in phase.items()}
 
-    # roofline of the sampler (dominant kernel of the hot path)
+    # roofline of the sampler (the closure-probe kernel)
     qh = h_q.numpy().view(np.uint64).reshape(B + 1, 4)
     closed_bins = int(qh[:B, 1:].sum())
     alg_bytes = (BYTES_PER_SAMPLE * K + BYTES_PER_CLOSED_BIN_SAMPLE * closed_bins +
@@ -206,6 +206,22 @@ def main():
             pmc = json.load(f)
         if pmc.get("sampler_hash") == sampler_hash() and pmc.get("workload_K") == K:
             traffic = pmc.get("hbm_bytes_per_launch")
+    # CSR build: the least bytes any method must move (read the edge list,
+    # write col and rowptr) and the bytes of this sort (histogram read of the
+    # edges; first pass reads the edges and writes two keys per edge; each
+    # later digit pass reads and writes every key; the dedup reads the keys
+    # twice and writes col and rowptr)
+    nkeys = 2 * m_in
+    digits = 2 * ((max(n - 1, 1).bit_length() + 7) // 8)
+    csr_min = 8 * m_in + 4 * 2 * m + 8 * (n + 1)
+    csr_sort = (8 * m_in + (8 * m_in + 8 * nkeys) + (digits - 1) * 16 * nkeys
+                + 16 * nkeys + 4 * 2 * m + 8 * (n + 1))
+    t_csr = avg["build_csr"] / 1000.0
+    roofline_csr = {"phase": "wedge_build_csr", "bound": "hbm", "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "digit_passes": digits,
+                    "min_bytes": csr_min, "achieved_min": round(csr_min / t_csr / 1e9, 2),
+                    "sort_bytes": csr_sort, "achieved_sort": round(csr_sort / t_csr / 1e9, 2),
+                    "frac_sort": round(csr_sort / t_csr / 1e9 / PEAK_HBM_GBS, 5)}
     roofline = {"kernel": "k_sample_close", "bound": "hbm", "achieved": round(achieved, 2),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 5),
                 "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
@@ -270,6 +286,7 @@ def main():
         "sample_close_checks_per_s": K / (avg["sample_close"] / 1000.0),
         "phase_ms": {kx: round(vx, 4) for kx, vx in avg.items()},
         "roofline": roofline,
+        "roofline_csr": roofline_csr,
         "cpu_baseline": cpu,
         "estimators": cvcmp,
         "estimates": {"c": est.glob["c"], "c_global": est.glob["c_global"], "t": est.glob["t"],
