@@ -79,6 +79,9 @@ uint64_t wedge_hoeffding_k(double eps, double delta);
  *                     undirected non-loop edges; [1] = number of input edges
  *                     rejected because an endpoint was >= n (they are
  *                     dropped; the caller decides whether that is an error).
+ *                     [0] = 2^64 - 1 means the sort's bounded wait between
+ *                     tiles gave up and rowptr/col are invalid (not expected:
+ *                     a tile only waits on tiles that are already running).
  * Workspace: wedge_build_csr_workspace(m_in, n) bytes of device memory,
  * 256-byte aligned, contents ignored on entry.
  * Errors: EINVAL (null/misaligned pointer), ERANGE (n == 0, m_in >= 2^40),
@@ -106,7 +109,9 @@ int wedge_build_csr(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in,
  * Workspace: wedge_bin_counts_workspace(n) bytes.
  * Device-side condition: a degree whose bin is >= max_bins is counted in the
  * index's overflow counter (read it with wedge_index_status); those vertices
- * are left out of every bin.
+ * are left out of every bin.  overflow = 2^64 - 1 means the sort of the
+ * centre order gave up waiting between tiles and the index is invalid (not
+ * expected, as for wedge_build_csr).
  * Errors: EINVAL, ERANGE (tau == 0, omega < 2, max_bins == 0 or > 4096),
  *         EWORKSPACE, EHIP.
  * ---------------------------------------------------------------------- */

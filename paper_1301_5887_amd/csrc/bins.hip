@@ -273,7 +273,7 @@ static size_t bins_layout(uint64_t n, uint32_t G, uint32_t max_bins, BinsWorkspa
   if (w) w->first_cls = (uint32_t*)(c + off);
   off += round_up(4 * ((size_t)G * ((size_t)max_bins + 1) + 2), 256);
   if (w) w->radix = (void*)(c + off);
-  off += radix_scratch_bytes(n);
+  off += os_scratch_bytes(n);
   return off;
 }
 
@@ -311,7 +311,8 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
   for (int s = 0; s < bit_width(dbound); s += 8) shifts[np++] = 32 + s;
   for (int s = 0; s < gbits; s += 8) shifts[np++] = gshift + s;
   uint64_t* sorted = nullptr;
-  rc = radix_sort(w.keys_a, w.keys_b, n, shifts, np, radix_scratch(w.radix, n), st, &sorted);
+  const OsScratch osc = os_scratch(w.radix, n);
+  rc = onesweep_sort_keys(w.keys_a, w.keys_b, n, shifts, np, osc, st, &sorted);
   if (rc) return rc;
   rc = scan_apply<uint64_t>(ClassLoad{sorted}, ClassApply{sorted, d_rowptr, n, cap, dmask, ix}, n,
                             w.scan_ws, st);
@@ -329,7 +330,8 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
   k_bin_finalize<<<(unsigned)ceil_div(rows, 256), 256, 0, st>>>(ix, n, cap, tau, omega, max_bins,
                                                                 G, d_n_b, d_p_b, w.first_cls);
   WEDGE_LAUNCH_CHECK("k_bin_finalize");
-  return WEDGE_OK;
+  // a sort whose bounded wait gave up leaves overflow = 2^64 - 1
+  return os_flag_stalls(osc, (uint64_t*)&ix.hdr->overflow, ~0ULL, st);
 }
 
 }  // namespace wedge

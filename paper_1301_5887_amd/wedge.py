@@ -228,6 +228,11 @@ class Workspace:
         return self.buf
 
 
+# m (wedge_build_csr) or the index's overflow counter (wedge_bin_counts) when
+# a sort's bounded wait between tiles gave up
+STALLED = (1 << 64) - 1
+
+
 def build_csr(src: torch.Tensor, dst: torch.Tensor, n: int, ws: Workspace | None = None,
               stream=None, sync: bool = True, out: tuple | None = None):
     """wedge_build_csr.  Returns a Csr (syncs to read m unless sync=False,
@@ -249,6 +254,8 @@ def build_csr(src: torch.Tensor, dst: torch.Tensor, n: int, ws: Workspace | None
     if not sync:
         return rowptr, col, info
     h = to_host_u64(info)
+    if int(h[0]) == STALLED:
+        raise WedgeError(-4, "wedge_build_csr: the sort gave up waiting between tiles")
     return Csr(n=n, m=int(h[0]), rowptr=rowptr, col=col, rejected=int(h[1]))
 
 
@@ -285,6 +292,8 @@ def bin_counts(g: Csr, tau: int = 2, omega: int = 2, max_bins: int = 64,
                   index=index)
     if read:
         st = index_status(bi, stream)
+        if st["overflow"] == STALLED:
+            raise WedgeError(-4, "wedge_bin_counts: the sort gave up waiting between tiles")
         if st["overflow"]:
             raise WedgeError(-2, f"{st['overflow']} vertices have a bin >= max_bins={max_bins}")
         bi.h_n_b = to_host_u64(n_b)

@@ -174,6 +174,11 @@ def test_degenerate_graphs():
     r = run_both(src, src, 3, B=8, k=100, dpb=8)
     assert r["g"].m == 0 and r["q"].sum() == 0
     check_all(r)
+    # one vertex: every edge is a self-loop or has an id out of range
+    r = run_both(np.array([0, 0, 3, 1], np.uint32), np.array([0, 0, 0, 0], np.uint32), 1, B=8,
+                 k=100, dpb=8)
+    assert r["g"].m == 0 and r["g"].rejected == 2
+    check_all(r)
     # one edge: no wedges
     r = run_both(np.array([0], np.uint32), np.array([1], np.uint32), 2, B=8, k=100, dpb=8)
     assert r["bi"].h_p_b.sum() == 0 and r["q"].sum() == 0
