@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--max-bins", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples-per-bin", type=int, default=1 << 22)
+    ap.add_argument("--triangles", type=int, default=5_000_000,
+                    help="wedges of the global stream for the triangle sample (0: skip)")
     ap.add_argument("--no-cv", action="store_true",
                     help="skip the plain-EB / learned-CV comparison")
     ap.add_argument("--cv-train", type=int, default=10_000_000)
@@ -267,6 +269,26 @@ def main():
             + (f", learned-CV with exact mean {lx['closure_checks']} (eval "
                f"{lx['eval_checks']}, {lx['seconds']:.4f} s)" if lx else ""))
 
+    tri = None
+    if args.triangles > 0:
+        from paper_1301_5887_amd import triangles as TR
+        g = W.Csr(n=n, m=int(m), rowptr=rowptr, col=col)
+        bi = W.BinIndex(n=n, m=int(m), tau=2, omega=2, max_bins=B, n_b=n_b, p_b=p_b,
+                        index=index, h_n_b=h_nb.numpy().view(np.uint64).copy(),
+                        h_p_b=h_pb.numpy().view(np.uint64).copy())
+        for _ in range(2):      # the second, warm run is reported
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ts = TR.sample(g, bi, args.triangles, args.seed, max_bins=B, keep_triangles=False)
+            t_tri = time.perf_counter() - t0
+        tri = {"k": args.triangles, "triangles": ts.count,
+               "expected_k_times_c_global": args.triangles * est.glob["c_global"],
+               "seconds": round(t_tri, 5),
+               "assortativity": [[r["min_bin"], r["count"], r["q1"], r["median"], r["q3"]]
+                                 for r in ts.box]}
+        log(f"[bench] triangle sample: {ts.count} triangles from {args.triangles} wedges "
+            f"in {t_tri * 1e3:.2f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(src, dst, n, B, hk, kg, args, W, torch, workload)
@@ -295,6 +317,7 @@ def main():
         "roofline_csr": roofline_csr,
         "cpu_baseline": cpu,
         "estimators": cvcmp,
+        "triangle_sample": tri,
         "estimates": {"c": est.glob["c"], "c_global": est.glob["c_global"], "t": est.glob["t"],
                       "t_global": est.glob["t_global"], "eps": est.glob["eps_global"]},
         "paper_context": "Hadoop, 32 nodes: 225 s + 0.33 s per million edges",
@@ -322,11 +345,17 @@ def pmc_summarize(fetch_dir: str, write_dir: str, workload_k: int, copy_gib: flo
     total = 0.0
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _pmc_rows(d, name)
-        samp = [float(r["Counter_Value"]) for r in rows if "k_sample_close" in r["Kernel_Name"]]
-        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        if not samp or not copies:
-            raise SystemExit(f"no sampler or calibration copy dispatch under {d}")
-        cal = max(copies)
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not copies:
+            raise SystemExit(f"no calibration copy dispatch under {d}")
+        cal_row = max(copies, key=lambda r: float(r["Counter_Value"]))
+        cal = float(cal_row["Counter_Value"])
+        # the timed steps' sampler launches come before the calibration copy;
+        # later sampler work (the triangle sample) is not part of the step
+        samp = [float(r["Counter_Value"]) for r in rows if "k_sample_close" in r["Kernel_Name"]
+                and int(r["Dispatch_Id"]) < int(cal_row["Dispatch_Id"])]
+        if not samp:
+            raise SystemExit(f"no sampler dispatch before the calibration copy under {d}")
         factor = copy_kib / cal
         per_launch = sum(samp) / len(samp) * factor * 1024.0
         out[name.lower()] = {"kib_per_dispatch": sum(samp) / len(samp), "dispatches": len(samp),

@@ -487,6 +487,59 @@ int wedge_cv_centre_means(const uint64_t* d_rowptr, const uint32_t* d_col, uint3
                           uint32_t* d_vout, void* d_workspace, size_t workspace_bytes,
                           void* stream);
 
+/* ------------------------------------------------------------------------
+ * Triangle sample and degree assortativity (Sec. 3 theorem on sampled
+ * triangles; Sec. 5 triangle statistics).  A closed wedge of a uniform wedge
+ * sample is a uniform sample (with replacement) of the graph's triangles,
+ * since every triangle owns exactly three wedges.  The global stream (row
+ * max_bins) draws wedges uniformly from the whole graph, so its closed
+ * records are uniform triangles; the paper obtains the same with one bin
+ * (tau = 1, omega = 10^7).
+ *
+ * In:  d_rec[k]  feature records of one row (wedge_sample_features with
+ *                closure = 1; WEDGE_DOMAIN_SAMPLE reproduces the samples of
+ *                wedge_sample_close), k < 2^32.
+ * Out: d_tri     nullable wedge_triangle[k]: the closed records' degree
+ *                triples in record order (compacted: triangle j is the j-th
+ *                closed record); entries past the count are untouched.
+ *      d_count   device uint64[1]: number of closed records.
+ *      d_hist    device uint64[max_bins * max_bins], overwritten:
+ *                d_hist[BinId(d_min) * max_bins + BinId(d_max)] counts the
+ *                triangles, BinId with (tau, omega) (the paper groups with
+ *                tau = omega = 2); a triangle whose BinId(d_max) >= max_bins
+ *                is counted in d_count only.
+ * Workspace: wedge_triangle_stats_workspace(k) bytes.
+ * Errors: EINVAL, ERANGE (k >= 2^32, max_bins == 0 or > 64, tau == 0,
+ *         omega < 2), EWORKSPACE, EHIP.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t d_min, d_mid, d_max; /* degrees of the triangle's vertices, sorted */
+  uint32_t sample;              /* index of its record in d_rec */
+} wedge_triangle;
+
+size_t wedge_triangle_stats_workspace(uint64_t k);
+int wedge_triangle_stats(const wedge_feature_rec* d_rec, uint64_t k, uint32_t tau,
+                         uint64_t omega, uint32_t max_bins, wedge_triangle* d_tri,
+                         uint64_t* d_count, uint64_t* d_hist, void* d_workspace,
+                         size_t workspace_bytes, void* stream);
+
+/* Box-plot statistics of the max-degree bin of the triangles in each
+ * min-degree bin, from a host copy of d_hist (host only).  Percentiles are
+ * nearest-rank: the p-quantile of N values is the smallest bin b with at
+ * least ceil(p N) of them <= b; whiskers are the most extreme bins within
+ * 1.5 IQR of the quartiles (Tukey), outliers the triangles beyond them.
+ * h_out[max_bins]: row b describes the triangles whose BinId(d_min) = b
+ * (count 0: none). */
+typedef struct {
+  uint64_t count;
+  uint64_t outliers;
+  uint32_t q1, median, q3;
+  uint32_t whisker_lo, whisker_hi;
+  uint32_t pad;
+} wedge_triangle_box_row;
+
+int wedge_triangle_box(const uint64_t* h_hist, uint32_t max_bins, wedge_triangle_box_row* h_out);
+
 /* Empirical-Bernstein half-width (Maurer & Pontil 2009, Thm. 4, two-sided,
  * each side at delta/2) of the mean of n i.i.d. values in an interval of
  * length R with sample variance var:

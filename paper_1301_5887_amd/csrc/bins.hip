@@ -65,22 +65,6 @@ IndexView index_view(void* base, uint64_t n_total, uint64_t m_total, uint32_t G,
   return v;
 }
 
-// BinId(d) for d >= 1, or `limit` when the bin would be >= limit.
-__device__ inline uint32_t bin_of(uint64_t d, uint32_t tau, uint64_t omega, uint32_t limit) {
-  if (d <= tau) return d < limit ? (uint32_t)d : limit;
-  uint32_t b = tau;
-  uint64_t lo = tau, term = 1;
-  while (b < limit) {
-    uint64_t next = lo + term;
-    if (next < lo) next = ~0ULL;
-    if (next > d) break;
-    ++b;
-    lo = next;
-    if (__builtin_mul_overflow(term, omega, &term)) term = ~0ULL;
-  }
-  return b;
-}
-
 // Degree code floor(8 L(d)), L Mitchell's piecewise-linear log2 (0 for
 // d = 0): monotone in d, so comparing codes picks the shorter of two rows
 // whenever the codes differ.
@@ -186,7 +170,7 @@ __global__ void k_bin_accumulate(IndexView ix, uint64_t n, uint32_t tau, uint64_
     const uint64_t end = (j + 1 < C) ? ix.cls_start[j + 1] : n;
     const uint64_t cnt = end - ix.cls_start[j];
     const uint32_t g = graph_of(voff, G, ix.vlist[ix.cls_start[j]]);
-    const uint32_t b = d == 0 ? 0 : bin_of(d, tau, omega, max_bins);
+    const uint32_t b = d == 0 ? 0 : bin_id_capped(d, tau, omega, max_bins);
     if (d > 0) {
       if (b >= max_bins) {
         atomicAdd((unsigned long long*)&ix.hdr->overflow, (unsigned long long)cnt);
@@ -201,7 +185,7 @@ __global__ void k_bin_accumulate(IndexView ix, uint64_t n, uint32_t tau, uint64_
     if (j > 0) {
       const uint64_t dp = ix.cls_deg[j - 1];
       const uint32_t gp = graph_of(voff, G, ix.vlist[ix.cls_start[j - 1]]);
-      sprev = (int64_t)slot_of(gp, dp == 0 ? 0 : bin_of(dp, tau, omega, max_bins), max_bins);
+      sprev = (int64_t)slot_of(gp, dp == 0 ? 0 : bin_id_capped(dp, tau, omega, max_bins), max_bins);
     }
     for (int64_t t = sprev + 1; t <= (int64_t)s; ++t) first_cls[t] = (uint32_t)j;
     if (j == C - 1)

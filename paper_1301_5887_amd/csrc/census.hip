@@ -101,22 +101,6 @@ static size_t census_layout(uint32_t max_bins, uint64_t n, uint64_t class_cap, C
   return off;
 }
 
-__device__ __host__ inline uint32_t bin_of_census(uint64_t d, uint32_t tau, uint64_t omega,
-                                                  uint32_t limit) {
-  if (d <= tau) return d < limit ? (uint32_t)d : limit;
-  uint32_t b = tau;
-  uint64_t lo = tau, term = 1;
-  while (b < limit) {
-    uint64_t next = lo + term;
-    if (next < lo) next = ~0ULL;
-    if (next > d) break;
-    ++b;
-    lo = next;
-    if (__builtin_mul_overflow(term, omega, &term)) term = ~0ULL;
-  }
-  return b;
-}
-
 // The (bin, bucket) keys that degrees >= 2 can take, numbered in increasing
 // degree order (bucket, then bin: both are monotone in the degree).  Thread k
 // takes bucket k; an exclusive scan of the per-bucket key counts numbers them.
@@ -130,8 +114,8 @@ __global__ __launch_bounds__(256) void k_census_keys(CensusView C, uint32_t tau,
   if (hi > 0xFFFFFFFFULL) hi = 0xFFFFFFFFULL;
   uint32_t b0 = 0, cnt = 0;
   if (hi >= 2 && lo <= hi) {
-    b0 = bin_of_census(lo, tau, omega, max_bins);
-    const uint32_t b1 = bin_of_census(hi, tau, omega, max_bins);  // bins b0 .. b1 hold degrees here
+    b0 = bin_id_capped(lo, tau, omega, max_bins);
+    const uint32_t b1 = bin_id_capped(hi, tau, omega, max_bins);  // bins b0 .. b1 hold degrees here
     if (b0 < max_bins) cnt = (b1 < max_bins ? b1 : max_bins - 1) - b0 + 1;
   }
   const uint32_t incl = wave_incl_scan(cnt, (int)lane);
@@ -210,7 +194,7 @@ __device__ inline uint64_t position_of_work(const IndexView& ix, const uint64_t*
 __device__ inline uint32_t key_of_degree(const CensusView& C, uint64_t d, uint32_t tau,
                                          uint64_t omega, uint32_t max_bins) {
   if (d < 2) return kNoKey;
-  const uint32_t b = bin_of_census(d, tau, omega, max_bins);
+  const uint32_t b = bin_id_capped(d, tau, omega, max_bins);
   if (b >= max_bins) return kNoKey;
   return C.key_of[b * kBuckets + bucket_of(d)];
 }

@@ -134,6 +134,24 @@ __host__ __device__ inline uint64_t bin_lo_deg(uint32_t b, uint32_t tau, uint64_
   return lo;
 }
 
+// BinId(d) of the integer reading of Eq. binid for d >= 1 (the largest b
+// with BinLoDeg(b) <= d), or `limit` when that bin would be >= limit.
+__host__ __device__ inline uint32_t bin_id_capped(uint64_t d, uint32_t tau, uint64_t omega,
+                                                  uint32_t limit) {
+  if (d <= tau) return d < limit ? (uint32_t)d : limit;
+  uint32_t b = tau;
+  uint64_t lo = tau, term = 1;
+  while (b < limit) {
+    uint64_t next = lo + term;
+    if (next < lo) next = ~0ULL;
+    if (next > d) break;
+    ++b;
+    lo = next;
+    if (__builtin_mul_overflow(term, omega, &term)) term = ~0ULL;
+  }
+  return b;
+}
+
 // Key id of every (bin, centre bucket) in a census buffer ([max_bins][256]
 // uint32, 0xFFFFFFFF where degrees >= 2 cannot take the pair).
 const uint32_t* census_key_of(const void* d_census, uint32_t max_bins);

@@ -38,22 +38,6 @@ struct TileSmem {
   uint64_t item[2];
 };
 
-// BinId(d) of the integer reading of Eq. binid, capped at limit.
-__device__ inline uint32_t bin_of_degree(uint64_t d, uint32_t tau, uint64_t omega, uint32_t limit) {
-  if (d <= tau) return d < limit ? (uint32_t)d : limit;
-  uint32_t b = tau;
-  uint64_t lo = tau, term = 1;
-  while (b < limit) {
-    uint64_t next = lo + term;
-    if (next < lo) next = ~0ULL;
-    if (next > d) break;
-    ++b;
-    lo = next;
-    if (__builtin_mul_overflow(term, omega, &term)) term = ~0ULL;
-  }
-  return b;
-}
-
 // The row's cumulative-wedge table in LDS: one entry per class, or the last
 // class of every group of S when the row has more classes than LDS holds.
 struct StagedRow {
@@ -308,7 +292,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
         fr.dv = (uint32_t)d[u];
         fr.dlo = (uint32_t)min(da[u], dc[u]);
         fr.dhi = (uint32_t)max(da[u], dc[u]);
-        fr.bin = (uint16_t)bin_of_degree(d[u], A.tau, A.omega, A.max_bins);
+        fr.bin = (uint16_t)bin_id_capped(d[u], A.tau, A.omega, A.max_bins);
         fr.closed = found[u] ? 1 : 0;
         fr.cls = (uint8_t)cls;
         A.feat[fslot * A.feat_stride + (s[u] - sbase)] = fr;
@@ -476,7 +460,7 @@ __global__ __launch_bounds__(kSampWG) void k_centre_means(const SamplerCtx A, co
     const uint64_t rp = A.ix.vrow[vi];
     const uint64_t idx = T.task[e].slot * C.stride + (s - sbase);
     if (C.vout) C.vout[idx] = A.ix.vlist[vi];
-    const uint32_t bin = bw == kGlobalWord ? bin_of_degree(d, A.tau, A.omega, A.max_bins) : f;
+    const uint32_t bin = bw == kGlobalWord ? bin_id_capped(d, A.tau, A.omega, A.max_bins) : f;
     const uint32_t ke = 63 - (uint32_t)__builtin_clzll(d);
     const uint32_t kb = 8 * ke + (uint32_t)(((d - (1ULL << ke)) * 8) >> ke);
     const uint32_t key = bin < A.max_bins ? C.key_of[bin * 256 + (kb < 255 ? kb : 255)]

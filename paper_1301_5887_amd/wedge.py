@@ -33,6 +33,12 @@ class WedgeSampleRec(ctypes.Structure):
                 ("cls", ctypes.c_uint32)]
 
 
+class WedgeTriangleBoxRow(ctypes.Structure):
+    _fields_ = [("count", _c_u64), ("outliers", _c_u64), ("q1", _c_u32), ("median", _c_u32),
+                ("q3", _c_u32), ("whisker_lo", _c_u32), ("whisker_hi", _c_u32),
+                ("pad", _c_u32)]
+
+
 class WedgeBinEstimate(ctypes.Structure):
     _fields_ = [("bin", ctypes.c_uint32), ("valid", ctypes.c_uint32), ("lo_deg", _c_u64),
                 ("n_b", _c_u64), ("p_b", _c_u64), ("k_b", _c_u64), ("q", _c_u64 * 4),
@@ -123,6 +129,10 @@ SIGNATURES = {
     "wedge_cv_centre_means": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _c_u32,
                                              _c_u64, _vp, _vp, _c_u64, _c_u32, _c_u32, _vp,
                                              _vp, _vp, _c_u64, _vp, _vp, ctypes.c_size_t, _vp]),
+    "wedge_triangle_stats_workspace": (ctypes.c_size_t, [_c_u64]),
+    "wedge_triangle_stats": (ctypes.c_int, [_vp, _c_u64, _c_u32, _c_u64, _c_u32, _vp, _vp, _vp,
+                                            _vp, ctypes.c_size_t, _vp]),
+    "wedge_triangle_box": (ctypes.c_int, [_vp, _c_u32, _vp]),
     "wedge_eb_halfwidth": (ctypes.c_double, [_c_u64, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double]),
     "wedge_cv_census_bytes": (ctypes.c_size_t, [_c_u32, _c_u64, _c_u32]),

@@ -199,3 +199,40 @@ def test_cv_row_estimate_matches_oracle_formula():
     b = C.beta_from_moments([st.n, st.sx, st.sg, st.sg2, st.sxg])
     ref_b = np.cov(X, g, bias=True)[0, 1] / np.var(g)
     assert b == pytest.approx(ref_b, rel=1e-6)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_triangle_box_matches_oracle(seed):
+    """wedge_triangle_box (host only) on a histogram against the oracle's box
+    statistics of the explicit value lists it was made from."""
+    from oracle import triangle_oracle as TO
+    from paper_1301_5887_amd import triangles as TR
+
+    rng = np.random.default_rng(seed)
+    B = 24
+    groups = {}
+    for b in rng.choice(B, size=int(rng.integers(1, 10)), replace=False):
+        vals = list(rng.integers(int(b), B, int(rng.integers(1, 400))))
+        if seed == 0 and not groups:
+            vals = [int(b)] * 40 + [B - 1]          # a far outlier
+        groups[int(b)] = vals
+    h = np.zeros((B, B), dtype=np.uint64)
+    for b, vals in groups.items():
+        for x in vals:
+            h[b, x] += 1
+    got = TR.box(h)
+    assert [r["min_bin"] for r in got] == sorted(groups)
+    for r in got:
+        ref = TO.box(groups[r["min_bin"]])
+        for key in ("count", "q1", "median", "q3", "whisker_lo", "whisker_hi", "outliers"):
+            assert r[key] == ref[key], (r, ref)
+
+
+def test_triangle_stats_validation():
+    L = W.lib()
+    z = ctypes.c_void_p(256)
+    assert L.wedge_triangle_stats(z, 10, 2, 2, 65, None, z, z, z, 1 << 20, None) == -2
+    assert L.wedge_triangle_stats(z, 1 << 32, 2, 2, 16, None, z, z, z, 1 << 20, None) == -2
+    assert L.wedge_triangle_stats(z, 10, 2, 2, 16, None, None, z, z, 1 << 20, None) == -1
+    assert L.wedge_triangle_stats(z, 10, 2, 2, 16, None, z, z, z, 0, None) == -3
+    assert L.wedge_triangle_box(None, 16, None) == -1
