@@ -75,6 +75,12 @@ def lib():
                                  ctypes.c_uint64, ctypes.c_uint64, _u64p,
                                  _u32p, _u32p, _u32p, _u8p, ctypes.c_uint64, ctypes.c_int]
         L.orc_sample.restype = ctypes.c_int
+        L.orc_sample_alloc.argtypes = [_u64p, _u32p, ctypes.c_uint32, _u64p, ctypes.c_uint64,
+                                       ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, _u64p,
+                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                       ctypes.c_uint64, _u64p, _u64p, _u32p, _u32p, _u32p, _u8p,
+                                       ctypes.c_uint64]
+        L.orc_sample_alloc.restype = ctypes.c_int
         L.orc_exact.argtypes = [_u64p, _u32p, ctypes.c_uint32, _u64p, ctypes.c_uint64,
                                 ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, _u64p]
         L.orc_exact.restype = ctypes.c_int
@@ -229,6 +235,44 @@ def sample(g: Graph, tau: int, omega: int, max_bins: int, k_per_bin, k_global: i
                    a=None if da is None else da.reshape(shp),
                    c=None if dc is None else dc.reshape(shp),
                    cls=None if dcls is None else dcls.reshape(shp))
+
+
+DOMAIN_ALLOC = 7
+
+
+def sample_alloc(g: Graph, tau: int, omega: int, max_bins: int, k_per_bin, k_global: int,
+                 seed: int, graph_id: int = 0, dump_per_bin: int = 0,
+                 domain: int = DOMAIN_ALLOC):
+    """Phase 2a allocation (Alg. phase2a) and per-vertex sampling: returns
+    (Samples with q and dumps, totals[max_bins + 1] = samples drawn per row)."""
+    k = np.ascontiguousarray(k_per_bin, dtype=np.uint64)
+    assert k.shape[0] == max_bins
+    rows = max_bins + 1
+    q = np.zeros(rows * 4, dtype=np.uint64)
+    tot = np.zeros(rows, dtype=np.uint64)
+    if dump_per_bin > 0:
+        dv = np.zeros(rows * dump_per_bin, dtype=np.uint32)
+        da = np.zeros_like(dv)
+        dc = np.zeros_like(dv)
+        dcls = np.zeros(rows * dump_per_bin, dtype=np.uint8)
+        ptrs = (_p(dv, _u32p), _p(da, _u32p), _p(dc, _u32p), _p(dcls, _u8p))
+    else:
+        dv = da = dc = dcls = None
+        ptrs = (None, None, None, None)
+    keys = g.keys if g.m > 0 else np.zeros(1, dtype=np.uint64)
+    col = g.col if g.col.size > 0 else np.zeros(1, dtype=np.uint32)
+    rc = lib().orc_sample_alloc(_p(g.rowptr, _u64p), _p(col, _u32p), g.n, _p(keys, _u64p), g.m,
+                                tau, omega, max_bins, _p(k, _u64p), k_global, seed, graph_id,
+                                domain, _p(q, _u64p), _p(tot, _u64p), *ptrs, dump_per_bin)
+    if rc != 0:
+        raise ValueError("oracle sample_alloc: bad input")
+    shp = (rows, dump_per_bin)
+    s = Samples(q=q.reshape(rows, 4),
+                v=None if dv is None else dv.reshape(shp),
+                a=None if da is None else da.reshape(shp),
+                c=None if dc is None else dc.reshape(shp),
+                cls=None if dcls is None else dcls.reshape(shp))
+    return s, tot
 
 
 def exact(g: Graph, tau: int, omega: int, max_bins: int) -> np.ndarray:

@@ -413,6 +413,89 @@ int orc_sample(const uint64_t* rowptr, const uint32_t* col, uint32_t n, const ui
   return bad ? -1 : 0;
 }
 
+// ------------------------------------------------- Phase 2a allocation mode
+// Alg. phase2a then the Sampling procedure of Alg. phase2c: every vertex v of
+// a row (bin b, or the whole graph for the global row) with d >= 2 gets
+// q_v = floor(q*) or ceil(q*) samples, q* = C(d,2) k / p_row, ceil with
+// probability q* - floor(q*) exactly (so E[q_v] = q*); the printed test
+// "x >= frac ? ceil : floor" would give ceil with probability 1 - frac, which
+// contradicts the text's example, so the text is followed).  The rounding draw
+// of v is uniform on [0, p_row) from word 2 of Philox blocks (v, b, g, r) and
+// rounds up iff it is below (C(d,2) k) mod p_row.  Samples are numbered s = 0,
+// 1, ... through the row's vertices in (degree, id) order; sample s at v takes
+// its ordered neighbour pair from word 1 of blocks (s, b, g, r), as the
+// i.i.d. sampler does.  Key (seed, domain).  Outputs: q[row][4] class counts,
+// totals[row] = sum of q_v, and the first dump_per_bin samples of each row.
+int orc_sample_alloc(const uint64_t* rowptr, const uint32_t* col, uint32_t n,
+                     const uint64_t* keys, uint64_t m, uint32_t tau, uint64_t omega,
+                     uint32_t max_bins, const uint64_t* k_per_bin, uint64_t k_global,
+                     uint64_t seed, uint32_t graph_id, uint64_t domain, uint64_t* q,
+                     uint64_t* totals, uint32_t* dump_v, uint32_t* dump_a, uint32_t* dump_c,
+                     uint8_t* dump_cls, uint64_t dump_per_bin) {
+  for (uint64_t i = 0; i < (uint64_t)(max_bins + 1) * 4; ++i) q[i] = 0;
+  for (uint32_t r = 0; r <= max_bins; ++r) totals[r] = 0;
+  std::vector<uint64_t> deg(n);
+  std::vector<uint32_t> vbin(n, 0);
+  BinTable bins(tau, omega, max_bins);
+  for (uint32_t v = 0; v < n; ++v) {
+    deg[v] = rowptr[v + 1] - rowptr[v];
+    if (deg[v] == 0) continue;
+    uint32_t b = bins(deg[v]);
+    if (b >= max_bins) return -1;
+    vbin[v] = b;
+  }
+  std::vector<std::pair<uint64_t, uint32_t>> dv;
+  for (uint32_t v = 0; v < n; ++v)
+    if (deg[v] >= 2) dv.push_back({deg[v], v});
+  std::sort(dv.begin(), dv.end());
+  std::vector<std::vector<uint32_t>> L(max_bins + 1);
+  std::vector<uint64_t> pb(max_bins + 1, 0);
+  for (auto& e : dv) {
+    L[vbin[e.second]].push_back(e.second);
+    L[max_bins].push_back(e.second);
+    pb[vbin[e.second]] += choose2(e.first);
+    pb[max_bins] += choose2(e.first);
+  }
+  int bad = 0;
+  for (uint32_t row = 0; row <= max_bins; ++row) {
+    const bool global = (row == max_bins);
+    const uint64_t k = global ? k_global : k_per_bin[row];
+    if (k == 0) continue;
+    if (L[row].empty()) { bad = 1; continue; }
+    const uint64_t bin_word = global ? kGlobalBin : row;
+    const uint64_t p = pb[row];
+    uint64_t s = 0;
+    for (uint32_t v : L[row]) {
+      const u128 num = (u128)choose2(deg[v]) * k;
+      uint64_t qv = (uint64_t)(num / p);
+      const uint64_t rem = (uint64_t)(num % p);
+      if (draw_below(seed, domain, v, bin_word, graph_id, 2, p) < rem) ++qv;
+      const uint64_t d = deg[v];
+      for (uint64_t j = 0; j < qv; ++j, ++s) {
+        uint64_t o = draw_below(seed, domain, s, bin_word, graph_id, 1, d * (d - 1));
+        uint64_t i = o / (d - 1);
+        uint64_t r = o % (d - 1);
+        uint64_t j2 = r + (r >= i ? 1 : 0);
+        uint32_t a = col[rowptr[v] + i];
+        uint32_t c = col[rowptr[v] + j2];
+        uint8_t cls = 0;
+        if (has_edge(keys, m, a, c))
+          cls = global ? 3 : (uint8_t)(1 + (vbin[a] == row ? 1 : 0) + (vbin[c] == row ? 1 : 0));
+        q[row * 4 + cls] += 1;
+        if (dump_v && s < dump_per_bin) {
+          uint64_t at = (uint64_t)row * dump_per_bin + s;
+          dump_v[at] = v;
+          dump_a[at] = a;
+          dump_c[at] = c;
+          dump_cls[at] = cls;
+        }
+      }
+    }
+    totals[row] = s;
+  }
+  return bad ? -1 : 0;
+}
+
 // --------------------------------------------------------------- exact mode
 // Definitions of Sec. 2.1/2.2 by enumeration: for every centre v and every
 // pair of distinct neighbours {a, c}, the wedge is closed iff {a,c} in E.
