@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--cpu-samples-per-bin", type=int, default=1 << 22)
     ap.add_argument("--triangles", type=int, default=5_000_000,
                     help="wedges of the global stream for the triangle sample (0: skip)")
+    ap.add_argument("--alloc-seeds", type=int, default=0,
+                    help="compare the Phase 2a allocation sampler with the i.i.d. one over "
+                         "this many seeds (0: skip)")
     ap.add_argument("--no-cv", action="store_true",
                     help="skip the plain-EB / learned-CV comparison")
     ap.add_argument("--cv-train", type=int, default=10_000_000)
@@ -269,6 +272,46 @@ def main():
             + (f", learned-CV with exact mean {lx['closure_checks']} (eval "
                f"{lx['eval_checks']}, {lx['seconds']:.4f} s)" if lx else ""))
 
+    alloc = None
+    if args.alloc_seeds > 0:
+        # the paper's allocation (Alg. phase2a) against the i.i.d. draws at the
+        # same k: time of one sampling of every row, and the spread of the
+        # per-bin and global c estimates over independent seeds
+        g = W.Csr(n=n, m=int(m), rowptr=rowptr, col=col)
+        bi = W.BinIndex(n=n, m=int(m), tau=2, omega=2, max_bins=B, n_b=n_b, p_b=p_b,
+                        index=index, h_n_b=h_nb.numpy().view(np.uint64).copy(),
+                        h_p_b=h_pb.numpy().view(np.uint64).copy())
+        aws = W.Workspace(dev)
+        est_i, est_a, t_i, t_a = [], [], [], []
+        for r in range(args.alloc_seeds + 1):
+            sd = args.seed + 5000 + r
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            so = W.sample_close(g, bi, hk, kg, sd)
+            qi = W.to_host_u64(so.q).reshape(B + 1, 4)
+            t1 = time.perf_counter()
+            sa, tot = W.sample_alloc(g, bi, hk, kg, sd, ws=aws)
+            qa = W.to_host_u64(sa.q).reshape(B + 1, 4)
+            t2 = time.perf_counter()
+            if r == 0:
+                continue        # the first round pays one-time costs
+            t_i.append(t1 - t0)
+            t_a.append(t2 - t1)
+            est_i.append(qi[:, 1:].sum(axis=1) / np.maximum(np.append(hk, kg), 1))
+            est_a.append(qa[:, 1:].sum(axis=1) / np.maximum(tot, 1).astype(np.float64))
+        ei, ea = np.array(est_i), np.array(est_a)
+        rows_s = [r for r in range(B + 1) if (r == B and kg) or (r < B and hk[r])]
+        alloc = {"seeds": args.alloc_seeds, "k": k,
+                 "iid_ms": round(1e3 * float(np.median(t_i)), 3),
+                 "alloc_ms": round(1e3 * float(np.median(t_a)), 3),
+                 "per_row": {("global" if r == B else str(r)):
+                             {"var_ratio_alloc_over_iid":
+                              round(float(ea[:, r].var(ddof=1) / max(ei[:, r].var(ddof=1), 1e-30)), 4),
+                              "mean_iid": float(ei[:, r].mean()), "mean_alloc": float(ea[:, r].mean())}
+                             for r in rows_s}}
+        log(f"[bench] allocation form: {alloc['alloc_ms']} ms per sampling (i.i.d. "
+            f"{alloc['iid_ms']} ms) over {args.alloc_seeds} seeds")
+
     tri = None
     if args.triangles > 0:
         from paper_1301_5887_amd import triangles as TR
@@ -318,6 +361,7 @@ def main():
         "cpu_baseline": cpu,
         "estimators": cvcmp,
         "triangle_sample": tri,
+        "allocation_form": alloc,
         "estimates": {"c": est.glob["c"], "c_global": est.glob["c_global"], "t": est.glob["t"],
                       "t_global": est.glob["t_global"], "eps": est.glob["eps_global"]},
         "paper_context": "Hadoop, 32 nodes: 225 s + 0.33 s per million edges",

@@ -355,7 +355,7 @@ typedef struct {
 
 /* Philox key domains of the streams (key word 1). */
 enum { WEDGE_DOMAIN_SAMPLE = 1, WEDGE_DOMAIN_TRAIN = 2, WEDGE_DOMAIN_AUX = 3,
-       WEDGE_DOMAIN_EVAL = 4, WEDGE_DOMAIN_CENTRE = 6 };
+       WEDGE_DOMAIN_EVAL = 4, WEDGE_DOMAIN_CENTRE = 6, WEDGE_DOMAIN_ALLOC = 7 };
 
 /* The sampler of wedge_sample_close with key (seed, domain), samples
  * s = s_begin[r] .. s_begin[r] + h_k[r] - 1 of every row r (bins r < max_bins
@@ -486,6 +486,36 @@ int wedge_cv_centre_means(const uint64_t* d_rowptr, const uint32_t* d_col, uint3
                           const float* d_gtable, float* d_out, uint64_t out_stride,
                           uint32_t* d_vout, void* d_workspace, size_t workspace_bytes,
                           void* stream);
+
+/* ------------------------------------------------------------------------
+ * wedge_sample_alloc -- the paper's own sample allocation (Alg. phase2a)
+ * followed by the Sampling procedure of Alg. phase2c, as an alternative to
+ * the i.i.d. draws of wedge_sample_close.
+ *
+ * For every row r (bin r < max_bins with h_k[r] > 0, and the global stream
+ * r = max_bins when k_global > 0) each vertex v of the row with d >= 2 gets
+ * q_v samples: q* = C(d,2) k_r / p_r rounded down, plus one with probability
+ * equal to its fractional part exactly (E[q_v] = q*; the rounding draw of v
+ * is uniform on [0, p_r) from word 2 of Philox blocks (v, row word, 0, retry)
+ * under key (seed, WEDGE_DOMAIN_ALLOC) and rounds up iff it is below
+ * (C(d,2) k_r) mod p_r).  The row's samples are numbered s = 0 .. Q_r - 1
+ * through its vertices in the centre order (degree, id); sample s at v takes
+ * the ordered neighbour pair of wedge_sample_close from word 1 of blocks
+ * (s, row word, 0, retry), is closure-tested and classified as there.
+ * Out: d_q[(max_bins+1)*4] class counts (overwritten); h_totals[max_bins+1]
+ *      (host) the realised totals Q_r, the denominators of the estimates
+ *      (pass them to wedge_estimate as the per-row sample counts);
+ *      d_dump (nullable) as in wedge_sample_close.
+ * Reads the totals back, so it synchronises the stream.  A row whose p_r is
+ * 0 draws nothing.  Workspace: wedge_sample_alloc_workspace(n, max_bins).
+ * Errors: as wedge_sample_close, plus EWORKSPACE.
+ * ---------------------------------------------------------------------- */
+size_t wedge_sample_alloc_workspace(uint32_t n, uint32_t max_bins);
+int wedge_sample_alloc(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
+                       const void* d_index, uint32_t max_bins, const uint64_t* h_k,
+                       uint64_t k_global, uint64_t seed, uint64_t* d_q, uint64_t* h_totals,
+                       wedge_sample_rec* d_dump, uint64_t dump_per_bin, void* d_workspace,
+                       size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Triangle sample and degree assortativity (Sec. 3 theorem on sampled

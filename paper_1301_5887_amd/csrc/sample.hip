@@ -22,6 +22,8 @@
 // pulls tiles of every (graph, bin) row of a batch from a device work queue.
 #include "common.hpp"
 #include "rng.hpp"
+#include <vector>
+
 #include "sample.hpp"
 #include "scan.hpp"
 
@@ -36,6 +38,7 @@ struct TileSmem {
   uint32_t start[kLdsClasses];
   unsigned long long red[5];
   uint64_t item[2];
+  uint64_t arange[2];  // allocation form: the tile's first and last vertex
 };
 
 // The row's cumulative-wedge table in LDS: one entry per class, or the last
@@ -93,8 +96,20 @@ __device__ inline void centre_of(const SamplerCtx& A, const TileSmem& sm, const 
   *vi = v;
 }
 
+// Allocation form: the row position i in [lo, hi) of the vertex holding
+// sample s, i.e. the last i with pre[off + i] <= pre[off] + s.
+__device__ inline uint64_t alloc_vertex(const SamplerCtx& A, const AllocRow& R, uint64_t s,
+                                        uint64_t lo, uint64_t hi) {
+  const uint64_t g = A.alloc_pre[R.off] + s;
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (A.alloc_pre[R.off + mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // One tile: samples [s0, s1) of index row f (graph g, bin word bword).
-template <int U>
+template <int U, bool kAlloc = false>
 __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint32_t bword,
                             uint64_t gword, uint64_t s0, uint64_t s1, uint64_t fslot,
                             uint64_t sbase) {
@@ -108,6 +123,11 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
   const bool global = (bword == kGlobalWord);
   const StagedRow R = stage_row(A, sm, M);
   if (tid < 5) sm.red[tid] = 0;
+  AllocRow AR{0, 0, 0, 0};
+  if (kAlloc) {
+    AR = A.alloc[f];
+    if (tid < 2) sm.arange[tid] = alloc_vertex(A, AR, tid == 0 ? s0 : s1 - 1, 0, AR.count);
+  }
   __syncthreads();
 
   const uint64_t seed = A.seed;
@@ -131,15 +151,25 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       x1[u] = 0;
       if (act[u]) {
         const U64x4 o = philox4x64_10(s[u], bw, gword, 0, seed, A.domain);
-        W[u] = M.cumw_base + below_from(o.w[0], M.p_b, seed, A.domain, s[u], bw, gword, 0);
+        if (!kAlloc)
+          W[u] = M.cumw_base + below_from(o.w[0], M.p_b, seed, A.domain, s[u], bw, gword, 0);
         x1[u] = o.w[1];
       }
     }
-    // 2. the centre: class by the staged table, then the vertex
+    // 2. the centre: class by the staged table, then the vertex (allocation
+    //    form: the vertex whose share of the row's samples holds s)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       uint64_t dd = 2, vv = 0;
-      if (act[u]) centre_of(A, sm, M, R, W[u], &dd, &vv);
+      if (act[u]) {
+        if (kAlloc) {
+          vv = AR.pos_lo + alloc_vertex(A, AR, s[u], sm.arange[0], sm.arange[1] + 1);
+          const uint32_t x = A.ix.vlist[vv];
+          dd = A.rowptr[x + 1] - A.rowptr[x];
+        } else {
+          centre_of(A, sm, M, R, W[u], &dd, &vv);
+        }
+      }
       d[u] = dd;
       vi[u] = vv;
     }
@@ -326,7 +356,7 @@ __device__ inline bool header_ok(const SamplerCtx& A) {
          H->num_graphs == A.num_graphs;
 }
 
-template <int U>
+template <int U, bool kAlloc = false>
 __global__ __launch_bounds__(kSampWG, U == 1 ? 8 : 1) void k_sample_close(const SamplerCtx A, const TaskTable T) {
   __shared__ TileSmem sm;
   const uint64_t tile = blockIdx.x;
@@ -341,8 +371,8 @@ __global__ __launch_bounds__(kSampWG, U == 1 ? 8 : 1) void k_sample_close(const 
     if (threadIdx.x == 0) atomicAdd((unsigned long long*)&A.ix.hdr->mismatch, 1ULL);
     return;
   }
-  sample_tile<U>(A, sm, T.task[e].row, T.task[e].bword, T.graph_word, s0, s1, T.task[e].slot,
-                 sbase);
+  sample_tile<U, kAlloc>(A, sm, T.task[e].row, T.task[e].bword, T.graph_word, s0, s1,
+                         T.task[e].slot, sbase);
 }
 
 // Persistent form: tiles of all (graph, row) pairs of a batch come from a
@@ -580,6 +610,11 @@ static int launch_tasks(const SamplerCtx& A, TaskTable& T, int U, hipStream_t st
   }
   if (tiles == 0) return WEDGE_OK;
   if (tiles > 0x7FFFFFFFULL) return set_error(WEDGE_ERANGE, "wedge_sample_close: too many tiles");
+  if (A.alloc) {
+    k_sample_close<1, true><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T);
+    WEDGE_LAUNCH_CHECK("k_sample_close");
+    return WEDGE_OK;
+  }
   switch (U) {
     case 1: k_sample_close<1><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T); break;
     case 2: k_sample_close<2><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T); break;
@@ -676,6 +711,84 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
   }
   if (T.ntask > 0 && (rc = launch_tasks(A, T, t.U, st))) return rc;
   return WEDGE_OK;
+}
+
+// ------------------------------------------------------- allocation form
+// Alg. phase2a on the index: the rows' vertex ranges, the per-vertex counts
+// by probabilistic rounding, and the rows' realised totals.
+constexpr uint64_t kDomainAlloc = 7;
+
+// floor((hi * 2^64 + lo) / p) and the remainder, for hi < p (restoring
+// division, one quotient bit per step).
+__device__ inline void divmod_128_64(uint64_t hi, uint64_t lo, uint64_t p, uint64_t* q,
+                                     uint64_t* r) {
+  uint64_t rem = hi, quo = 0;
+  for (int b = 63; b >= 0; --b) {
+    const uint64_t top = rem >> 63;
+    rem = (rem << 1) | (lo >> 63);
+    lo <<= 1;
+    if (top || rem >= p) {
+      rem -= p;
+      quo |= 1ULL << b;
+    }
+  }
+  *q = quo;
+  *r = rem;
+}
+
+// Row table: vertex range of every row with samples (its classes are
+// consecutive in the centre order) and the rows' offsets in the count array.
+__global__ void k_alloc_rows(IndexView ix, const uint64_t* __restrict__ k, uint32_t max_bins,
+                             AllocRow* __restrict__ rows) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t off = 0;
+  for (uint32_t f = 0; f <= max_bins; ++f) {
+    const BinMeta M = ix.bins[f];
+    AllocRow r{off, 0, 0, k[f]};
+    if (k[f] > 0 && M.p_b > 0 && M.cls_lo < M.cls_hi) {
+      const uint32_t j = M.cls_hi - 1;
+      const uint64_t dj = ix.cls_deg[j];
+      const uint64_t prev = j > 0 ? ix.cls_cumw[j - 1] : 0;
+      const uint64_t last = (ix.cls_cumw[j] - prev) / (dj * (dj - 1) / 2);
+      r.pos_lo = ix.cls_start[M.cls_lo];
+      r.count = ix.cls_start[j] + last - r.pos_lo;
+    } else {
+      r.k = 0;
+    }
+    rows[f] = r;
+    off += r.count;
+  }
+}
+
+// q_v = floor(q*) + [U(p) < (C(d,2) k) mod p], q* = C(d,2) k / p, for every
+// vertex of row blockIdx.y; the draw is word 2 of blocks (v, row word, g, r).
+__global__ void k_alloc_round(const uint64_t* __restrict__ rowptr, IndexView ix,
+                              const AllocRow* __restrict__ rows, uint32_t max_bins, uint64_t seed,
+                              uint64_t domain, uint64_t gword, uint64_t* __restrict__ qv) {
+  const uint32_t f = blockIdx.y;
+  const AllocRow R = rows[f];
+  if (R.count == 0) return;
+  const uint64_t p = ix.bins[f].p_b;
+  const uint64_t bw = f == max_bins ? kGlobalWord : f;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < R.count; i += stride) {
+    const uint32_t v = ix.vlist[R.pos_lo + i];
+    const uint64_t d = rowptr[v + 1] - rowptr[v];
+    const uint64_t a = d * (d - 1) / 2;
+    uint64_t fl, rem;
+    divmod_128_64(__umul64hi(a, R.k), a * R.k, p, &fl, &rem);
+    const U64x4 o = philox4x64_10(v, bw, gword, 0, seed, domain);
+    const uint64_t w = below_from(o.w[2], p, seed, domain, v, bw, gword, 2);
+    qv[R.off + i] = fl + (w < rem ? 1 : 0);
+  }
+}
+
+__global__ void k_alloc_totals(const AllocRow* __restrict__ rows, uint32_t nrows,
+                               const uint64_t* __restrict__ pre, uint64_t* __restrict__ tot) {
+  for (uint32_t f = threadIdx.x; f < nrows; f += blockDim.x) {
+    const AllocRow R = rows[f];
+    tot[f] = R.count ? pre[R.off + R.count] - pre[R.off] : 0;
+  }
 }
 
 static int launch_centre_tasks(const SamplerCtx& A, TaskTable& T, const CentreArgs& C,
@@ -787,6 +900,139 @@ extern "C" int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d
     K.k = h_k[b];
     K.s_begin = h_s_begin ? h_s_begin[b] : 0;
     K.slot = slot++;
+    if (T.ntask == kMaxTasks) {
+      if ((rc = launch_tasks(A, T, t.U, st))) return rc;
+      T.ntask = 0;
+    }
+  }
+  if (T.ntask > 0 && (rc = launch_tasks(A, T, t.U, st))) return rc;
+  return WEDGE_OK;
+}
+
+struct AllocWorkspace {
+  AllocRow* rows;
+  uint64_t* k;
+  uint64_t* tot;
+  uint64_t* qv;
+  uint64_t* scan_ws;
+};
+
+static size_t alloc_layout(uint32_t n, uint32_t max_bins, AllocWorkspace* w, void* base) {
+  char* c = (char*)base;
+  size_t off = 0;
+  const uint64_t rows = (uint64_t)max_bins + 1;
+  const uint64_t N = 2 * (uint64_t)n + 1;
+  auto take = [&](size_t bytes) {
+    char* p = c + off;
+    off += round_up(bytes, 256);
+    return p;
+  };
+  AllocWorkspace x;
+  x.rows = (AllocRow*)take(rows * sizeof(AllocRow));
+  x.k = (uint64_t*)take(rows * 8);
+  x.tot = (uint64_t*)take(rows * 8);
+  x.qv = (uint64_t*)take(N * 8);
+  x.scan_ws = (uint64_t*)take(scan_ws_elems(N) * 8);
+  if (w) *w = x;
+  return off;
+}
+
+extern "C" size_t wedge_sample_alloc_workspace(uint32_t n, uint32_t max_bins) {
+  return alloc_layout(n, max_bins, nullptr, nullptr);
+}
+
+extern "C" int wedge_sample_alloc(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
+                                  uint64_t m, const void* d_index, uint32_t max_bins,
+                                  const uint64_t* h_k, uint64_t k_global, uint64_t seed,
+                                  uint64_t* d_q, uint64_t* h_totals, wedge_sample_rec* d_dump,
+                                  uint64_t dump_per_bin, void* d_workspace,
+                                  size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (n == 0) return set_error(WEDGE_ERANGE, "wedge_sample_alloc: n must be >= 1");
+  if (max_bins == 0 || max_bins > 4096)
+    return set_error(WEDGE_ERANGE, "wedge_sample_alloc: max_bins must be in [1, 4096]");
+  if (!d_rowptr || !d_index || !h_k || !d_q || !h_totals || !d_workspace)
+    return set_error(WEDGE_EINVAL, "wedge_sample_alloc: null pointer");
+  if (!aligned(d_rowptr, 8) || !aligned(d_index, 256) || !aligned(d_q, 8) ||
+      !aligned(d_col, 4) || !aligned(d_dump, 16) || !aligned(d_workspace, 256))
+    return set_error(WEDGE_EINVAL, "wedge_sample_alloc: misaligned pointer");
+  if (workspace_bytes < wedge_sample_alloc_workspace(n, max_bins))
+    return set_error(WEDGE_EWORKSPACE, "wedge_sample_alloc: workspace %zu < %zu bytes",
+                     workspace_bytes, wedge_sample_alloc_workspace(n, max_bins));
+  uint64_t total = k_global;
+  for (uint32_t b = 0; b < max_bins; ++b) {
+    if (h_k[b] > (1ULL << 48))
+      return set_error(WEDGE_ERANGE, "wedge_sample_alloc: k[%u] above 2^48", b);
+    total += h_k[b];
+  }
+  if (k_global > (1ULL << 48))
+    return set_error(WEDGE_ERANGE, "wedge_sample_alloc: k_global above 2^48");
+  if (total > 0 && (m == 0 || !d_col))
+    return set_error(WEDGE_EINVAL, "wedge_sample_alloc: samples requested of a graph without edges");
+  if (d_dump && dump_per_bin == 0) d_dump = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  AllocWorkspace w;
+  alloc_layout(n, max_bins, &w, d_workspace);
+  const uint32_t rows = max_bins + 1;
+  std::vector<uint64_t> hk(rows);
+  for (uint32_t b = 0; b < max_bins; ++b) hk[b] = h_k[b];
+  hk[max_bins] = k_global;
+  const IndexView ix = index_view(const_cast<void*>(d_index), n, m, 1, max_bins);
+  const uint64_t N = 2 * (uint64_t)n + 1;
+  int rc;
+  if ((rc = fill<uint64_t>(d_q, (uint64_t)rows * 4, 0, st))) return rc;
+  if ((rc = fill<uint64_t>(w.qv, N, 0, st))) return rc;
+  WEDGE_HIP_TRY(hipMemcpyAsync(w.k, hk.data(), rows * 8, hipMemcpyHostToDevice, st));
+  k_alloc_rows<<<1, 64, 0, st>>>(ix, w.k, max_bins, w.rows);
+  WEDGE_LAUNCH_CHECK("k_alloc_rows");
+  k_alloc_round<<<dim3(256, rows), 256, 0, st>>>(d_rowptr, ix, w.rows, max_bins, seed,
+                                                 kDomainAlloc, 0, w.qv);
+  WEDGE_LAUNCH_CHECK("k_alloc_round");
+  rc = scan_apply<uint64_t>(LoadArray<uint64_t>{w.qv}, StoreExclusive<uint64_t>{w.qv}, N,
+                            w.scan_ws, st);
+  if (rc) return rc;
+  k_alloc_totals<<<1, 256, 0, st>>>(w.rows, rows, w.qv, w.tot);
+  WEDGE_LAUNCH_CHECK("k_alloc_totals");
+  WEDGE_HIP_TRY(hipMemcpyAsync(h_totals, w.tot, rows * 8, hipMemcpyDeviceToHost, st));
+  WEDGE_HIP_TRY(hipStreamSynchronize(st));
+  uint64_t drawn = 0;
+  for (uint32_t f = 0; f < rows; ++f) drawn += h_totals[f];
+  SampleTuning t = default_tuning(drawn);
+  normalise(t);
+  SamplerCtx A;
+  A.rowptr = d_rowptr;
+  A.col = d_col;
+  A.ix = ix;
+  A.seed = seed;
+  A.spt = t.spt;
+  A.dump_per_bin = dump_per_bin;
+  A.q = d_q;
+  A.probe_loads = nullptr;
+  A.dump = d_dump;
+  A.class_cap = class_capacity(n, m, 1);
+  A.n = n;
+  A.max_bins = max_bins;
+  A.num_graphs = 1;
+  A.domain = kDomainAlloc;
+  A.s_begin = 0;
+  A.feat = nullptr;
+  A.feat_stride = 0;
+  A.omega = 2;
+  A.tau = 1;
+  A.closure = 1;
+  A.alloc = w.rows;
+  A.alloc_pre = w.qv;
+  TaskTable T;
+  T.graph_word = 0;
+  T.ntask = 0;
+  for (uint32_t b = 0; b < rows; ++b) {
+    if (h_totals[b] == 0) continue;
+    Task& K = T.task[T.ntask++];
+    K.row = b;
+    K.bword = (b == max_bins) ? kGlobalWord : b;
+    K.k = h_totals[b];
+    K.s_begin = 0;
+    K.slot = b;
     if (T.ntask == kMaxTasks) {
       if ((rc = launch_tasks(A, T, t.U, st))) return rc;
       T.ntask = 0;

@@ -8,6 +8,18 @@ namespace wedge {
 constexpr int kSampWG = 256;
 constexpr int kMaxTasks = 64;
 
+// Allocation form (Alg. phase2a): row f's vertices are vlist positions
+// [pos_lo, pos_lo + count); their sample counts sit at [off, off + count) of
+// a concatenated array whose exclusive prefix (alloc_pre) numbers the row's
+// samples, so sample s of the row is centred at the vertex whose prefix
+// range holds alloc_pre[off] + s.
+struct AllocRow {
+  uint64_t off;
+  uint64_t count;
+  uint64_t pos_lo;
+  uint64_t k;
+};
+
 // Everything a tile needs, passed by value to the kernels.
 struct SamplerCtx {
   const uint64_t* rowptr;
@@ -31,6 +43,9 @@ struct SamplerCtx {
   uint64_t omega;           // binning, for the centre's bin in a record
   uint32_t tau;
   int closure;              // 0: skip the closure search (feature-only draws)
+  // allocation form: centres from per-vertex counts instead of word 0
+  const AllocRow* alloc = nullptr;     // [rows], nullable
+  const uint64_t* alloc_pre = nullptr; // exclusive prefix of the counts
 };
 
 struct Task {

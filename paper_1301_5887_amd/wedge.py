@@ -129,6 +129,10 @@ SIGNATURES = {
     "wedge_cv_centre_means": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _c_u32,
                                              _c_u64, _vp, _vp, _c_u64, _c_u32, _c_u32, _vp,
                                              _vp, _vp, _c_u64, _vp, _vp, ctypes.c_size_t, _vp]),
+    "wedge_sample_alloc_workspace": (ctypes.c_size_t, [_c_u32, _c_u32]),
+    "wedge_sample_alloc": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _vp, _c_u64,
+                                          _c_u64, _vp, _vp, _vp, _c_u64, _vp, ctypes.c_size_t,
+                                          _vp]),
     "wedge_triangle_stats_workspace": (ctypes.c_size_t, [_c_u64]),
     "wedge_triangle_stats": (ctypes.c_int, [_vp, _c_u64, _c_u32, _c_u64, _c_u32, _vp, _vp, _vp,
                                             _vp, ctypes.c_size_t, _vp]),
@@ -368,6 +372,31 @@ def sample_close(g: Csr, bi: BinIndex, h_k: np.ndarray, k_global: int, seed: int
                                             int(samples_per_tile or 4096), _stream(stream))
     _check(rc)
     return out
+
+
+def sample_alloc(g: Csr, bi: BinIndex, h_k: np.ndarray, k_global: int, seed: int,
+                 dump_per_bin: int = 0, ws: Workspace | None = None, stream=None):
+    """wedge_sample_alloc (Alg. phase2a allocation, then per-vertex pairs).
+    Synchronises; returns (SampleOut, totals[max_bins + 1]) with totals the
+    realised samples per row."""
+    _require_gpu(g.rowptr, g.col, bi.index)
+    dev = g.rowptr.device
+    hk = np.ascontiguousarray(h_k, dtype=np.uint64)
+    assert hk.shape[0] == bi.max_bins
+    rows = bi.max_bins + 1
+    q = torch.empty(rows * 4, dtype=torch.int64, device=dev)
+    dump = (torch.zeros((rows * dump_per_bin, 4), dtype=torch.int32, device=dev)
+            if dump_per_bin > 0 else None)
+    tot = np.zeros(rows, dtype=np.uint64)
+    need = int(lib().wedge_sample_alloc_workspace(g.n, bi.max_bins))
+    wbuf = (ws or Workspace(dev)).get(need)
+    _check(lib().wedge_sample_alloc(_ptr(g.rowptr), _ptr(g.col), g.n, g.m, _ptr(bi.index),
+                                    bi.max_bins, hk.ctypes.data_as(_vp), k_global, seed,
+                                    _ptr(q), tot.ctypes.data_as(_vp), _ptr(dump), dump_per_bin,
+                                    _ptr(wbuf), wbuf.numel(), _stream(stream)))
+    out = SampleOut(q=q, probe_loads=None, dump=dump, h_k=tot[:bi.max_bins].copy(),
+                    k_global=int(tot[bi.max_bins]))
+    return out, tot
 
 
 @dataclass
