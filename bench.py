@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--alloc-seeds", type=int, default=0,
                     help="compare the Phase 2a allocation sampler with the i.i.d. one over "
                          "this many seeds (0: skip)")
+    ap.add_argument("--join", action="store_true",
+                    help="also test the step's wedges by a join against the edge list "
+                         "streamed from host memory")
     ap.add_argument("--no-cv", action="store_true",
                     help="skip the plain-EB / learned-CV comparison")
     ap.add_argument("--cv-train", type=int, default=10_000_000)
@@ -312,6 +315,42 @@ def main():
         log(f"[bench] allocation form: {alloc['alloc_ms']} ms per sampling (i.i.d. "
             f"{alloc['iid_ms']} ms) over {args.alloc_seeds} seeds")
 
+    join = None
+    if args.join:
+        # closure of the step's wedges by a join against the unsorted edge
+        # list streamed from pinned host memory (no adjacency used)
+        g = W.Csr(n=n, m=int(m), rowptr=rowptr, col=col)
+        bi = W.BinIndex(n=n, m=int(m), tau=2, omega=2, max_bins=B, n_b=n_b, p_b=p_b,
+                        index=index, h_n_b=h_nb.numpy().view(np.uint64).copy(),
+                        h_p_b=h_pb.numpy().view(np.uint64).copy())
+        dpb = int(max(int(hk.max()), kg))
+        so = W.sample_close(g, bi, hk, kg, args.seed, dump_per_bin=dpb)
+        dmp = so.dump.view(B + 1, dpb, 4)
+        rows_s = [r for r in range(B) if hk[r]] + ([B] if kg else [])
+        recs = torch.cat([dmp[r, : (kg if r == B else int(hk[r]))] for r in rows_s])
+        qa, qc = recs[:, 1].contiguous(), recs[:, 2].contiguous()
+        closed_ref = int((recs[:, 3] > 0).sum().item())
+        del so, dmp, recs
+        hs = torch.from_numpy(src.view(np.int32)).pin_memory()
+        hd = torch.from_numpy(dst.view(np.int32)).pin_memory()
+        jws = W.Workspace(dev)
+        for _ in range(2):          # the second, warm run is reported
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            closed = W.closure_join(qa, qc, hs, hd, ws=jws)
+            torch.cuda.synchronize()
+            t_join = time.perf_counter() - t0
+        nclosed = int(closed.sum().item())
+        join = {"queries": int(qa.numel()), "edges_streamed": m_in, "seconds": round(t_join, 5),
+                "closure_checks_per_s": qa.numel() / t_join,
+                "edge_stream_GBps": round(8 * m_in / t_join / 1e9, 2),
+                "closed": nclosed, "closed_by_search": closed_ref}
+        if nclosed != closed_ref:
+            raise RuntimeError(f"closure join disagrees with the sampler: {join}")
+        log(f"[bench] closure join: {qa.numel()} wedges against {m_in} streamed edges in "
+            f"{t_join * 1e3:.1f} ms")
+        del qa, qc, closed, hs, hd, jws
+
     tri = None
     if args.triangles > 0:
         from paper_1301_5887_amd import triangles as TR
@@ -361,6 +400,7 @@ def main():
         "cpu_baseline": cpu,
         "estimators": cvcmp,
         "triangle_sample": tri,
+        "closure_join": join,
         "allocation_form": alloc,
         "estimates": {"c": est.glob["c"], "c_global": est.glob["c_global"], "t": est.glob["t"],
                       "t_global": est.glob["t_global"], "eps": est.glob["eps_global"]},

@@ -518,6 +518,32 @@ int wedge_sample_alloc(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t
                        size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * wedge_closure_join -- closure tests by a join against an unsorted edge
+ * list streamed from host memory (the pattern of Alg. phase3b: the wedges'
+ * endpoint pairs meet the edges by key, either orientation), for edge lists
+ * that are not (or cannot be) held as a sorted adjacency in HBM.
+ *
+ * In:  d_a[k], d_c[k]  device uint32 endpoints of k wedges (a != c).
+ *      h_src[m_in], h_dst[m_in]  host uint32 edge list, any order, repeats
+ *                     and self-loops allowed; pinned memory lets the copies
+ *                     overlap the probes; it must stay valid until the work
+ *                     on `stream` has finished.
+ *      chunk_edges    edges per copy (0: 2^24).
+ * Out: d_closed[k]    device uint8: 1 iff {a_i, c_i} is an edge.
+ * The pairs go into an open-addressing table (SplitMix64 hash, at most half
+ * full); chunks of the edge list are copied on a second stream of the same
+ * device (created on first use, default priority) into two alternating
+ * buffers while the caller's stream probes the previous chunk.
+ * Workspace: wedge_closure_join_workspace(k, chunk_edges) bytes.
+ * Errors: EINVAL, ERANGE (k >= 2^40), EWORKSPACE, EHIP.
+ * ---------------------------------------------------------------------- */
+size_t wedge_closure_join_workspace(uint64_t k, uint64_t chunk_edges);
+int wedge_closure_join(const uint32_t* d_a, const uint32_t* d_c, uint64_t k,
+                       const uint32_t* h_src, const uint32_t* h_dst, uint64_t m_in,
+                       uint64_t chunk_edges, uint8_t* d_closed, void* d_workspace,
+                       size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Triangle sample and degree assortativity (Sec. 3 theorem on sampled
  * triangles; Sec. 5 triangle statistics).  A closed wedge of a uniform wedge
  * sample is a uniform sample (with replacement) of the graph's triangles,

@@ -1,0 +1,194 @@
+// Closure by a join against an unsorted edge stream (the pattern of
+// Alg. phase3b): the wedges' endpoint pairs become canonical keys
+// min<<32|max in an open-addressing table in HBM; the edge list, held in host
+// memory, streams through in chunks (copies on a second stream overlap the
+// probes of the previous chunk), and every edge whose key is in the table
+// marks it; each wedge then reads its key's mark.  No adjacency is built and
+// the edge list is never sorted.
+#include <mutex>
+
+#include "common.hpp"
+#include "scan.hpp"
+
+namespace wedge {
+
+constexpr uint64_t kJoinEmpty = ~0ULL;  // no canonical key of ids < 2^32 - 1
+constexpr uint64_t kJoinNone = ~0ULL;
+
+// SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014) as the hash.
+__device__ inline uint64_t join_mix(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xBF58476D1CE4E5B9ULL;
+  x ^= x >> 27;
+  x *= 0x94D049BB133111EBULL;
+  return x ^ (x >> 31);
+}
+
+__device__ inline uint64_t canon_key(uint32_t a, uint32_t c) {
+  const uint32_t lo = a < c ? a : c, hi = a < c ? c : a;
+  return ((uint64_t)lo << 32) | hi;
+}
+
+// Slot of key (inserting it when `insert`), kJoinNone when absent; linear
+// probing in a table at most half full, so every probe sequence ends.
+template <bool kInsert>
+__device__ inline uint64_t join_slot(unsigned long long* table, uint64_t mask, uint64_t key) {
+  uint64_t h = join_mix(key) & mask;
+  for (;;) {
+    const uint64_t cur = __hip_atomic_load(&table[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == key) return h;
+    if (cur == kJoinEmpty) {
+      if (!kInsert) return kJoinNone;
+      const uint64_t prev = atomicCAS(&table[h], (unsigned long long)kJoinEmpty,
+                                      (unsigned long long)key);
+      if (prev == kJoinEmpty || prev == key) return h;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__global__ void k_join_insert(const uint32_t* __restrict__ a, const uint32_t* __restrict__ c,
+                              uint64_t k, unsigned long long* table, uint64_t mask) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride)
+    join_slot<true>(table, mask, canon_key(a[i], c[i]));
+}
+
+__global__ void k_join_probe(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
+                             uint64_t ne, unsigned long long* table, uint64_t mask,
+                             uint8_t* __restrict__ mark) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += stride) {
+    const uint32_t u = src[i], w = dst[i];
+    if (u == w) continue;
+    const uint64_t s = join_slot<false>(table, mask, canon_key(u, w));
+    if (s != kJoinNone) mark[s] = 1;
+  }
+}
+
+__global__ void k_join_resolve(const uint32_t* __restrict__ a, const uint32_t* __restrict__ c,
+                               uint64_t k, unsigned long long* table, uint64_t mask,
+                               const uint8_t* __restrict__ mark, uint8_t* __restrict__ closed) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride) {
+    const uint64_t s = join_slot<false>(table, mask, canon_key(a[i], c[i]));
+    closed[i] = (s != kJoinNone && mark[s]) ? 1 : 0;
+  }
+}
+
+static uint64_t join_capacity(uint64_t k) {
+  uint64_t cap = 1024;
+  while (cap < 2 * k) cap <<= 1;
+  return cap;
+}
+
+struct JoinWorkspace {
+  unsigned long long* table;
+  uint8_t* mark;
+  uint32_t* buf[2][2];  // [buffer][src, dst]
+};
+
+static size_t join_layout(uint64_t k, uint64_t chunk, JoinWorkspace* w, void* base) {
+  const uint64_t cap = join_capacity(k);
+  char* c = (char*)base;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = c + off;
+    off += round_up(bytes, 256);
+    return p;
+  };
+  JoinWorkspace x;
+  x.table = (unsigned long long*)take(cap * 8);
+  x.mark = (uint8_t*)take(cap);
+  for (int b = 0; b < 2; ++b)
+    for (int j = 0; j < 2; ++j) x.buf[b][j] = (uint32_t*)take(chunk * 4);
+  if (w) *w = x;
+  return off;
+}
+
+constexpr uint64_t kJoinChunk = 1ULL << 24;
+
+// One copy stream per device, created on first use and kept until the
+// process ends.
+static int copy_stream(hipStream_t* out) {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  WEDGE_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return set_error(WEDGE_ERANGE, "wedge_closure_join: device id");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev]) WEDGE_HIP_TRY(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  *out = streams[dev];
+  return WEDGE_OK;
+}
+
+}  // namespace wedge
+
+using namespace wedge;
+
+extern "C" size_t wedge_closure_join_workspace(uint64_t k, uint64_t chunk_edges) {
+  return join_layout(k, chunk_edges ? chunk_edges : kJoinChunk, nullptr, nullptr);
+}
+
+extern "C" int wedge_closure_join(const uint32_t* d_a, const uint32_t* d_c, uint64_t k,
+                                  const uint32_t* h_src, const uint32_t* h_dst, uint64_t m_in,
+                                  uint64_t chunk_edges, uint8_t* d_closed, void* d_workspace,
+                                  size_t workspace_bytes, void* stream) {
+  clear_error();
+  const uint64_t chunk = chunk_edges ? chunk_edges : kJoinChunk;
+  if ((k > 0 && (!d_a || !d_c || !d_closed)) || (m_in > 0 && (!h_src || !h_dst)) || !d_workspace)
+    return set_error(WEDGE_EINVAL, "wedge_closure_join: null pointer");
+  if (!aligned(d_a, 4) || !aligned(d_c, 4) || !aligned(h_src, 4) || !aligned(h_dst, 4) ||
+      !aligned(d_workspace, 256))
+    return set_error(WEDGE_EINVAL, "wedge_closure_join: misaligned pointer");
+  if (k >= (1ULL << 40)) return set_error(WEDGE_ERANGE, "wedge_closure_join: k >= 2^40");
+  if (workspace_bytes < wedge_closure_join_workspace(k, chunk_edges))
+    return set_error(WEDGE_EWORKSPACE, "wedge_closure_join: workspace %zu < %zu bytes",
+                     workspace_bytes, wedge_closure_join_workspace(k, chunk_edges));
+  if (k == 0) return WEDGE_OK;
+  hipStream_t st = (hipStream_t)stream;
+  JoinWorkspace w;
+  join_layout(k, chunk, &w, d_workspace);
+  const uint64_t cap = join_capacity(k), mask = cap - 1;
+  int rc = fill<unsigned long long>(w.table, cap, kJoinEmpty, st);
+  if (rc || (rc = fill<uint8_t>(w.mark, cap, 0, st))) return rc;
+  k_join_insert<<<2048, 256, 0, st>>>(d_a, d_c, k, w.table, mask);
+  WEDGE_LAUNCH_CHECK("k_join_insert");
+  hipStream_t cs;
+  if ((rc = copy_stream(&cs))) return rc;
+  hipEvent_t start, copied[2], used[2];
+  WEDGE_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  for (int b = 0; b < 2; ++b) {
+    WEDGE_HIP_TRY(hipEventCreateWithFlags(&copied[b], hipEventDisableTiming));
+    WEDGE_HIP_TRY(hipEventCreateWithFlags(&used[b], hipEventDisableTiming));
+  }
+  // the copies may only overwrite the buffers once earlier work on the
+  // caller's stream is done with the workspace
+  WEDGE_HIP_TRY(hipEventRecord(start, st));
+  WEDGE_HIP_TRY(hipStreamWaitEvent(cs, start, 0));
+  const uint64_t nchunks = (m_in + chunk - 1) / chunk;
+  for (uint64_t j = 0; j < nchunks; ++j) {
+    const int b = (int)(j & 1);
+    const uint64_t e0 = j * chunk;
+    const uint64_t ne = (m_in - e0) < chunk ? (m_in - e0) : chunk;
+    if (j >= 2) WEDGE_HIP_TRY(hipStreamWaitEvent(cs, used[b], 0));
+    WEDGE_HIP_TRY(hipMemcpyAsync(w.buf[b][0], h_src + e0, ne * 4, hipMemcpyHostToDevice, cs));
+    WEDGE_HIP_TRY(hipMemcpyAsync(w.buf[b][1], h_dst + e0, ne * 4, hipMemcpyHostToDevice, cs));
+    WEDGE_HIP_TRY(hipEventRecord(copied[b], cs));
+    WEDGE_HIP_TRY(hipStreamWaitEvent(st, copied[b], 0));
+    unsigned blocks = (unsigned)((ne + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    k_join_probe<<<blocks, 256, 0, st>>>(w.buf[b][0], w.buf[b][1], ne, w.table, mask, w.mark);
+    WEDGE_LAUNCH_CHECK("k_join_probe");
+    WEDGE_HIP_TRY(hipEventRecord(used[b], st));
+  }
+  k_join_resolve<<<2048, 256, 0, st>>>(d_a, d_c, k, w.table, mask, w.mark, d_closed);
+  WEDGE_LAUNCH_CHECK("k_join_resolve");
+  // events may be destroyed while work that records them is pending
+  WEDGE_HIP_TRY(hipEventDestroy(start));
+  for (int b = 0; b < 2; ++b) {
+    WEDGE_HIP_TRY(hipEventDestroy(copied[b]));
+    WEDGE_HIP_TRY(hipEventDestroy(used[b]));
+  }
+  return WEDGE_OK;
+}

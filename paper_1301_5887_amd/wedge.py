@@ -133,6 +133,9 @@ SIGNATURES = {
     "wedge_sample_alloc": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _vp, _c_u64,
                                           _c_u64, _vp, _vp, _vp, _c_u64, _vp, ctypes.c_size_t,
                                           _vp]),
+    "wedge_closure_join_workspace": (ctypes.c_size_t, [_c_u64, _c_u64]),
+    "wedge_closure_join": (ctypes.c_int, [_vp, _vp, _c_u64, _vp, _vp, _c_u64, _c_u64, _vp, _vp,
+                                          ctypes.c_size_t, _vp]),
     "wedge_triangle_stats_workspace": (ctypes.c_size_t, [_c_u64]),
     "wedge_triangle_stats": (ctypes.c_int, [_vp, _c_u64, _c_u32, _c_u64, _c_u32, _vp, _vp, _vp,
                                             _vp, ctypes.c_size_t, _vp]),
@@ -397,6 +400,24 @@ def sample_alloc(g: Csr, bi: BinIndex, h_k: np.ndarray, k_global: int, seed: int
     out = SampleOut(q=q, probe_loads=None, dump=dump, h_k=tot[:bi.max_bins].copy(),
                     k_global=int(tot[bi.max_bins]))
     return out, tot
+
+
+def closure_join(a: torch.Tensor, c: torch.Tensor, h_src: torch.Tensor, h_dst: torch.Tensor,
+                 chunk_edges: int = 0, ws: Workspace | None = None, stream=None) -> torch.Tensor:
+    """wedge_closure_join: closure flags (uint8 device tensor) of the wedges
+    (a, c) against the host edge list (h_src, h_dst: int32 CPU tensors,
+    preferably pinned)."""
+    _require_gpu(a, c)
+    assert a.numel() == c.numel() and h_src.numel() == h_dst.numel()
+    assert not h_src.is_cuda and not h_dst.is_cuda
+    k = a.numel()
+    closed = torch.empty(max(k, 1), dtype=torch.uint8, device=a.device)
+    need = int(lib().wedge_closure_join_workspace(k, chunk_edges))
+    wbuf = (ws or Workspace(a.device)).get(need)
+    _check(lib().wedge_closure_join(_ptr(a), _ptr(c), k, _vp(h_src.data_ptr()),
+                                    _vp(h_dst.data_ptr()), h_src.numel(), chunk_edges,
+                                    _ptr(closed), _ptr(wbuf), wbuf.numel(), _stream(stream)))
+    return closed[:k]
 
 
 @dataclass

@@ -236,3 +236,12 @@ def test_triangle_stats_validation():
     assert L.wedge_triangle_stats(z, 10, 2, 2, 16, None, None, z, z, 1 << 20, None) == -1
     assert L.wedge_triangle_stats(z, 10, 2, 2, 16, None, z, z, z, 0, None) == -3
     assert L.wedge_triangle_box(None, 16, None) == -1
+
+
+def test_closure_join_validation():
+    L = W.lib()
+    z = ctypes.c_void_p(256)
+    assert L.wedge_closure_join(None, z, 10, z, z, 5, 0, z, z, 1 << 30, None) == -1
+    assert L.wedge_closure_join(z, z, 1 << 40, z, z, 5, 0, z, z, 1 << 30, None) == -2
+    assert L.wedge_closure_join(z, z, 10, z, z, 5, 0, z, z, 16, None) == -3
+    assert L.wedge_closure_join(z, z, 0, None, None, 0, 0, None, z, 1 << 30, None) == 0
