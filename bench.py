@@ -266,6 +266,12 @@ def main():
                                n_train=args.cv_train)
         cvcmp["plain_hoeffding"] = {"closure_checks": K,
                                     "seconds": avg["sample_close"] / 1000.0}
+        # the learned forms against the plain (Hoeffding) form at the same
+        # interval; rows_with_cv says whether the network was used at all
+        cvcmp["vs_plain_hoeffding"] = {
+            name: {"fewer_closure_checks": cvcmp[name]["closure_checks"] < K,
+                   "less_wall_time": cvcmp[name]["seconds"] < avg["sample_close"] / 1000.0}
+            for name in ("learned_cv_centre", "learned_cv_exact_mean") if name in cvcmp}
         lc = cvcmp["learned_cv_centre"]
         lx = cvcmp.get("learned_cv_exact_mean")
         log(f"[bench] estimator comparison: plain-Hoeffding {K} checks, plain-EB "

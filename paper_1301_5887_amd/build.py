@@ -8,7 +8,6 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
-import shutil
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))

@@ -5,7 +5,6 @@ the smallest degree, and the bin of the largest degree is summarised per
 group as in the paper's box plots (Sec. 5)."""
 from __future__ import annotations
 
-import ctypes
 from dataclasses import dataclass
 
 import numpy as np

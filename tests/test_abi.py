@@ -245,3 +245,17 @@ def test_closure_join_validation():
     assert L.wedge_closure_join(z, z, 1 << 40, z, z, 5, 0, z, z, 1 << 30, None) == -2
     assert L.wedge_closure_join(z, z, 10, z, z, 5, 0, z, z, 16, None) == -3
     assert L.wedge_closure_join(z, z, 0, None, None, 0, 0, None, z, 1 << 30, None) == 0
+
+
+def test_sample_alloc_validation():
+    L = W.lib()
+    z = ctypes.c_void_p(256)
+    hk = (ctypes.c_uint64 * 8)()
+    tot = (ctypes.c_uint64 * 9)()
+    big = 1 << 30
+    assert L.wedge_sample_alloc(z, z, 0, 5, z, 8, hk, 0, 1, z, tot, None, 0, z, big, None) == -2
+    assert L.wedge_sample_alloc(z, z, 10, 5, z, 0, hk, 0, 1, z, tot, None, 0, z, big, None) == -2
+    assert L.wedge_sample_alloc(z, z, 10, 5, None, 8, hk, 0, 1, z, tot, None, 0, z, big, None) == -1
+    assert L.wedge_sample_alloc(z, z, 10, 5, z, 8, hk, 0, 1, z, tot, None, 0, z, 16, None) == -3
+    hk[3] = (1 << 48) + 1
+    assert L.wedge_sample_alloc(z, z, 10, 5, z, 8, hk, 0, 1, z, tot, None, 0, z, big, None) == -2

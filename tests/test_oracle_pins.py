@@ -8,7 +8,6 @@ pure-Python brute force, and chi-square uniformity of the sampler.
 import json
 import math
 import os
-from itertools import combinations
 
 import numpy as np
 import pytest
