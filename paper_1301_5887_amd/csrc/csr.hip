@@ -2,11 +2,13 @@
 // the input convention of Sec. 4.1 / 5.1: undirected, self-loops and
 // repeated edges carry no meaning).
 //
-// 1. Onesweep LSD radix sort of the directed keys u<<32|w and w<<32|u of
+// 1. Onesweep LSD radix sort of the directed keys u<<ks|w and w<<ks|u of
 //    every input edge (u, w) over the significant digits of dst, then of
-//    src; the first pass builds the keys from the edge list as it reads it
-//    (a self-loop stays a key u<<32|u; an edge with an id >= n becomes the
-//    self-loop 0<<32|0 and is counted as rejected).
+//    src; ks = 24 when every id is below 2^24 (48-bit keys in the packed
+//    layout, 6 bytes moved per key and pass), else 32.  The first pass builds
+//    the keys from the edge list as it reads it (a self-loop stays a key
+//    u<<ks|u; an edge with an id >= n becomes the self-loop 0 and is counted
+//    as rejected).
 // 2. One scan over the sorted keys: a key is kept iff it is not a self-loop
 //    and differs from its predecessor; its exclusive count is its position
 //    in col, and every change of src writes the row starts it spans.
@@ -17,10 +19,10 @@
 namespace wedge {
 
 struct DedupLoad {
-  const uint64_t* k;
+  KeyView k;
   __device__ uint64_t operator()(uint64_t i) const {
     const uint64_t x = k[i];
-    const bool loop = (uint32_t)(x >> 32) == (uint32_t)x;
+    const bool loop = k.src(x) == k.dst(x);
     const bool repeat = i > 0 && k[i - 1] == x;
     return (!loop && !repeat) ? 1 : 0;
   }
@@ -30,8 +32,8 @@ struct DedupLoad {
 // tile of kScanTile keys is base + it * 256 + tid (coalesced); every key and
 // its predecessor are loaded before the scan, so the writes that follow wait
 // on no further loads.
-__global__ __launch_bounds__(kScanWG) void k_dedup_apply(const uint64_t* __restrict__ k,
-                                                         uint64_t N, uint32_t n,
+__global__ __launch_bounds__(kScanWG) void k_dedup_apply(const KeyView k, uint64_t N,
+                                                         uint32_t n,
                                                          const uint64_t* __restrict__ block_prefix,
                                                          uint32_t* __restrict__ col,
                                                          uint64_t* __restrict__ rowptr,
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(kScanWG) void k_dedup_apply(const uint64_t* __restr
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
     const uint64_t g = base + (uint64_t)it * kScanWG + tid;
-    const bool loop = (uint32_t)(x[it] >> 32) == (uint32_t)x[it];
+    const bool loop = k.src(x[it]) == k.dst(x[it]);
     const uint64_t v = (g < N && !loop && x[it] != prev[it]) ? 1 : 0;
     keep |= (uint32_t)v << it;
     const uint64_t incl = wave_incl_scan(v, lane);
@@ -73,15 +75,15 @@ __global__ __launch_bounds__(kScanWG) void k_dedup_apply(const uint64_t* __restr
     if (g < N) {
       const uint64_t prefix = run + before + ex[it];
       const bool kept = (keep >> it) & 1;
-      const uint32_t s = (uint32_t)(x[it] >> 32);
-      if (kept) col[prefix] = (uint32_t)x[it];
+      const uint32_t s = k.src(x[it]);
+      if (kept) col[prefix] = k.dst(x[it]);
       // rowptr[v] = number of kept keys with src < v: the first key of each
       // src writes it for every vertex since the previous key's src.
       uint64_t first_v;
       if (g == 0) {
         first_v = 0;
       } else {
-        const uint32_t sp = (uint32_t)(prev[it] >> 32);
+        const uint32_t sp = k.src(prev[it]);
         first_v = (sp == s) ? (uint64_t)s + 1 : (uint64_t)sp + 1;
       }
       for (uint64_t v = first_v; v <= s; ++v) rowptr[v] = prefix;
@@ -132,18 +134,21 @@ int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint3
   int rc = fill<uint64_t>(d_info, 2, 0, st);
   if (rc) return rc;
   if (N == 0) return fill<uint64_t>(d_rowptr, (uint64_t)n + 1, 0, st);
-  // digits of dst (bits 0..nb) then of src (bits 32..32+nb)
+  // digits of dst (bits 0..nb) then of src (bits ks..ks+nb); ids below 2^24
+  // make 48-bit keys, sorted in the packed layout
   int shifts[16];
   int np = 0;
   const int nb = bit_width((uint64_t)n - 1);
+  const int ks = nb <= 24 ? 24 : 32;
   for (int s = 0; s < nb; s += 8) shifts[np++] = s;
-  for (int s = 0; s < nb; s += 8) shifts[np++] = 32 + s;
+  for (int s = 0; s < nb; s += 8) shifts[np++] = ks + s;
   if (np == 0) shifts[np++] = 0;  // n == 1: one pass still writes the keys
-  EdgeSource E{d_src, d_dst, m_in, n, d_eoff, d_voff, G, (unsigned long long*)(d_info + 1)};
-  uint64_t* sorted = nullptr;
+  EdgeSource E{d_src, d_dst, m_in, n, d_eoff, d_voff, G, (unsigned long long*)(d_info + 1), ks};
+  uint64_t* sorted_base = nullptr;
   const OsScratch osc = os_scratch(w.radix, N);
-  rc = onesweep_sort_edges(E, w.keys_a, w.keys_b, shifts, np, osc, st, &sorted);
+  rc = onesweep_sort_edges(E, w.keys_a, w.keys_b, shifts, np, osc, st, &sorted_base);
   if (rc) return rc;
+  const KeyView sorted{sorted_base, N, ks};
   // kept-key counts per tile, their exclusive scan, then the apply pass
   const uint64_t nb_tiles = ceil_div(N, kScanTile);
   uint64_t* part = w.scan_ws;

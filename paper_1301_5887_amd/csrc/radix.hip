@@ -21,8 +21,8 @@ __device__ inline uint32_t os_graph_of_edge(const uint64_t* __restrict__ eoff, u
   return lo;
 }
 
-// The two keys of edge i of the edge list (see EdgeSource): *k0 = u<<32|w,
-// *k1 = w<<32|u; returns true when an id is out of range.
+// The two keys of edge i of the edge list (see EdgeSource): *k0 = u<<ks|w,
+// *k1 = w<<ks|u; returns true when an id is out of range.
 __device__ inline bool edge_keys(const EdgeSource& E, uint64_t i, uint64_t* k0, uint64_t* k1) {
   uint64_t u = E.src[i], w = E.dst[i];
   uint64_t base = 0, lim = E.n;
@@ -38,8 +38,8 @@ __device__ inline bool edge_keys(const EdgeSource& E, uint64_t i, uint64_t* k0, 
     u += base;
     w += base;
   }
-  *k0 = (u << 32) | w;
-  *k1 = (w << 32) | u;
+  *k0 = (u << E.ks) | w;
+  *k1 = (w << E.ks) | u;
   return bad;
 }
 
@@ -121,7 +121,7 @@ __device__ inline void os_store(unsigned long long* p, unsigned long long v) {
 }
 
 // One digit pass.  kEdges: the input keys are made from the edge list.
-template <bool kEdges>
+template <bool kEdges, bool kPacked = false>
 __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t* __restrict__ in,
                                                    uint64_t* __restrict__ out, uint64_t N,
                                                    int shift, uint64_t tag,
@@ -172,8 +172,8 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
           const bool valid = e + h < E.m_in;
           uint64_t u = us[h], w = ws[h];
           if (u >= E.n || w >= E.n) u = w = 0;  // counted by the histogram pass
-          key[4 * it + 2 * h] = valid ? ((u << 32) | w) : 0;
-          key[4 * it + 2 * h + 1] = valid ? ((w << 32) | u) : 0;
+          key[4 * it + 2 * h] = valid ? ((u << E.ks) | w) : 0;
+          key[4 * it + 2 * h + 1] = valid ? ((w << E.ks) | u) : 0;
           ok[4 * it + 2 * h] = ok[4 * it + 2 * h + 1] = valid;
         }
       }
@@ -195,7 +195,13 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
     for (int it = 0; it < kOsItems; ++it) {
       const uint64_t g = tbase + (uint64_t)wave * 64 * kOsItems + (uint64_t)it * 64 + lane;
       ok[it] = g < N;
-      key[it] = ok[it] ? in[g] : 0;
+      if (kPacked) {
+        const uint32_t* in_lo = (const uint32_t*)in;
+        const uint16_t* in_hi = (const uint16_t*)(in_lo + N);
+        key[it] = ok[it] ? ((uint64_t)in_lo[g] | ((uint64_t)in_hi[g] << 32)) : 0;
+      } else {
+        key[it] = ok[it] ? in[g] : 0;
+      }
     }
   }
 #pragma unroll
@@ -297,7 +303,16 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
     const uint64_t k = s_keys[j];
     const uint32_t d = (uint32_t)(k >> shift) & 255;
     const uint64_t at = s_glob[d] + (uint64_t)j;
-    if (at < N) out[at] = k;
+    if (at < N) {
+      if (kPacked) {
+        uint32_t* out_lo = (uint32_t*)out;
+        uint16_t* out_hi = (uint16_t*)(out_lo + N);
+        out_lo[at] = (uint32_t)k;
+        out_hi[at] = (uint16_t)(k >> 32);
+      } else {
+        out[at] = k;
+      }
+    }
   }
 }
 
@@ -314,13 +329,13 @@ int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int
   OsShifts S;
   S.npass = npass;
   for (int p = 0; p < kOsMaxPasses; ++p) S.s[p] = p < npass ? shifts[p] : 0;
-  // both keys of every edge are sorted, so the src digit at bit 32 + s has
+  // both keys of every edge are sorted, so the src digit at bit ks + s has
   // the same histogram as the dst digit at bit s: count it once
   for (int p = 0; p < kOsMaxPasses; ++p) {
     S.mirror[p] = -1;
-    if (p >= npass || S.s[p] < 32) continue;
+    if (p >= npass || S.s[p] < E.ks) continue;
     for (int q = 0; q < npass; ++q)
-      if (S.s[q] == S.s[p] - 32) S.mirror[p] = q;
+      if (S.s[q] == S.s[p] - E.ks) S.mirror[p] = q;
   }
   if ((rc = fill<uint64_t>(sc.hist, kOsMaxPasses * 256, 0, st))) return rc;
   if ((rc = fill<unsigned long long>(sc.status, nt * 256, 0, st))) return rc;
@@ -337,14 +352,22 @@ int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int
   uint64_t* dst = a;
   for (int p = 0; p < npass; ++p) {
     const uint64_t tag = (uint64_t)(p + 1) << 56;
-    if (p == 0)
-      k_os_pass<true><<<(unsigned)nt, kOsWG, 0, st>>>(E, nullptr, dst, N, shifts[p], tag,
-                                                       sc.base + p * 256, sc.status,
-                                                       sc.tickets + p);
-    else
-      k_os_pass<false><<<(unsigned)nt, kOsWG, 0, st>>>(E, src, dst, N, shifts[p], tag,
-                                                        sc.base + p * 256, sc.status,
-                                                        sc.tickets + p);
+    const uint64_t* base = sc.base + p * 256;
+    if (E.ks == 32) {
+      if (p == 0)
+        k_os_pass<true><<<(unsigned)nt, kOsWG, 0, st>>>(E, nullptr, dst, N, shifts[p], tag, base,
+                                                         sc.status, sc.tickets + p);
+      else
+        k_os_pass<false><<<(unsigned)nt, kOsWG, 0, st>>>(E, src, dst, N, shifts[p], tag, base,
+                                                          sc.status, sc.tickets + p);
+    } else {
+      if (p == 0)
+        k_os_pass<true, true><<<(unsigned)nt, kOsWG, 0, st>>>(E, nullptr, dst, N, shifts[p], tag,
+                                                               base, sc.status, sc.tickets + p);
+      else
+        k_os_pass<false, true><<<(unsigned)nt, kOsWG, 0, st>>>(E, src, dst, N, shifts[p], tag,
+                                                                base, sc.status, sc.tickets + p);
+    }
     WEDGE_LAUNCH_CHECK("k_os_pass");
     src = dst;
     dst = (dst == a) ? b : a;

@@ -70,6 +70,28 @@ struct EdgeSource {
   const uint32_t* voff;  // [G + 1] vertex offsets (G > 1)
   uint32_t G;
   unsigned long long* rejected;
+  // bit position of the source id in a key (key = u << ks | w).  32: 64-bit
+  // keys; 24 (every id < 2^24): 48-bit keys, stored packed as a uint32 array
+  // of their low words followed by a uint16 array of their high words, so a
+  // pass moves 6 bytes per key instead of 8.
+  int ks = 32;
+};
+
+// Key i of a sorted array in either layout.
+struct KeyView {
+  const uint64_t* k;  // 64-bit keys, or the packed layout's base
+  uint64_t N;
+  int ks;
+  __device__ __forceinline__ uint64_t operator[](uint64_t i) const {
+    if (ks == 32) return k[i];
+    const uint32_t* lo = (const uint32_t*)k;
+    const uint16_t* hi = (const uint16_t*)(lo + N);
+    return (uint64_t)lo[i] | ((uint64_t)hi[i] << 32);
+  }
+  __device__ __forceinline__ uint32_t src(uint64_t x) const { return (uint32_t)(x >> ks); }
+  __device__ __forceinline__ uint32_t dst(uint64_t x) const {
+    return (uint32_t)(x & ((1ULL << ks) - 1));
+  }
 };
 
 // Sorts the 2 m_in keys of the edges by the digits at `shifts` (least
