@@ -223,16 +223,18 @@ def main():
     # CSR build: the least bytes any method must move (read the edge list,
     # write col and rowptr) and the bytes of this sort (histogram read of the
     # edges; first pass reads the edges and writes two keys per edge; each
-    # later digit pass reads and writes every key; the dedup reads the keys
-    # twice and writes col and rowptr)
+    # later digit pass reads and writes every key, 6 or 8 bytes; the dedup
+    # reads the keys twice and writes col and rowptr)
     nkeys = 2 * m_in
-    digits = 2 * ((max(n - 1, 1).bit_length() + 7) // 8)
+    idbits = max(n - 1, 1).bit_length()
+    digits = 2 * ((idbits + 7) // 8)
+    kb = 6 if idbits <= 24 else 8           # bytes per key (packed below 2^24 ids)
     csr_min = 8 * m_in + 4 * 2 * m + 8 * (n + 1)
-    csr_sort = (8 * m_in + (8 * m_in + 8 * nkeys) + (digits - 1) * 16 * nkeys
-                + 16 * nkeys + 4 * 2 * m + 8 * (n + 1))
+    csr_sort = (8 * m_in + (8 * m_in + kb * nkeys) + (digits - 1) * 2 * kb * nkeys
+                + 2 * kb * nkeys + 4 * 2 * m + 8 * (n + 1))
     t_csr = avg["build_csr"] / 1000.0
     roofline_csr = {"phase": "wedge_build_csr", "bound": "hbm", "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "digit_passes": digits,
+                    "unit": "GB/s", "digit_passes": digits, "key_bytes": kb,
                     "min_bytes": csr_min, "achieved_min": round(csr_min / t_csr / 1e9, 2),
                     "sort_bytes": csr_sort, "achieved_sort": round(csr_sort / t_csr / 1e9, 2),
                     "frac_sort": round(csr_sort / t_csr / 1e9 / PEAK_HBM_GBS, 5)}
