@@ -2,21 +2,29 @@
 
 For every bin b (and the global stream) the closed fraction c_b of Thm.
 cd-est is estimated by
-    c_CV = mean_EVAL(X - beta_b g) + beta_b mean_AUX(g)
+    c_CV = mean_EVAL(X - beta_b g) + beta_b mu_g
 where X is the exact closure label of a uniform wedge of the bin, g in (0,1)
 is the network's closure probability from the wedge's degrees, beta_b is fixed
-from held-out training draws before any EVAL or AUX draw, and the TRAIN, AUX
-and EVAL draws use distinct Philox key domains, so c_CV is unbiased whatever
-the network learned.  EVAL and AUX draws come in blocks of doubling size;
-after block i the two-sided empirical-Bernstein half-widths at confidence
-delta_i = delta / (i (i+1)) (a union bound over all stopping times) are
-    eps_EVAL = EB(n, var(X - beta g), 1 + |beta|)
-    eps_AUX  = |beta| EB(n_aux, var(g), 1)
-and a bin stops once eps_EVAL + eps_AUX <= eps.  beta = 0 with no AUX draws
-is plain wedge sampling with the same stopping rule ("plain-EB").  All work
+from held-out TRAIN draws before any EVAL draw, and the TRAIN, EVAL, AUX and
+centre draws use distinct Philox key domains, so c_CV is unbiased whatever the
+network learned.  mu_g, the mean of g over the bin's wedges, comes in one of
+three forms:
+  exact    from the census of (bin, centre bucket, endpoint bucket pair)
+           counts (the network depends on the wedge only through them);
+  centre   from centre draws: v with probability p_v / p_b and gbar(v), the
+           mean of g over all wedges at v (E[gbar] = mu_g);
+  AUX      from uniform wedge draws without a closure test.
+Draws come in rounds whose sizes are fixed before any EVAL draw (first round
+from the held-out draws, then growing by a constant factor); after round i
+the two-sided empirical-Bernstein half-width at delta_i = delta / (i (i+1))
+(a union bound over rounds) is checked against eps: EB(n, var(X - beta g),
+1 + |beta|) at delta_i for the exact form, plus |beta| EB of the mean of
+gbar (or of g) with delta_i split in two for the centre (AUX) form.
+beta = 0 is plain wedge sampling with the same rule ("plain-EB").  All work
 runs in libwedge: the sampler in feature mode, the network's forward,
-gradient and Adam kernels, and the integer moment sums; this module only
-sequences the calls and evaluates the closed-form bounds.
+gradient and Adam kernels, the census, the centre draws and the integer
+moment sums; this module only sequences the calls and evaluates the
+closed-form bounds and plans.
 """
 from __future__ import annotations
 
@@ -408,7 +416,8 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
         recs = new_records(A, stride, dev)
         sample_features(g, bi, hk, sb, seed, DOMAIN_EVAL, True, recs, stride, stream=stream)
         gv = torch.zeros(A * stride, dtype=torch.float32, device=dev)
-        if net is not None:
+        # g only matters on rows whose beta is not 0 (plain rows use X alone)
+        if net is not None and any((beta or {}).get(r, 0.0) != 0.0 for r in active):
             net.forward(recs, A * stride, gv, stream=stream)
         m = _moments_per_row(recs, gv, incs, stride, dev)
         am = None
