@@ -51,6 +51,8 @@ static size_t index_layout(uint64_t n_total, uint64_t m_total, uint32_t G, uint3
   off += round_up(cap * 8, 256);
   if (v) v->vcode = (uint8_t*)(c + off);
   off += round_up((size_t)n_total, 256);
+  if (v) v->vmeta = (uint64_t*)(c + off);
+  off += round_up(((size_t)n_total + 1) * 8, 256);
   return off;
 }
 
@@ -78,12 +80,14 @@ __device__ inline uint8_t degree_code(uint64_t d) {
 __global__ void k_deg_keys(const uint64_t* __restrict__ rowptr, uint32_t n,
                            const uint32_t* __restrict__ voff, uint32_t G, int gshift,
                            uint64_t dmask, uint64_t* __restrict__ keys,
-                           uint8_t* __restrict__ vcode) {
+                           uint8_t* __restrict__ vcode, uint64_t* __restrict__ vmeta) {
   uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; v < n; v += stride) {
     uint64_t d = rowptr[v + 1] - rowptr[v];
     vcode[v] = degree_code(d);
+    vmeta[v] = rowptr[v] | ((uint64_t)degree_code(d) << 56);
+    if (v == (uint64_t)n - 1) vmeta[n] = rowptr[n];
     if (d > dmask) d = dmask;
     uint64_t key = (d << 32) | v;
     if (G > 1) key |= (uint64_t)graph_of(voff, G, (uint32_t)v) << gshift;
@@ -284,7 +288,7 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
     uint64_t blocks = ceil_div(n, 256);
     if (blocks > 65536) blocks = 65536;
     k_deg_keys<<<(unsigned)blocks, 256, 0, st>>>(d_rowptr, (uint32_t)n, d_voff, G, gshift, dmask,
-                                                 w.keys_a, ix.vcode);
+                                                 w.keys_a, ix.vcode, ix.vmeta);
     WEDGE_LAUNCH_CHECK("k_deg_keys");
   }
   // sort by the degree digits, then by the graph digits; ids stay ascending

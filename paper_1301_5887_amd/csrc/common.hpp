@@ -78,7 +78,10 @@ struct IndexView {
   uint32_t* cls_start;// [class_cap] first position of class j in vlist
   uint64_t* cls_cumw; // [class_cap] inclusive prefix of count_j * C(d_j, 2)
   uint8_t* vcode;     // [n] degree code floor(8 L(d)) per vertex id (monotone in d)
+  uint64_t* vmeta;    // [n+1] rowptr[v] | code(v) << 56 (row start and degree code)
 };
+
+constexpr uint64_t kRowMask = (1ULL << 56) - 1;
 
 // Upper bound on the number of distinct (graph, degree) pairs of G simple
 // graphs with n_total vertices and m_total edges in all.

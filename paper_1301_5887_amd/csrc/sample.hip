@@ -9,8 +9,8 @@
 // the LDS holds) in LDS, then each lane carries U independent samples
 // through the dependent gather chain
 //     Philox -> centre class (LDS search) -> adjacency start of the centre
-//            -> col (a, c) -> rowptr[a], rowptr[c] -> binary search in the
-//            shorter row,
+//            -> col (a, c) -> row-start words of a and c -> binary search
+//            in the shorter row,
 // issuing the loads of its U samples back to back so that U x (waves per CU)
 // chains are in flight per CU.  Class counts are reduced per wave with
 // shuffles, per workgroup in LDS, and added to the row's four uint64
@@ -132,7 +132,6 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
 
   const uint64_t seed = A.seed;
   const uint64_t bw = bword;
-  const uint64_t* __restrict__ rowptr = A.rowptr;
   const uint32_t* __restrict__ col = A.col;
   uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0, cnt3 = 0;
   uint64_t probes = 0;
@@ -200,23 +199,26 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       c[u] = act[u] ? col[rp[u] + ic[u]] : 0;
     }
     // 4. closure: search one endpoint in the row of the other, the row with
-    //    the smaller degree code (a byte per vertex; tie: the row of a), so
-    //    only one endpoint's row bounds are read up front
-    uint64_t da[U], dc[U];
+    //    the smaller degree code (tie: the row of a).  One 8-byte word per
+    //    vertex holds its row start and, in the top byte, its degree code, so
+    //    the two endpoint words plus the searched row's end bound are the
+    //    only loads before the search
+    uint64_t da[U], dc[U], my[U];
     bool in_a[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      uint32_t ca = 0, cc = 0;
+      uint64_t ma = 0, mc = 0;
       if (act[u]) {
-        ca = A.ix.vcode[a[u]];
-        cc = A.ix.vcode[c[u]];
+        ma = A.ix.vmeta[a[u]];
+        mc = A.ix.vmeta[c[u]];
       }
-      in_a[u] = ca <= cc;
+      in_a[u] = (ma >> 56) <= (mc >> 56);
       const uint32_t x = in_a[u] ? a[u] : c[u];
+      my[u] = in_a[u] ? mc : ma;  // the other endpoint's row start and code
       uint64_t r0 = 0, r1 = 0;
       if (act[u]) {
-        r0 = rowptr[x];
-        r1 = rowptr[x + 1];
+        r0 = (in_a[u] ? ma : mc) & kRowMask;
+        r1 = A.ix.vmeta[x + 1] & kRowMask;
       }
       const uint64_t dx = r1 - r0;
       da[u] = in_a[u] ? dx : 0;
@@ -291,7 +293,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
     for (int u = 0; u < U; ++u) {
       if (act[u] && (A.feat || (found[u] && !global))) {
         const uint32_t y = in_a[u] ? c[u] : a[u];
-        const uint64_t dy = rowptr[y + 1] - rowptr[y];
+        const uint64_t dy = (A.ix.vmeta[y + 1] & kRowMask) - (my[u] & kRowMask);
         if (in_a[u]) dc[u] = dy; else da[u] = dy;
       }
     }
