@@ -43,6 +43,30 @@ __device__ inline bool edge_keys(const EdgeSource& E, uint64_t i, uint64_t* k0, 
   return bad;
 }
 
+// Lanes of the wave, among those with `valid`, whose 8-bit digit equals this
+// lane's: each ballot on one digit bit keeps the lanes that agree on it.
+// t is 0 or all ones (the bit, sign-extended), so a lane keeps
+// p & ~(m ^ t): m where its bit is 1, ~m where it is 0 (one three-input
+// bitwise op per 32-bit half).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  const uint64_t v = __ballot(valid);
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  uint32_t t[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) t[b] = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+  // opaque to the optimiser, so each ballot compares t[b] itself instead of
+  // re-deriving the bit with a shift
+  asm("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]),
+      "+v"(t[7]));
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t m = __ballot(t[b] != 0);
+    lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)m, t[b], 0x90);
+    hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m >> 32), t[b], 0x90);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Counts of every digit of every pass over all keys, and the rejected edges.
 __global__ __launch_bounds__(kOsWG) void k_os_hist_edges(EdgeSource E, OsShifts S,
                                                          uint64_t* __restrict__ hist) {
@@ -131,6 +155,7 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
   constexpr int kWaves = kOsWG / 64;
   __shared__ uint64_t s_keys[kOsTile];
   __shared__ uint32_t s_cnt[kWaves][256];
+  __shared__ uint32_t s_spare[kWaves][64];
   __shared__ uint32_t s_tile_off[256];
   __shared__ uint64_t s_glob[256];
   __shared__ uint32_t s_wsum[kWaves];
@@ -142,13 +167,14 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
   const uint64_t tile = s_tile;
   const uint64_t tbase = tile * kOsTile;
 
-  // stable ranking inside the tile (see k_radix_scatter).  The first pass
-  // may take its keys in any order (the edge list has none), so each lane
-  // reads whole edges and holds both keys of an edge.
+  // Stable ranking inside the tile: key (wave, it, lane) goes after every
+  // key of its digit in earlier waves, earlier items of its wave and lower
+  // lanes of its item.  The first pass may take its keys in any order (the
+  // edge list has none), so each lane reads whole edges and holds both keys
+  // of an edge.
   uint64_t key[kOsItems];
   uint32_t rank[kOsItems];
   bool ok[kOsItems];
-  const uint64_t lt_mask = (1ULL << lane) - 1;
   if (kEdges) {
     const uint64_t ebase = tile * (kOsTile / 2);
     const bool pairs = E.G == 1 && ((((uintptr_t)E.src) | ((uintptr_t)E.dst)) & 7) == 0;
@@ -204,33 +230,43 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
       }
     }
   }
+  // Per item, the lowest lane of each digit's group adds the group's size to
+  // the wave's counter of that digit (LDS returns the count before it) and
+  // the group reads it from that lane.  A wave's LDS operations complete in
+  // issue order, so item it sees the counts of items 0..it-1.  The peer
+  // masks of all items come first (straight-line code the scheduler can
+  // interleave); rank[it] holds below | leader << 8 | size << 16 until the
+  // counters are read.  Every lane issues the add, the others adding 0 to a
+  // slot of their own, so the adds need no branch.
 #pragma unroll
   for (int it = 0; it < kOsItems; ++it) {
-    const bool valid = ok[it];
     const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
-    uint64_t peers = __ballot(valid);
+    const uint64_t peers = digit_peers(d, ok[it]);
+    const uint32_t below =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                  __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+    const uint32_t leader = (uint32_t)__builtin_ctzll(peers | (1ULL << 63));
+    rank[it] = below | (leader << 8) | ((uint32_t)__popcll(peers) << 16);
+  }
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    uint32_t before = 0;
-    if (valid) before = s_cnt[wave][d];
-    rank[it] = before + (uint32_t)__popcll(peers & lt_mask);
-    if (valid && (peers & lt_mask) == 0) s_cnt[wave][d] = before + (uint32_t)__popcll(peers);
-    __builtin_amdgcn_wave_barrier();
+  for (int it = 0; it < kOsItems; ++it) {
+    const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
+    const uint32_t below = rank[it] & 255, leader = (rank[it] >> 8) & 255;
+    const bool lead = ok[it] && below == 0;
+    uint32_t* slot = lead ? &s_cnt[wave][d] : &s_spare[wave][lane];
+    const uint32_t before = atomicAdd(slot, lead ? rank[it] >> 16 : 0u);
+    rank[it] = (uint32_t)__shfl(before, (int)leader, 64) + below;
   }
   __syncthreads();
-  uint32_t cnt = 0;  // keys of digit tid in the tile
+  uint32_t cnt = 0;           // keys of digit tid in the tile
+  uint32_t wex[kWaves] = {};  // keys of digit tid in the waves before w
   if (tid < 256) {
     const int d = tid;
     uint32_t run = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
-      const uint32_t c = s_cnt[w][d];
-      s_cnt[w][d] = run;
-      run += c;
+      wex[w] = run;
+      run += s_cnt[w][d];
     }
     cnt = run;
     // publish this tile's count before looking back
@@ -246,6 +282,9 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
       uint32_t off = incl - cnt;
       for (int w = 0; w < wave; ++w) off += s_wsum[w];
       s_tile_off[tid] = off;
+      // each wave's first slot for digit tid in the tile-sorted order
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) s_cnt[w][tid] = off + wex[w];
     }
   }
   if (tid < 256) {
@@ -294,7 +333,7 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
   for (int it = 0; it < kOsItems; ++it) {
     if (ok[it]) {
       const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
-      s_keys[s_tile_off[d] + s_cnt[wave][d] + rank[it]] = key[it];
+      s_keys[s_cnt[wave][d] + rank[it]] = key[it];
     }
   }
   __syncthreads();
