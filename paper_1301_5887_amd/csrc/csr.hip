@@ -9,7 +9,7 @@
 //    the keys from the edge list as it reads it (a self-loop stays a key
 //    u<<ks|u; an edge with an id >= n becomes the self-loop 0 and is counted
 //    as rejected).
-// 2. One scan over the sorted keys: a key is kept iff it is not a self-loop
+// 2. One pass over the sorted keys: a key is kept iff it is not a self-loop
 //    and differs from its predecessor; its exclusive count is its position
 //    in col, and every change of src writes the row starts it spans.
 #include "common.hpp"
@@ -18,58 +18,113 @@
 
 namespace wedge {
 
-struct DedupLoad {
-  KeyView k;
-  __device__ uint64_t operator()(uint64_t i) const {
-    const uint64_t x = k[i];
-    const bool loop = k.src(x) == k.dst(x);
-    const bool repeat = i > 0 && k[i - 1] == x;
-    return (!loop && !repeat) ? 1 : 0;
-  }
-};
+// Status word of a tile in the dedup's look-back: flag (2 bits) | count.
+constexpr uint64_t kDdAgg = 1ULL << 62;
+constexpr uint64_t kDdInc = 2ULL << 62;
+constexpr uint64_t kDdValue = kDdAgg - 1;
 
-// Row starts and compaction over the sorted keys.  Element (it, tid) of a
-// tile of kScanTile keys is base + it * 256 + tid (coalesced); every key and
-// its predecessor are loaded before the scan, so the writes that follow wait
-// on no further loads.
-__global__ __launch_bounds__(kScanWG) void k_dedup_apply(const KeyView k, uint64_t N,
-                                                         uint32_t n,
-                                                         const uint64_t* __restrict__ block_prefix,
-                                                         uint32_t* __restrict__ col,
-                                                         uint64_t* __restrict__ rowptr,
-                                                         uint64_t* __restrict__ info) {
-  __shared__ uint64_t s_tot[kScanItems][kScanWG / 64];
+__device__ inline uint64_t dd_load(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void dd_store(unsigned long long* p, uint64_t v) {
+  __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Row starts and compaction over the sorted keys in one pass.  Tiles of
+// kScanTile keys are taken in ticket order; element (it, tid) of a tile is
+// base + it * 256 + tid (coalesced), and its predecessor is the key of the
+// lane below (the wave's lane 0 reads it from memory), so every key is read
+// once.  A tile counts its kept keys with ballots, publishes the count and
+// finds the kept keys of all earlier tiles by a decoupled look-back (wave 0
+// inspects 64 earlier tiles per step), then writes col and the row starts.
+__global__ __launch_bounds__(kScanWG) void k_dedup(const KeyView k, uint64_t N, uint32_t n,
+                                                   unsigned long long* __restrict__ status,
+                                                   unsigned long long* __restrict__ ticket,
+                                                   unsigned long long* __restrict__ stalls,
+                                                   uint32_t* __restrict__ col,
+                                                   uint64_t* __restrict__ rowptr,
+                                                   uint64_t* __restrict__ info) {
+  constexpr int kWaves = kScanWG / 64;
+  static_assert(kScanItems * kWaves == 64, "one wave holds the tile's row totals");
+  __shared__ uint32_t s_tot[kScanItems][kWaves];
+  __shared__ uint64_t s_tile, s_excl;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  if (tid == 0) s_tile = atomicAdd(ticket, 1ULL);
+  __syncthreads();
+  const uint64_t tile = s_tile;
+  const uint64_t base = tile * kScanTile;
   uint64_t x[kScanItems], prev[kScanItems];
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
     const uint64_t g = base + (uint64_t)it * kScanWG + tid;
     x[it] = g < N ? k[g] : 0;
-    prev[it] = (g > 0 && g < N) ? k[g - 1] : ~0ULL;
+  }
+#pragma unroll
+  for (int it = 0; it < kScanItems; ++it) {
+    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
+    uint64_t p = __shfl_up(x[it], 1, 64);
+    if (lane == 0) p = (g > 0 && g < N) ? k[g - 1] : ~0ULL;
+    prev[it] = p;
   }
   uint32_t keep = 0;  // bit it: key (it, tid) is kept
-  uint64_t ex[kScanItems];
+  uint32_t ex[kScanItems];  // kept keys of lower lanes in this wave's part of row it
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
     const uint64_t g = base + (uint64_t)it * kScanWG + tid;
     const bool loop = k.src(x[it]) == k.dst(x[it]);
-    const uint64_t v = (g < N && !loop && x[it] != prev[it]) ? 1 : 0;
-    keep |= (uint32_t)v << it;
-    const uint64_t incl = wave_incl_scan(v, lane);
-    ex[it] = incl - v;
-    if (lane == 63) s_tot[it][wave] = incl;
+    const bool kept = g < N && !loop && x[it] != prev[it];
+    const uint64_t m = __ballot(kept);
+    ex[it] = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    keep |= (uint32_t)kept << it;
+    if (lane == 0) s_tot[it][wave] = (uint32_t)__popcll(m);
   }
   __syncthreads();
-  uint64_t run = block_prefix ? block_prefix[blockIdx.x] : 0;
+  if (wave == 0) {
+    const uint64_t agg = wave_sum<uint64_t>((&s_tot[0][0])[lane]);
+    uint64_t excl = 0;
+    if (tile == 0) {
+      if (lane == 0) dd_store(status, kDdInc | agg);
+    } else {
+      if (lane == 0) dd_store(status + tile, kDdAgg | agg);
+      // lane l inspects tile t - l; tiles before 0 read as an inclusive 0.
+      // Every earlier tile holds its ticket and is running, so each wait
+      // ends; the bound only guarantees that the wave exits.
+      int64_t t = (int64_t)tile - 1;
+      uint32_t spins = 0;
+      for (;;) {
+        const int64_t j = t - lane;
+        const uint64_t sw = j >= 0 ? dd_load(status + j) : kDdInc;
+        const uint64_t inc = __ballot((sw & kDdInc) != 0);
+        const uint64_t pub = __ballot((sw & (kDdAgg | kDdInc)) != 0);
+        const int li = inc ? (int)__builtin_ctzll(inc) : 64;  // nearest inclusive
+        const uint64_t upto = li >= 63 ? ~0ULL : ((2ULL << li) - 1);
+        if ((pub & upto) != upto) {
+          if (++spins > (1u << 24)) {
+            if (lane == 0) atomicAdd(stalls, 1ULL);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += wave_sum<uint64_t>(lane <= li ? (sw & kDdValue) : 0);
+        if (li < 64) break;
+        t -= 64;
+      }
+      if (lane == 0) dd_store(status + tile, kDdInc | (excl + agg));
+    }
+    if (lane == 0) s_excl = excl;
+  }
+  __syncthreads();
+  uint64_t run = s_excl;
 #pragma unroll
   for (int it = 0; it < kScanItems; ++it) {
-    uint64_t row = 0, before = 0;
+    uint32_t row = 0, before = 0;
 #pragma unroll
-    for (int w = 0; w < kScanWG / 64; ++w) {
-      const uint64_t t = s_tot[it][w];
-      if (w < wave) before += t;
-      row += t;
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = s_tot[it][w];
+      if (w < wave) before += c;
+      row += c;
     }
     const uint64_t g = base + (uint64_t)it * kScanWG + tid;
     if (g < N) {
@@ -149,24 +204,16 @@ int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint3
   rc = onesweep_sort_edges(E, w.keys_a, w.keys_b, shifts, np, osc, st, &sorted_base);
   if (rc) return rc;
   const KeyView sorted{sorted_base, N, ks};
-  // kept-key counts per tile, their exclusive scan, then the apply pass
+  // one pass: tiles in ticket order, look-back statuses in the scan scratch
   const uint64_t nb_tiles = ceil_div(N, kScanTile);
-  uint64_t* part = w.scan_ws;
-  if (nb_tiles == 1) {
-    k_dedup_apply<<<1, kScanWG, 0, st>>>(sorted, N, n, nullptr, d_col, d_rowptr, d_info);
-    WEDGE_LAUNCH_CHECK("k_dedup_apply");
-  } else {
-    k_scan_reduce<uint64_t, DedupLoad><<<(unsigned)(nb_tiles + 1), kScanWG, 0, st>>>(
-        DedupLoad{sorted}, N, part);
-    WEDGE_LAUNCH_CHECK("k_scan_reduce");
-    rc = scan_apply<uint64_t>(LoadArray<uint64_t>{part}, StoreExclusive<uint64_t>{part},
-                              nb_tiles + 1, part + nb_tiles + 1, st);
-    if (rc) return rc;
-    k_dedup_apply<<<(unsigned)nb_tiles, kScanWG, 0, st>>>(sorted, N, n, part, d_col, d_rowptr,
-                                                          d_info);
-    WEDGE_LAUNCH_CHECK("k_dedup_apply");
-  }
-  // a sort whose bounded wait gave up leaves m = 2^64 - 1
+  unsigned long long* dd_status = (unsigned long long*)w.scan_ws;
+  if ((rc = fill<unsigned long long>(dd_status, nb_tiles, 0, st))) return rc;
+  if ((rc = fill<unsigned long long>(w.counters, 1, 0, st))) return rc;
+  k_dedup<<<(unsigned)nb_tiles, kScanWG, 0, st>>>(sorted, N, n, dd_status, w.counters,
+                                                  osc.tickets + kOsMaxPasses, d_col, d_rowptr,
+                                                  d_info);
+  WEDGE_LAUNCH_CHECK("k_dedup");
+  // a sort or dedup whose bounded wait gave up leaves m = 2^64 - 1
   return os_flag_stalls(osc, d_info, ~0ULL, st);
 }
 
