@@ -238,6 +238,19 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
   // interleave); rank[it] holds below | leader << 8 | size << 16 until the
   // counters are read.  Every lane issues the add, the others adding 0 to a
   // slot of their own, so the adds need no branch.
+  if (kEdges) {
+    // The edge list has no order to keep, so the first pass ranks each key
+    // by an LDS add of 1 on its wave's digit counter: the lanes of one add
+    // get distinct counts in an unspecified order.  The later passes are
+    // stable and cover every digit, so the sorted result depends on the key
+    // values only.
+#pragma unroll
+    for (int it = 0; it < kOsItems; ++it) {
+      const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
+      uint32_t* slot = ok[it] ? &s_cnt[wave][d] : &s_spare[wave][lane];
+      rank[it] = atomicAdd(slot, ok[it] ? 1u : 0u);
+    }
+  } else {
 #pragma unroll
   for (int it = 0; it < kOsItems; ++it) {
     const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
@@ -256,6 +269,7 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
     uint32_t* slot = lead ? &s_cnt[wave][d] : &s_spare[wave][lane];
     const uint32_t before = atomicAdd(slot, lead ? rank[it] >> 16 : 0u);
     rank[it] = (uint32_t)__shfl(before, (int)leader, 64) + below;
+  }
   }
   __syncthreads();
   uint32_t cnt = 0;           // keys of digit tid in the tile
