@@ -36,12 +36,11 @@ sys.path.insert(0, ROOT)
 METRIC = "closure checks/s + s per M edges at fixed CI; learned-CV vs plain samples"
 PEAK_HBM_GBS = 8000.0
 # bytes the sampler must read per sample besides its search: the centre's
-# adjacency start (8), the two neighbour ids (8), the degree codes of both
-# endpoints (2), the row bounds of the endpoint whose row is searched (16);
-# the other endpoint's row bounds (16) only for a closed sample of a bin
-# (its class needs both degrees); plus 4 bytes per adjacency word the search
-# reads (counted by the kernel).
-BYTES_PER_SAMPLE = 34
+# adjacency start (8), the two neighbour ids (8), the row bounds of the
+# endpoint whose row is searched (16); the other endpoint's row bounds (16)
+# only for a closed sample of a bin (its class needs both degrees); plus 4
+# bytes per adjacency word the search reads (counted by the kernel).
+BYTES_PER_SAMPLE = 32
 BYTES_PER_CLOSED_BIN_SAMPLE = 16
 BYTES_PER_PROBE = 4
 PMC_FILE = os.path.join(ROOT, "profiles", "sample_close_rmat_s24_counters.json")

@@ -9,8 +9,8 @@
 // the LDS holds) in LDS, then each lane carries U independent samples
 // through the dependent gather chain
 //     Philox -> centre class (LDS search) -> adjacency start of the centre
-//            -> col (a, c) -> row-start words of a and c -> binary search
-//            in the shorter row,
+//            -> col (a, c) -> row-start word of a (and of c when a's row
+//            is long) -> search in the chosen row,
 // issuing the loads of its U samples back to back so that U x (waves per CU)
 // chains are in flight per CU.  Class counts are reduced per wave with
 // shuffles, per workgroup in LDS, and added to the row's four uint64
@@ -28,6 +28,13 @@
 #include "scan.hpp"
 
 namespace wedge {
+
+// Degree code (floor of 8 log2 of the degree, Mitchell's form) above which
+// the closure step also reads the other endpoint's word to search the
+// shorter row: about degree 560.
+constexpr uint64_t kLongRowCode = 72;
+// No vertex word has every bit set (row starts are below 2^41).
+constexpr uint64_t kNoWord = ~0ULL;
 
 constexpr int kLdsClasses = 1024;
 constexpr uint32_t kGlobalWord = 0xFFFFFFFFu;
@@ -198,23 +205,25 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       a[u] = act[u] ? col[rp[u] + ia[u]] : 0;
       c[u] = act[u] ? col[rp[u] + ic[u]] : 0;
     }
-    // 4. closure: search one endpoint in the row of the other, the row with
-    //    the smaller degree code (tie: the row of a).  One 8-byte word per
-    //    vertex holds its row start and, in the top byte, its degree code, so
-    //    the two endpoint words plus the searched row's end bound are the
-    //    only loads before the search
+    // 4. closure: search one endpoint in the row of the other.  One 8-byte
+    //    word per vertex holds its row start and, in the top byte, its degree
+    //    code.  The search takes a's row unless that row is long (code above
+    //    kLongRowCode); then c's word is read too and the row with the
+    //    smaller code is searched (tie: a's).  A random line costs more than
+    //    the extra probes of a short row, so c's word is read only where the
+    //    search it may save is long.
     uint64_t da[U], dc[U], my[U];
     bool in_a[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       uint64_t ma = 0, mc = 0;
-      if (act[u]) {
-        ma = A.ix.vmeta[a[u]];
-        mc = A.ix.vmeta[c[u]];
-      }
-      in_a[u] = (ma >> 56) <= (mc >> 56);
+      if (act[u]) ma = A.ix.vmeta[a[u]];
+      const bool both = act[u] && (ma >> 56) > kLongRowCode;
+      if (both) mc = A.ix.vmeta[c[u]];
+      in_a[u] = !both || (ma >> 56) <= (mc >> 56);
       const uint32_t x = in_a[u] ? a[u] : c[u];
-      my[u] = in_a[u] ? mc : ma;  // the other endpoint's row start and code
+      // the other endpoint's word, or kNoWord when it has not been read
+      my[u] = in_a[u] ? (both ? mc : kNoWord) : ma;
       uint64_t r0 = 0, r1 = 0;
       if (act[u]) {
         r0 = (in_a[u] ? ma : mc) & kRowMask;
@@ -293,7 +302,8 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
     for (int u = 0; u < U; ++u) {
       if (act[u] && (A.feat || (found[u] && !global))) {
         const uint32_t y = in_a[u] ? c[u] : a[u];
-        const uint64_t dy = (A.ix.vmeta[y + 1] & kRowMask) - (my[u] & kRowMask);
+        const uint64_t wy = my[u] == kNoWord ? A.ix.vmeta[y] : my[u];
+        const uint64_t dy = (A.ix.vmeta[y + 1] & kRowMask) - (wy & kRowMask);
         if (in_a[u]) dc[u] = dy; else da[u] = dy;
       }
     }
