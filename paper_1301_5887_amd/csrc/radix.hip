@@ -76,14 +76,37 @@ __global__ __launch_bounds__(kOsWG) void k_os_hist_edges(EdgeSource E, OsShifts 
   __syncthreads();
   unsigned long long bad_edges = 0;
   const uint64_t stride = (uint64_t)gridDim.x * kOsWG;
-  for (uint64_t i = (uint64_t)blockIdx.x * kOsWG + tid; i < E.m_in; i += stride) {
-    uint64_t k0, k1;
-    bad_edges += edge_keys(E, i, &k0, &k1) ? 1 : 0;
+  auto count = [&](uint64_t k0, uint64_t k1) {
     for (int p = 0; p < S.npass; ++p) {
       if (S.mirror[p] >= 0) continue;
       atomicAdd(&s_h[p][(k0 >> S.s[p]) & 255], 1u);
       atomicAdd(&s_h[p][(k1 >> S.s[p]) & 255], 1u);
     }
+  };
+  uint64_t i0 = 0;  // edges before i0 are counted by the 16-byte loads
+  if (E.G == 1 && ((((uintptr_t)E.src) | ((uintptr_t)E.dst)) & 15) == 0) {
+    // four edges per lane and load (the same keys edge_keys makes)
+    const uint64_t nq = E.m_in / 4;
+    for (uint64_t q = (uint64_t)blockIdx.x * kOsWG + tid; q < nq; q += stride) {
+      const uint4 su = reinterpret_cast<const uint4*>(E.src)[q];
+      const uint4 du = reinterpret_cast<const uint4*>(E.dst)[q];
+      const uint32_t us[4] = {su.x, su.y, su.z, su.w}, ws[4] = {du.x, du.y, du.z, du.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        uint64_t u = us[h], w = ws[h];
+        if (u >= E.n || w >= E.n) {
+          u = w = 0;
+          ++bad_edges;
+        }
+        count((u << E.ks) | w, (w << E.ks) | u);
+      }
+    }
+    i0 = nq * 4;
+  }
+  for (uint64_t i = i0 + (uint64_t)blockIdx.x * kOsWG + tid; i < E.m_in; i += stride) {
+    uint64_t k0, k1;
+    bad_edges += edge_keys(E, i, &k0, &k1) ? 1 : 0;
+    count(k0, k1);
   }
   bad_edges = wave_sum<unsigned long long>(bad_edges);
   if ((tid & 63) == 0 && bad_edges) atomicAdd(E.rejected, bad_edges);
