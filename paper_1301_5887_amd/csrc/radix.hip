@@ -190,11 +190,10 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
   const uint64_t tile = s_tile;
   const uint64_t tbase = tile * kOsTile;
 
-  // Stable ranking inside the tile: key (wave, it, lane) goes after every
-  // key of its digit in earlier waves, earlier items of its wave and lower
-  // lanes of its item.  The first pass may take its keys in any order (the
-  // edge list has none), so each lane reads whole edges and holds both keys
-  // of an edge.
+  // Keys of the tile: item it of lane l in wave w is key
+  // tbase + (w * kOsItems + it) * 64 + l.  The first pass may take its keys in
+  // any order (the edge list has none), so each lane reads whole edges and
+  // holds both keys of an edge.
   uint64_t key[kOsItems];
   uint32_t rank[kOsItems];
   bool ok[kOsItems];
@@ -253,14 +252,8 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
       }
     }
   }
-  // Per item, the lowest lane of each digit's group adds the group's size to
-  // the wave's counter of that digit (LDS returns the count before it) and
-  // the group reads it from that lane.  A wave's LDS operations complete in
-  // issue order, so item it sees the counts of items 0..it-1.  The peer
-  // masks of all items come first (straight-line code the scheduler can
-  // interleave); rank[it] holds below | leader << 8 | size << 16 until the
-  // counters are read.  Every lane issues the add, the others adding 0 to a
-  // slot of their own, so the adds need no branch.
+  // rank[it]: the key's position among its wave's keys of the same digit
+  // (the waves' counts are combined into tile offsets below).
   if (kEdges) {
     // The edge list has no order to keep, so the first pass ranks each key
     // by an LDS add of 1 on its wave's digit counter: the lanes of one add
@@ -274,25 +267,35 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
       rank[it] = atomicAdd(slot, ok[it] ? 1u : 0u);
     }
   } else {
+    // Stable: key (it, lane) goes after every key of its digit in earlier
+    // items and in lower lanes of its item.  Per item, the lowest lane of
+    // each digit's group adds the group's size to the wave's counter of that
+    // digit (LDS returns the count before it) and the group reads it from
+    // that lane.  A wave's LDS operations complete in issue order, so item it
+    // sees the counts of items 0..it-1.  The peer masks of all items come
+    // first (straight-line code the scheduler can interleave); rank[it] holds
+    // below | leader << 8 | size << 16 until the counters are read.  Every
+    // lane issues the add, the others adding 0 to a slot of their own, so the
+    // adds need no branch.
 #pragma unroll
-  for (int it = 0; it < kOsItems; ++it) {
-    const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
-    const uint64_t peers = digit_peers(d, ok[it]);
-    const uint32_t below =
-        __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
-                                  __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-    const uint32_t leader = (uint32_t)__builtin_ctzll(peers | (1ULL << 63));
-    rank[it] = below | (leader << 8) | ((uint32_t)__popcll(peers) << 16);
-  }
+    for (int it = 0; it < kOsItems; ++it) {
+      const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
+      const uint64_t peers = digit_peers(d, ok[it]);
+      const uint32_t below =
+          __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                    __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+      const uint32_t leader = (uint32_t)__builtin_ctzll(peers | (1ULL << 63));
+      rank[it] = below | (leader << 8) | ((uint32_t)__popcll(peers) << 16);
+    }
 #pragma unroll
-  for (int it = 0; it < kOsItems; ++it) {
-    const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
-    const uint32_t below = rank[it] & 255, leader = (rank[it] >> 8) & 255;
-    const bool lead = ok[it] && below == 0;
-    uint32_t* slot = lead ? &s_cnt[wave][d] : &s_spare[wave][lane];
-    const uint32_t before = atomicAdd(slot, lead ? rank[it] >> 16 : 0u);
-    rank[it] = (uint32_t)__shfl(before, (int)leader, 64) + below;
-  }
+    for (int it = 0; it < kOsItems; ++it) {
+      const uint32_t d = (uint32_t)(key[it] >> shift) & 255;
+      const uint32_t below = rank[it] & 255, leader = (rank[it] >> 8) & 255;
+      const bool lead = ok[it] && below == 0;
+      uint32_t* slot = lead ? &s_cnt[wave][d] : &s_spare[wave][lane];
+      const uint32_t before = atomicAdd(slot, lead ? rank[it] >> 16 : 0u);
+      rank[it] = (uint32_t)__shfl(before, (int)leader, 64) + below;
+    }
   }
   __syncthreads();
   uint32_t cnt = 0;           // keys of digit tid in the tile
