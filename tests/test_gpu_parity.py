@@ -119,6 +119,11 @@ def test_rmat_scale14_ragged_k():
     n, src, dst = gen.rmat_graph500(14, 16, seed=7)
     r = run_both(src, dst, n, tau=2, omega=2, B=40, k=12_345, kg=7_777, seed=3)
     check_all(r)
+    # rows on both sides of degree 2^9: the sampler searches the first
+    # endpoint's row directly when it is short and compares both rows' degree
+    # codes when it is long, so both forms are in the dumped samples
+    deg = r["og"].degrees()
+    assert deg.max() > 2048 and (deg[deg > 1] < 512).any()
 
 
 def test_bter_community_graph():
