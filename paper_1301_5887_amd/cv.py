@@ -78,6 +78,31 @@ def new_records(rows: int, stride: int, device="cuda") -> torch.Tensor:
     return torch.empty(max(rows * stride, 1) * 4, dtype=torch.int32, device=device)
 
 
+class _RoundBuffers:
+    """Device buffers of the training draws and of the sequential rounds,
+    kept between rounds and calls (grown, never shrunk, held until the process
+    ends), so that a timed round allocates no device memory once a first call
+    has sized them.  Calls that use them must not overlap (one stream)."""
+
+    def __init__(self):
+        self._bufs = {}
+
+    def take(self, name: str, n: int, dtype, device) -> torch.Tensor:
+        key = (name, str(torch.device(device)), dtype)
+        n = max(int(n), 1)
+        b = self._bufs.get(key)
+        if b is None or b.numel() < n:
+            b = torch.empty(n, dtype=dtype, device=device)
+            self._bufs[key] = b
+        return b[:n]
+
+    def records(self, name: str, rows: int, stride: int, device) -> torch.Tensor:
+        return self.take(name, max(rows * stride, 1) * 4, torch.int32, device)
+
+
+_ROUND_BUFFERS = _RoundBuffers()
+
+
 class Mlp:
     """Network state on the device (wedge_mlp_*)."""
 
@@ -413,12 +438,15 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             break
         A = len(active)   # records are compact: row j is active[j]
         stride = max(incs)
-        recs = new_records(A, stride, dev)
+        recs = _ROUND_BUFFERS.records("eval", A, stride, dev)
         sample_features(g, bi, hk, sb, seed, DOMAIN_EVAL, True, recs, stride, stream=stream)
-        gv = torch.zeros(A * stride, dtype=torch.float32, device=dev)
-        # g only matters on rows whose beta is not 0 (plain rows use X alone)
+        gv = _ROUND_BUFFERS.take("eval_g", A * stride, torch.float32, dev)
+        # g only matters on rows whose beta is not 0 (plain rows use X alone);
+        # the forward writes every entry, otherwise g is 0
         if net is not None and any((beta or {}).get(r, 0.0) != 0.0 for r in active):
             net.forward(recs, A * stride, gv, stream=stream)
+        else:
+            gv.zero_()
         m = _moments_per_row(recs, gv, incs, stride, dev)
         am = None
         cm, crow = None, []
@@ -435,14 +463,14 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             if crow:
                 cinc = [int(hc[r]) for r in crow]
                 cstride = max(cinc)
-                cout = torch.empty(len(crow) * cstride, dtype=torch.float32, device=dev)
+                cout = _ROUND_BUFFERS.take("centre", len(crow) * cstride, torch.float32, dev)
                 centre_means(g, bi, centre, hc, sc, seed, DOMAIN_CENTRE, cout, cstride,
                              stream=stream)
                 cm = _moments_per_row(None, cout, cinc, cstride, dev)
         elif net is not None and exact_means is None:
-            arecs = new_records(A, stride, dev)
+            arecs = _ROUND_BUFFERS.records("aux", A, stride, dev)
             sample_features(g, bi, hk, sb, seed, DOMAIN_AUX, False, arecs, stride, stream=stream)
-            agv = torch.zeros(A * stride, dtype=torch.float32, device=dev)
+            agv = _ROUND_BUFFERS.take("aux_g", A * stride, torch.float32, dev)
             net.forward(arecs, A * stride, agv, stream=stream)
             am = _moments_per_row(arecs, agv, incs, stride, dev)
         delta_i = delta / (i * (i + 1))
@@ -503,17 +531,17 @@ def train(g: W.Csr, bi: W.BinIndex, rows: list[int], n_train: int, seed: int,
     hk = np.zeros(B + 1, dtype=np.uint64)
     sb = np.zeros(B + 1, dtype=np.uint64)
     hk[rows] = n_fit
-    fit = new_records(R, n_fit, dev)
+    fit = _ROUND_BUFFERS.records("train_fit", R, n_fit, dev)
     sample_features(g, bi, hk, 0, seed, DOMAIN_TRAIN, True, fit, n_fit, stream=stream)
     hk[rows] = n_hold
     sb[rows] = n_fit
-    hold = new_records(R, n_hold, dev)
+    hold = _ROUND_BUFFERS.records("train_hold", R, n_hold, dev)
     sample_features(g, bi, hk, sb, seed, DOMAIN_TRAIN, True, hold, n_hold, stream=stream)
     net = Mlp(dev)
     net.init(init_seed, stream=stream)
     net.train(fit, R, n_fit, n_fit, per_row_batch, epochs, lr=lr, stream=stream)
     losses = [float(net.loss.item())]
-    gv = torch.zeros(R * n_hold, dtype=torch.float32, device=dev)
+    gv = _ROUND_BUFFERS.take("train_hold_g", R * n_hold, torch.float32, dev)
     net.forward(hold, R * n_hold, gv, stream=stream)
     mom = W.to_host_u64(moments(hold, gv, R, n_hold, n_hold)).view(np.int64).reshape(R, 5)
     beta = {r: beta_from_moments(mom[i]) for i, r in enumerate(rows)}
