@@ -30,47 +30,51 @@ __device__ inline void dd_store(unsigned long long* p, uint64_t v) {
   __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Dedup tiles: kDdWG threads with kDdItems keys each.
+constexpr int kDdWG = 256;
+constexpr int kDdItems = 16;
+constexpr uint64_t kDdTile = (uint64_t)kDdWG * kDdItems;
+
 // Row starts and compaction over the sorted keys in one pass.  Tiles of
-// kScanTile keys are taken in ticket order; element (it, tid) of a tile is
-// base + it * 256 + tid (coalesced), and its predecessor is the key of the
+// kDdTile keys are taken in ticket order; element (it, tid) of a tile is
+// base + it * kDdWG + tid (coalesced), and its predecessor is the key of the
 // lane below (the wave's lane 0 reads it from memory), so every key is read
 // once.  A tile counts its kept keys with ballots, publishes the count and
 // finds the kept keys of all earlier tiles by a decoupled look-back (wave 0
 // inspects 64 earlier tiles per step), then writes col and the row starts.
-__global__ __launch_bounds__(kScanWG) void k_dedup(const KeyView k, uint64_t N, uint32_t n,
+__global__ __launch_bounds__(kDdWG) void k_dedup(const KeyView k, uint64_t N, uint32_t n,
                                                    unsigned long long* __restrict__ status,
                                                    unsigned long long* __restrict__ ticket,
                                                    unsigned long long* __restrict__ stalls,
                                                    uint32_t* __restrict__ col,
                                                    uint64_t* __restrict__ rowptr,
                                                    uint64_t* __restrict__ info) {
-  constexpr int kWaves = kScanWG / 64;
-  static_assert(kScanItems * kWaves == 64, "one wave holds the tile's row totals");
-  __shared__ uint32_t s_tot[kScanItems][kWaves];
+  constexpr int kWaves = kDdWG / 64;
+  __shared__ uint32_t s_tot[kDdItems][kWaves];
   __shared__ uint64_t s_tile, s_excl;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) s_tile = atomicAdd(ticket, 1ULL);
   __syncthreads();
   const uint64_t tile = s_tile;
-  const uint64_t base = tile * kScanTile;
-  uint64_t x[kScanItems], prev[kScanItems];
+  const uint64_t base = tile * kDdTile;
+  uint64_t x[kDdItems], prev[kDdItems];
 #pragma unroll
-  for (int it = 0; it < kScanItems; ++it) {
-    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
+  for (int it = 0; it < kDdItems; ++it) {
+    const uint64_t g = base + (uint64_t)it * kDdWG + tid;
     x[it] = g < N ? k[g] : 0;
   }
 #pragma unroll
-  for (int it = 0; it < kScanItems; ++it) {
-    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
+  for (int it = 0; it < kDdItems; ++it) {
+    const uint64_t g = base + (uint64_t)it * kDdWG + tid;
     uint64_t p = __shfl_up(x[it], 1, 64);
     if (lane == 0) p = (g > 0 && g < N) ? k[g - 1] : ~0ULL;
     prev[it] = p;
   }
   uint32_t keep = 0;  // bit it: key (it, tid) is kept
-  uint32_t ex[kScanItems];  // kept keys of lower lanes in this wave's part of row it
+  uint32_t ex[kDdItems];  // kept keys of lower lanes in this wave's part of row it
 #pragma unroll
-  for (int it = 0; it < kScanItems; ++it) {
-    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
+  for (int it = 0; it < kDdItems; ++it) {
+    const uint64_t g = base + (uint64_t)it * kDdWG + tid;
     const bool loop = k.src(x[it]) == k.dst(x[it]);
     const bool kept = g < N && !loop && x[it] != prev[it];
     const uint64_t m = __ballot(kept);
@@ -81,7 +85,9 @@ __global__ __launch_bounds__(kScanWG) void k_dedup(const KeyView k, uint64_t N, 
   }
   __syncthreads();
   if (wave == 0) {
-    const uint64_t agg = wave_sum<uint64_t>((&s_tot[0][0])[lane]);
+    uint64_t part = 0;
+    for (int e = lane; e < kDdItems * kWaves; e += 64) part += (&s_tot[0][0])[e];
+    const uint64_t agg = wave_sum<uint64_t>(part);
     uint64_t excl = 0;
     if (tile == 0) {
       if (lane == 0) dd_store(status, kDdInc | agg);
@@ -118,7 +124,7 @@ __global__ __launch_bounds__(kScanWG) void k_dedup(const KeyView k, uint64_t N, 
   __syncthreads();
   uint64_t run = s_excl;
 #pragma unroll
-  for (int it = 0; it < kScanItems; ++it) {
+  for (int it = 0; it < kDdItems; ++it) {
     uint32_t row = 0, before = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
@@ -126,7 +132,7 @@ __global__ __launch_bounds__(kScanWG) void k_dedup(const KeyView k, uint64_t N, 
       if (w < wave) before += c;
       row += c;
     }
-    const uint64_t g = base + (uint64_t)it * kScanWG + tid;
+    const uint64_t g = base + (uint64_t)it * kDdWG + tid;
     if (g < N) {
       const uint64_t prefix = run + before + ex[it];
       const bool kept = (keep >> it) & 1;
@@ -171,8 +177,8 @@ static size_t csr_layout(uint64_t m_in, CsrWorkspace* w, void* base) {
   off += keys;
   if (w) w->counters = (unsigned long long*)(c + off);
   off += 256;
-  if (w) w->scan_ws = (uint64_t*)(c + off);
-  off += round_up(scan_ws_elems(N) * 8, 256);
+  if (w) w->scan_ws = (uint64_t*)(c + off);  // the dedup's status word per tile
+  off += round_up((ceil_div(N, kDdTile) + 1) * 8, 256);
   if (w) w->radix = (void*)(c + off);
   off += os_scratch_bytes(N);
   return off;
@@ -205,11 +211,11 @@ int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint3
   if (rc) return rc;
   const KeyView sorted{sorted_base, N, ks};
   // one pass: tiles in ticket order, look-back statuses in the scan scratch
-  const uint64_t nb_tiles = ceil_div(N, kScanTile);
+  const uint64_t nb_tiles = ceil_div(N, kDdTile);
   unsigned long long* dd_status = (unsigned long long*)w.scan_ws;
   if ((rc = fill<unsigned long long>(dd_status, nb_tiles, 0, st))) return rc;
   if ((rc = fill<unsigned long long>(w.counters, 1, 0, st))) return rc;
-  k_dedup<<<(unsigned)nb_tiles, kScanWG, 0, st>>>(sorted, N, n, dd_status, w.counters,
+  k_dedup<<<(unsigned)nb_tiles, kDdWG, 0, st>>>(sorted, N, n, dd_status, w.counters,
                                                   osc.tickets + kOsMaxPasses, d_col, d_rowptr,
                                                   d_info);
   WEDGE_LAUNCH_CHECK("k_dedup");
