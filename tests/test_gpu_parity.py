@@ -126,6 +126,17 @@ def test_rmat_scale14_ragged_k():
     assert deg.max() > 2048 and (deg[deg > 1] < 512).any()
 
 
+def test_ids_above_2_24():
+    """Ids above 2^24: the adjacency sort takes 64-bit keys (src << 32 | dst)
+    instead of the packed 48-bit layout, and the dedup reads them as such;
+    the top 1,000 ids are isolated vertices."""
+    scale, m_in = 25, 400_000
+    src, dst = gen.rmat(scale, m_in, 31)
+    n = (1 << scale) + 1000
+    r = run_both(src, dst, n, tau=2, omega=2, B=40, k=3_000, kg=2_000, seed=13)
+    check_all(r)
+
+
 def test_bter_community_graph():
     """BTER-like community graph (dense blocks of similar degree, Chung-Lu
     excess): CSR, bins, every dumped sample and the estimates."""
