@@ -240,9 +240,11 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
     // Search [lo, lo + len) for key.  Ids are spread over [0, n) and a row
     // holds them in ascending order, so in a long row of a single graph the
     // first probe goes where the key's share of the id range points and the
-    // second a few standard deviations further, which leaves a short interval
-    // (one or two cache lines) for the bisection; a bad guess only costs the
-    // two probes.  Stage 0: interpolated probe; 1: window edge; 2: midpoints.
+    // second about one standard deviation further (the key's position is
+    // binomial, sd <= sqrt(len) / 2), which leaves a short interval, often in
+    // the first probe's line, for the bisection; a bad guess only costs the
+    // two probes.  A wider window (two or four sd) read more lines.  Stage 0:
+    // interpolated probe; 1: window edge; 2: midpoints.
     const float inv_n = 1.0f / (float)A.n;  // the guess needs no precision
     uint32_t stage[U];
     uint64_t win[U];
@@ -251,7 +253,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
     for (int u = 0; u < U; ++u) {
       const bool interp = A.num_graphs == 1 && len[u] > 64;
       stage[u] = interp ? 0 : 2;
-      win[u] = interp ? 2 * (uint64_t)__fsqrt_rn((float)len[u]) + 8 : 0;
+      win[u] = interp ? (uint64_t)(0.5f * __fsqrt_rn((float)len[u])) + 8 : 0;
       right[u] = true;
     }
     bool more = true;
