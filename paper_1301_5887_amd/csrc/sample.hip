@@ -238,22 +238,23 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       found[u] = false;
     }
     // Search [lo, lo + len) for key.  Ids are spread over [0, n) and a row
-    // holds them in ascending order, so in a long row of a single graph the
-    // first probe goes where the key's share of the id range points and the
-    // second about one standard deviation further (the key's position is
-    // binomial, sd <= sqrt(len) / 2), which leaves a short interval, often in
-    // the first probe's line, for the bisection; a bad guess only costs the
-    // two probes.  A wider window (two or four sd) read more lines.  Stage 0:
-    // interpolated probe; 1: window edge; 2: midpoints.
+    // holds them in ascending order, so in a row of more than 16 entries of a
+    // single graph the first probe goes where the key's share of the id range
+    // points; the next ones gallop away from it on the key's side (2, 4, 8,
+    // ... entries past the last probe) until one passes the key, and a
+    // bisection finishes inside that step.  The key is usually a few entries
+    // from the guess, so most searches stay in the guess's cache line, and a
+    // bad guess costs O(log distance) probes.  Stage 0: interpolated probe;
+    // 1: galloping; 2: bisection.
     const float inv_n = 1.0f / (float)A.n;  // the guess needs no precision
     uint32_t stage[U];
     uint64_t win[U];
     bool right[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const bool interp = A.num_graphs == 1 && len[u] > 64;
+      const bool interp = A.num_graphs == 1 && len[u] > 16;
       stage[u] = interp ? 0 : 2;
-      win[u] = interp ? (uint64_t)(0.5f * __fsqrt_rn((float)len[u])) + 8 : 0;
+      win[u] = interp ? 2 : 0;  // first galloping step
       right[u] = true;
     }
     bool more = true;
@@ -266,7 +267,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
         if (stage[u] == 0) {
           h[u] = (uint64_t)((float)len[u] * ((float)key[u] * inv_n));
         } else if (stage[u] == 1) {
-          // the key is just past the guess: the window edge on that side
+          // the key is past the last probe: one step further on that side
           if (right[u])
             h[u] = win[u] < len[u] ? win[u] : len[u] - 1;
           else
@@ -282,18 +283,25 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
       for (int u = 0; u < U; ++u) {
         if (len[u] > 0) {
           ++probes;
+          // a galloping probe with the key still beyond it doubles the step
+          bool again = false;
           if (x[u] == key[u]) {
             found[u] = true;
             len[u] = 0;
           } else if (x[u] < key[u]) {
             lo[u] += h[u] + 1;
             len[u] -= h[u] + 1;
+            again = stage[u] == 1 && right[u];
             right[u] = true;
           } else {
             len[u] = h[u];
+            again = stage[u] == 1 && !right[u];
             right[u] = false;
           }
-          stage[u] = stage[u] < 2 ? stage[u] + 1 : 2;
+          if (again)
+            win[u] *= 2;
+          else
+            stage[u] = stage[u] < 2 ? stage[u] + 1 : 2;
           more |= len[u] > 0;
         }
       }
