@@ -638,8 +638,8 @@ def plans_centre(tr: TrainResult, pilot: dict, bi: W.BinIndex, eps: float, delta
 
 
 def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, seed: int = 11,
-            n_train: int = 10_000_000, epochs: int = 1, per_row_batch: int = 4096,
-            lr: float = 2e-2, growth: float = 1.1, aux_form: bool = True,
+            n_train: int = 10_000_000, epochs: int = 1, per_row_batch: int = 8192,
+            lr: float = 4e-2, growth: float = 1.1, aux_form: bool = True,
             exact_form: bool = True, pilot: int = 4096) -> dict:
     """Samples and wall time to reach a half-width <= eps at confidence
     1 - delta on every sampled bin and on the global stream, for plain
