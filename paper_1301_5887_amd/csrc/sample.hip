@@ -31,8 +31,8 @@ namespace wedge {
 
 // Degree code (floor of 8 log2 of the degree, Mitchell's form) above which
 // the closure step also reads the other endpoint's word to search the
-// shorter row: about degree 560.
-constexpr uint64_t kLongRowCode = 72;
+// shorter row: about degree 4,500.
+constexpr uint64_t kLongRowCode = 96;
 // No vertex word has every bit set (row starts are below 2^41).
 constexpr uint64_t kNoWord = ~0ULL;
 

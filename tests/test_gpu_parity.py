@@ -119,11 +119,17 @@ def test_rmat_scale14_ragged_k():
     n, src, dst = gen.rmat_graph500(14, 16, seed=7)
     r = run_both(src, dst, n, tau=2, omega=2, B=40, k=12_345, kg=7_777, seed=3)
     check_all(r)
-    # rows on both sides of degree 2^9: the sampler searches the first
-    # endpoint's row directly when it is short and compares both rows' degree
-    # codes when it is long, so both forms are in the dumped samples
+
+
+def test_rmat_scale16_long_rows():
+    """Rows on both sides of degree 2^12: the sampler searches the first
+    endpoint's row directly when it is short and compares both rows' degree
+    codes when it is long, so both forms are in the dumped samples."""
+    n, src, dst = gen.rmat_graph500(16, 16, seed=7)
+    r = run_both(src, dst, n, tau=2, omega=2, B=40, k=20_000, kg=20_000, seed=5)
+    check_all(r)
     deg = r["og"].degrees()
-    assert deg.max() > 2048 and (deg[deg > 1] < 512).any()
+    assert (deg > 8192).any() and (deg[deg > 1] < 1024).any()
 
 
 def test_ids_above_2_24():
