@@ -79,9 +79,10 @@ uint64_t wedge_hoeffding_k(double eps, double delta);
  *                     undirected non-loop edges; [1] = number of input edges
  *                     rejected because an endpoint was >= n (they are
  *                     dropped; the caller decides whether that is an error).
- *                     [0] = 2^64 - 1 means the sort's bounded wait between
- *                     tiles gave up and rowptr/col are invalid (not expected:
- *                     a tile only waits on tiles that are already running).
+ *                     [0] = 2^64 - 1 means a bounded wait between tiles (of
+ *                     the sort or of the compaction) gave up and rowptr/col
+ *                     are invalid (not expected: a tile only waits on tiles
+ *                     that are already running).
  * Workspace: wedge_build_csr_workspace(m_in, n) bytes of device memory,
  * 256-byte aligned, contents ignored on entry.
  * Errors: EINVAL (null/misaligned pointer), ERANGE (n == 0, m_in >= 2^40),
