@@ -246,12 +246,15 @@ constexpr int kGradWaves = 4;
 constexpr int kGradTilesPerWave = 4;
 constexpr uint64_t kGradChunk = 16ULL * kGradWaves * kGradTilesPerWave;  // records per WG
 
-// LDS operand tiles of one wave (transposes for the weight-gradient products)
+// LDS operand tiles of one wave (transposes for the weight-gradient products).
+// Rows hold 16 values padded to 20 (40 bytes): 8-byte reads stay aligned and
+// the rows a wave touches at once fall in different banks.
+constexpr int kGradRow = 20;
 struct GradSmem {
-  uint16_t da2[kH][16];  // dA2^T [o][s]
-  uint16_t h1[kH][16];   // H1^T  [i][s]
-  uint16_t da1[kH][16];  // dA1^T [i][s]
-  uint16_t x[16][16];    // X     [s][f], f >= 4 zero
+  uint16_t da2[kH][kGradRow];  // dA2^T [o][s]
+  uint16_t h1[kH][kGradRow];   // H1^T  [i][s]
+  uint16_t da1[kH][kGradRow];  // dA1^T [i][s]
+  uint16_t x[16][kGradRow];    // X     [s][f], f >= 4 zero
 };
 
 // Biases and output weights read from LDS (gradient kernel).
