@@ -232,14 +232,16 @@ def main():
     # write col and rowptr) and the bytes of this sort (histogram read of the
     # edges; first pass reads the edges and writes two keys per edge; each
     # later digit pass reads and writes every key, 6 or 8 bytes; the dedup
-    # reads the keys twice and writes col and rowptr)
+    # reads the keys once and writes col and rowptr)
     nkeys = 2 * m_in
     idbits = max(n - 1, 1).bit_length()
-    digits = 2 * ((idbits + 7) // 8)
+    # ids below 2^24: 8-bit digits of dst then of src in 48-bit keys; wider
+    # ids: every 8-bit digit of the 2 * idbits-bit key u << idbits | w
+    digits = 2 * ((idbits + 7) // 8) if idbits <= 24 else (2 * idbits + 7) // 8
     kb = 6 if idbits <= 24 else 8           # bytes per key (packed below 2^24 ids)
     csr_min = 8 * m_in + 4 * 2 * m + 8 * (n + 1)
     csr_sort = (8 * m_in + (8 * m_in + kb * nkeys) + (digits - 1) * 2 * kb * nkeys
-                + 2 * kb * nkeys + 4 * 2 * m + 8 * (n + 1))
+                + kb * nkeys + 4 * 2 * m + 8 * (n + 1))
     t_csr = avg["build_csr"] / 1000.0
     roofline_csr = {"phase": "wedge_build_csr", "bound": "hbm", "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "digit_passes": digits, "key_bytes": kb,

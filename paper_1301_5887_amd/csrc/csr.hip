@@ -5,7 +5,8 @@
 // 1. Onesweep LSD radix sort of the directed keys u<<ks|w and w<<ks|u of
 //    every input edge (u, w) over the significant digits of dst, then of
 //    src; ks = 24 when every id is below 2^24 (48-bit keys in the packed
-//    layout, 6 bytes moved per key and pass), else 32.  The first pass builds
+//    layout, 6 bytes moved per key and pass), else the ids' bit width (keys
+//    of 2 ks bits in uint64, every 8-bit digit of them one pass).  The first pass builds
 //    the keys from the edge list as it reads it (a self-loop stays a key
 //    u<<ks|u; an edge with an id >= n becomes the self-loop 0 and is counted
 //    as rejected).
@@ -195,14 +196,20 @@ int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint3
   int rc = fill<uint64_t>(d_info, 2, 0, st);
   if (rc) return rc;
   if (N == 0) return fill<uint64_t>(d_rowptr, (uint64_t)n + 1, 0, st);
-  // digits of dst (bits 0..nb) then of src (bits ks..ks+nb); ids below 2^24
-  // make 48-bit keys, sorted in the packed layout
+  // Ids below 2^24 make 48-bit keys u << 24 | w, sorted in the packed layout
+  // by the digits of dst (bits 0..nb) then of src (bits 24..24+nb).  Wider
+  // ids make keys u << nb | w with no unused bits between the ids, sorted by
+  // the 8-bit digits of all 2 nb bits (28-bit ids: 7 passes instead of 8).
   int shifts[16];
   int np = 0;
   const int nb = bit_width((uint64_t)n - 1);
-  const int ks = nb <= 24 ? 24 : 32;
-  for (int s = 0; s < nb; s += 8) shifts[np++] = s;
-  for (int s = 0; s < nb; s += 8) shifts[np++] = ks + s;
+  const int ks = nb <= 24 ? 24 : nb;
+  if (ks == 24) {
+    for (int s = 0; s < nb; s += 8) shifts[np++] = s;
+    for (int s = 0; s < nb; s += 8) shifts[np++] = ks + s;
+  } else {
+    for (int s = 0; s < 2 * nb; s += 8) shifts[np++] = s;
+  }
   if (np == 0) shifts[np++] = 0;  // n == 1: one pass still writes the keys
   EdgeSource E{d_src, d_dst, m_in, n, d_eoff, d_voff, G, (unsigned long long*)(d_info + 1), ks};
   uint64_t* sorted_base = nullptr;

@@ -432,7 +432,7 @@ int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int
   for (int p = 0; p < npass; ++p) {
     const uint64_t tag = (uint64_t)(p + 1) << 56;
     const uint64_t* base = sc.base + p * 256;
-    if (E.ks == 32) {
+    if (E.ks > 24) {
       if (p == 0)
         k_os_pass<true><<<(unsigned)nt, kOsWG, 0, st>>>(E, nullptr, dst, N, shifts[p], tag, base,
                                                          sc.status, sc.tickets + p);

@@ -70,10 +70,11 @@ struct EdgeSource {
   const uint32_t* voff;  // [G + 1] vertex offsets (G > 1)
   uint32_t G;
   unsigned long long* rejected;
-  // bit position of the source id in a key (key = u << ks | w).  32: 64-bit
-  // keys; 24 (every id < 2^24): 48-bit keys, stored packed as a uint32 array
-  // of their low words followed by a uint16 array of their high words, so a
-  // pass moves 6 bytes per key instead of 8.
+  // bit position of the source id in a key (key = u << ks | w).  24 (every
+  // id < 2^24): 48-bit keys, stored packed as a uint32 array of their low
+  // words followed by a uint16 array of their high words, so a pass moves 6
+  // bytes per key instead of 8; above 24 (ks = the ids' bit width, so the key
+  // has no unused bits between the two ids): keys stored as uint64.
   int ks = 32;
 };
 
@@ -83,7 +84,7 @@ struct KeyView {
   uint64_t N;
   int ks;
   __device__ __forceinline__ uint64_t operator[](uint64_t i) const {
-    if (ks == 32) return k[i];
+    if (ks > 24) return k[i];
     const uint32_t* lo = (const uint32_t*)k;
     const uint16_t* hi = (const uint16_t*)(lo + N);
     return (uint64_t)lo[i] | ((uint64_t)hi[i] << 32);
