@@ -57,10 +57,10 @@ inline OsScratch os_scratch(void* p, uint64_t N) {
   return s;
 }
 
-// Directed keys of an edge list: key 2i = u<<32|w and key 2i+1 = w<<32|u of
+// Directed keys of an edge list: key 2i = u<<ks|w and key 2i+1 = w<<ks|u of
 // edge i = (u, w); in a batch (G > 1) ids are local to their graph and are
 // shifted by its vertex offset; an edge with an id out of range becomes the
-// self-loop 0<<32|0 (dropped later) and is counted once.
+// self-loop 0<<ks|0 (dropped later) and is counted once.
 struct EdgeSource {
   const uint32_t* src;
   const uint32_t* dst;
