@@ -48,6 +48,9 @@ def lib():
         if not os.path.exists(_LIB):
             build()
         L = ctypes.CDLL(_LIB)
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
         L.orc_lemire16.argtypes = [ctypes.c_uint32, _u16p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.orc_lemire16.restype = ctypes.c_uint32
@@ -99,6 +102,16 @@ def lib():
 
 def _p(a: np.ndarray, t):
     return a.ctypes.data_as(t)
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(lib().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Thread count of the oracle's later parallel loops (process-wide)."""
+    lib().orc_set_num_threads(int(t))
 
 
 # ---------------------------------------------------------------- primitives
@@ -161,18 +174,44 @@ class Graph:
         return np.diff(self.rowptr)
 
 
-def build_graph(src, dst, n: int) -> Graph:
-    """Canonical undirected simple graph and its adjacency (Sec. 4.1, 5.1)."""
+def build_graph(src, dst, n: int, progress=None) -> Graph:
+    """Canonical undirected simple graph and its adjacency (Sec. 4.1, 5.1).
+    `progress` (a print function) gets a line after the canonical keys."""
     s = np.ascontiguousarray(src, dtype=np.uint32)
     d = np.ascontiguousarray(dst, dtype=np.uint32)
     keys = np.empty(max(len(s), 1), dtype=np.uint64)
     rej = np.zeros(1, dtype=np.uint64)
     m = int(lib().orc_canon(_p(s, _u32p), _p(d, _u32p), len(s), n, _p(keys, _u64p), _p(rej, _u64p)))
-    keys = keys[:m].copy()
+    keys = keys[:m]       # a view: no second copy of a multi-GB key array
+    if progress:
+        progress(f"[oracle] {m} canonical edge keys sorted")
     rowptr = np.zeros(n + 1, dtype=np.uint64)
     col = np.zeros(max(2 * m, 1), dtype=np.uint32)
     lib().orc_csr(_p(keys, _u64p), m, n, _p(rowptr, _u64p), _p(col, _u32p))
     return Graph(n=n, keys=keys, rowptr=rowptr, col=col[: 2 * m], rejected=int(rej[0]))
+
+
+def sparse_rows(src, dst, n: int):
+    """The adjacency of Sec. 4.1 / 5.1 (undirected, self-loops and repeats
+    dropped, ids >= n rejected) for graphs whose n is too large for dense
+    rows: returns (the vertices that have edges, ascending; their degrees;
+    the concatenation of their rows, each ascending; the number of rejected
+    input edges).  Plain numpy, for any n < 2^32."""
+    s = np.asarray(src, dtype=np.uint64)
+    d = np.asarray(dst, dtype=np.uint64)
+    bad = (s >= n) | (d >= n)
+    keep = ~bad & (s != d)
+    lo = np.minimum(s[keep], d[keep])
+    hi = np.maximum(s[keep], d[keep])
+    edges = np.unique((lo << np.uint64(32)) | hi)
+    a = edges >> np.uint64(32)
+    b = edges & np.uint64(0xFFFFFFFF)
+    u = np.concatenate([a, b])
+    w = np.concatenate([b, a])
+    order = np.lexsort((w, u))
+    u, w = u[order], w[order]
+    verts, deg = np.unique(u, return_counts=True)
+    return verts, deg.astype(np.uint64), w.astype(np.uint32), int(bad.sum())
 
 
 def bins(g: Graph, tau: int, omega: int, max_bins: int):

@@ -177,6 +177,15 @@ struct BinTable {
 
 inline uint64_t choose2(uint64_t d) { return d < 2 ? 0 : d * (d - 1) / 2; }
 
+// (degree, id) pairs in ascending order: the centre order of a bin.
+inline void psort(std::vector<std::pair<uint64_t, uint32_t>>& dv) {
+#ifdef _OPENMP
+  __gnu_parallel::sort(dv.begin(), dv.end());
+#else
+  std::sort(dv.begin(), dv.end());
+#endif
+}
+
 inline bool has_edge(const uint64_t* keys, uint64_t m, uint32_t a, uint32_t c) {
   uint32_t lo = a < c ? a : c, hi = a < c ? c : a;
   uint64_t key = ((uint64_t)lo << 32) | hi;
@@ -186,6 +195,25 @@ inline bool has_edge(const uint64_t* keys, uint64_t m, uint32_t a, uint32_t c) {
 }  // namespace
 
 extern "C" {
+
+// Threads an OpenMP region of the oracle uses (1 without OpenMP).
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// Sets the thread count of the oracle's later parallel regions (and of
+// any other OpenMP code in the process).
+void orc_set_num_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
 
 // -------------------------------------------------------------- primitives
 void orc_philox4x64_10(const uint64_t* ctr, const uint64_t* key, uint64_t* out) {
@@ -237,44 +265,55 @@ uint64_t orc_hoeffding_k(double eps, double delta) {
 // Canonical edge set (Sec. 4.1 input convention; Sec. 5.1 "treated as
 // undirected"): drop self-loops, store (min, max) as key min<<32|max, sort,
 // remove duplicates.  Edges with an id >= n are rejected and counted.
-// Returns m; keys_out must hold m_in entries.
+// Returns m; keys_out must hold m_in entries.  Dropped edges first take the
+// value 2^64-1, which no kept key can have (its low word would be an id
+// >= 2^32-1 > max), so after the sort they sit at the end and are cut off.
 uint64_t orc_canon(const uint32_t* src, const uint32_t* dst, uint64_t m_in, uint32_t n,
                    uint64_t* keys_out, uint64_t* rejected) {
-  uint64_t cnt = 0, rej = 0;
-  for (uint64_t i = 0; i < m_in; ++i) {
+  const uint64_t kDropped = ~(uint64_t)0;
+  uint64_t rej = 0;
+#pragma omp parallel for schedule(static) reduction(+ : rej)
+  for (int64_t i = 0; i < (int64_t)m_in; ++i) {
     uint32_t u = src[i], w = dst[i];
-    if (u >= n || w >= n) { ++rej; continue; }
-    if (u == w) continue;
+    if (u >= n || w >= n) { ++rej; keys_out[i] = kDropped; continue; }
+    if (u == w) { keys_out[i] = kDropped; continue; }
     uint32_t lo = u < w ? u : w, hi = u < w ? w : u;
-    keys_out[cnt++] = ((uint64_t)lo << 32) | hi;
+    keys_out[i] = ((uint64_t)lo << 32) | hi;
   }
 #ifdef _OPENMP
-  __gnu_parallel::sort(keys_out, keys_out + cnt);
+  __gnu_parallel::sort(keys_out, keys_out + m_in);
 #else
-  std::sort(keys_out, keys_out + cnt);
+  std::sort(keys_out, keys_out + m_in);
 #endif
+  uint64_t cnt = (uint64_t)(std::lower_bound(keys_out, keys_out + m_in, kDropped) - keys_out);
   uint64_t m = (uint64_t)(std::unique(keys_out, keys_out + cnt) - keys_out);
   if (rejected) *rejected = rej;
   return m;
 }
 
 // Adjacency lists from canonical keys: N(v) holds every neighbour once, in
-// ascending id order.  rowptr[n+1], col[2m].
+// ascending id order.  rowptr[n+1], col[2m].  Rows are filled in any order
+// (parallel) and then each row is sorted, so the result is the definition's.
 void orc_csr(const uint64_t* keys, uint64_t m, uint32_t n, uint64_t* rowptr, uint32_t* col) {
   std::vector<uint64_t> deg(n, 0);
-  for (uint64_t e = 0; e < m; ++e) {
-    deg[(uint32_t)(keys[e] >> 32)]++;
-    deg[(uint32_t)keys[e]]++;
+  uint64_t* dg = deg.data();
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < (int64_t)m; ++e) {
+    __atomic_fetch_add(&dg[(uint32_t)(keys[e] >> 32)], 1, __ATOMIC_RELAXED);
+    __atomic_fetch_add(&dg[(uint32_t)keys[e]], 1, __ATOMIC_RELAXED);
   }
   rowptr[0] = 0;
   for (uint32_t v = 0; v < n; ++v) rowptr[v + 1] = rowptr[v] + deg[v];
   std::vector<uint64_t> fill(rowptr, rowptr + n);
-  for (uint64_t e = 0; e < m; ++e) {
+  uint64_t* fl = fill.data();
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < (int64_t)m; ++e) {
     uint32_t a = (uint32_t)(keys[e] >> 32), b = (uint32_t)keys[e];
-    col[fill[a]++] = b;
-    col[fill[b]++] = a;
+    col[__atomic_fetch_add(&fl[a], 1, __ATOMIC_RELAXED)] = b;
+    col[__atomic_fetch_add(&fl[b], 1, __ATOMIC_RELAXED)] = a;
   }
-  for (uint32_t v = 0; v < n; ++v) std::sort(col + rowptr[v], col + rowptr[v + 1]);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t v = 0; v < (int64_t)n; ++v) std::sort(col + rowptr[v], col + rowptr[v + 1]);
 }
 
 // Phase 1b: per bin b, n_b = #vertices, p_b = sum of C(d,2).  Degree-0
@@ -283,15 +322,18 @@ int orc_bins(const uint64_t* rowptr, uint32_t n, uint32_t tau, uint64_t omega, u
              uint64_t* n_b, uint64_t* p_b) {
   for (uint32_t b = 0; b < max_bins; ++b) n_b[b] = p_b[b] = 0;
   BinTable bins(tau, omega, max_bins);
-  for (uint32_t v = 0; v < n; ++v) {
+  int out_of_range = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_b[:max_bins], p_b[:max_bins]) \
+    reduction(| : out_of_range)
+  for (int64_t v = 0; v < (int64_t)n; ++v) {
     uint64_t d = rowptr[v + 1] - rowptr[v];
     if (d == 0) continue;
     uint32_t b = bins(d);
-    if (b >= max_bins) return -2;
+    if (b >= max_bins) { out_of_range = 1; continue; }
     n_b[b] += 1;
     p_b[b] += choose2(d);
   }
-  return 0;
+  return out_of_range ? -2 : 0;
 }
 
 // The centre order of the global stream: every vertex with d >= 2, sorted
@@ -302,7 +344,7 @@ uint64_t orc_center_order(const uint64_t* rowptr, uint32_t n, uint32_t* order_ou
     uint64_t d = rowptr[v + 1] - rowptr[v];
     if (d >= 2) dv.push_back({d, v});
   }
-  std::sort(dv.begin(), dv.end());
+  psort(dv);
   for (size_t i = 0; i < dv.size(); ++i) order_out[i] = dv[i].second;
   return dv.size();
 }
@@ -332,20 +374,23 @@ int orc_sample(const uint64_t* rowptr, const uint32_t* col, uint32_t n, const ui
   std::vector<uint64_t> deg(n);
   std::vector<uint32_t> vbin(n, 0);
   BinTable bins(tau, omega, max_bins);
-  for (uint32_t v = 0; v < n; ++v) {
+  int out_of_range = 0;
+#pragma omp parallel for schedule(static) reduction(| : out_of_range)
+  for (int64_t v = 0; v < (int64_t)n; ++v) {
     deg[v] = rowptr[v + 1] - rowptr[v];
     if (deg[v] == 0) continue;
     uint32_t b = bins(deg[v]);
-    if (b >= max_bins) return -1;
+    if (b >= max_bins) out_of_range = 1;
     vbin[v] = b;
   }
+  if (out_of_range) return -1;
   // L_b lists ordered by (d, id) and their inclusive prefix sums of p_v.
   std::vector<uint32_t> order;
   {
     std::vector<std::pair<uint64_t, uint32_t>> dv;
     for (uint32_t v = 0; v < n; ++v)
       if (deg[v] >= 2) dv.push_back({deg[v], v});
-    std::sort(dv.begin(), dv.end());
+    psort(dv);
     order.resize(dv.size());
     for (size_t i = 0; i < dv.size(); ++i) order[i] = dv[i].second;
   }
@@ -447,7 +492,7 @@ int orc_sample_alloc(const uint64_t* rowptr, const uint32_t* col, uint32_t n,
   std::vector<std::pair<uint64_t, uint32_t>> dv;
   for (uint32_t v = 0; v < n; ++v)
     if (deg[v] >= 2) dv.push_back({deg[v], v});
-  std::sort(dv.begin(), dv.end());
+  psort(dv);
   std::vector<std::vector<uint32_t>> L(max_bins + 1);
   std::vector<uint64_t> pb(max_bins + 1, 0);
   for (auto& e : dv) {

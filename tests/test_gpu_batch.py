@@ -145,13 +145,17 @@ def test_batch_graph500_recipe_reduced_scales():
     bt.destroy_graph()
 
 
-def test_batch_full_recipe_sampled_oracle():
+FULL_CHUNKS = 8
+
+
+@pytest.fixture(scope="module")
+def full_recipe():
     """The batched workload at its full size: 512 R-MAT graphs (Graph500
-    parameters, scales 10..20 and edge factors 8..32 drawn from the batch seed,
-    seeds 100..611), 20,000 samples per bin and per global stream, the launch
-    shape picked by the autotuner, the whole pipeline captured into one HIP
-    graph and replayed; every 16th graph (and the largest) is compared
-    bit-exact with the oracle run on that graph alone."""
+    parameters, scales 10..20 and edge factors 8..32 drawn from the batch
+    seed, seeds 100..611), 20,000 samples per bin and per global stream, the
+    launch shape picked by the autotuner, the whole pipeline captured into
+    one HIP graph and replayed.  Returns the graphs and the replay's
+    per-graph results (host copies; the device batch is released)."""
     import time
     shapes = gen.batch_shapes(512, seed=100)
     graphs = []
@@ -169,6 +173,8 @@ def test_batch_full_recipe_sampled_oracle():
     print(f"[batch-full] autotune ms={['%.3f' % t for t in ms]} best={best.lanes_in_flight},"
           f"{best.samples_per_tile},{best.workgroups}", flush=True)
     bt.capture(best, delta=delta)
+    bt.q.zero_()
+    torch.cuda.synchronize()
     bt.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -177,18 +183,36 @@ def test_batch_full_recipe_sampled_oracle():
     print(f"[batch-full] one replay of the whole pipeline: {time.perf_counter() - t0:.4f} s",
           flush=True)
     h = bt.host()
-    largest = int(np.argmax([len(x[1]) for x in graphs]))
-    pick = sorted(set(range(0, 512, 16)) | {largest})
-    for g in pick:
+    bt.destroy_graph()
+    del bt
+    torch.cuda.empty_cache()
+    return dict(graphs=graphs, h=h, tau=tau, omega=omega, B=B, k=k, seed=seed, delta=delta)
+
+
+@pytest.mark.parametrize("chunk", range(FULL_CHUNKS))
+def test_batch_full_recipe_oracle(full_recipe, chunk):
+    """Every graph of the full-size batch (this chunk's 64 of the 512)
+    against the oracle run on that graph alone: n_b, p_b and q bit-exact,
+    the device's FP64 estimates within 1e-12."""
+    F = full_recipe
+    graphs, h, B, k = F["graphs"], F["h"], F["B"], F["k"]
+    per = len(graphs) // FULL_CHUNKS
+    lo, hi = chunk * per, (chunk + 1) * per if chunk < FULL_CHUNKS - 1 else len(graphs)
+    print(f"[batch-full] oracle graphs {lo}..{hi - 1}", flush=True)
+    for g in range(lo, hi):
         n, src, dst = graphs[g]
         og = O.build_graph(src, dst, n)
-        n_b, p_b = O.bins(og, tau, omega, B)
+        n_b, p_b = O.bins(og, F["tau"], F["omega"], B)
         kb = O.k_for_bins(p_b, k)
         kgg = k if int(p_b.sum()) > 0 else 0
-        s = O.sample(og, tau, omega, B, kb, kgg, seed, graph_id=g)
-        per_bin, glob = O.estimate(p_b, s.q, kb, kgg, delta)
+        s = O.sample(og, F["tau"], F["omega"], B, kb, kgg, F["seed"], graph_id=g)
+        per_bin, glob = O.estimate(p_b, s.q, kb, kgg, F["delta"])
         assert (h["n_b"][g] == n_b).all() and (h["p_b"][g] == p_b).all(), g
         assert (h["q"][g] == s.q).all(), g
         for j in range(6):
             assert abs(h["est_glob"][g][j] - glob[j]) <= REL * max(1.0, abs(glob[j])), (g, j)
-    bt.destroy_graph()
+        eb = h["est_bins"][g]
+        for b in range(B):
+            for j in range(3):
+                x, y = eb[b, j], per_bin[b, j]
+                assert abs(x - y) <= REL * max(1.0, abs(y)), (g, b, j)

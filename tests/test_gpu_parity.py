@@ -132,15 +132,59 @@ def test_rmat_scale16_long_rows():
     assert (deg > 8192).any() and (deg[deg > 1] < 1024).any()
 
 
-def test_ids_above_2_24():
-    """Ids above 2^24: the adjacency sort takes 64-bit keys (src << 32 | dst)
-    instead of the packed 48-bit layout, and the dedup reads them as such;
-    the top 1,000 ids are isolated vertices."""
-    scale, m_in = 25, 400_000
-    src, dst = gen.rmat(scale, m_in, 31)
-    n = (1 << scale) + 1000
+@pytest.mark.parametrize("nb", [25, 28, 31])
+def test_ids_above_2_24(nb):
+    """Ids of nb > 24 bits: the adjacency sort takes keys u << nb | w (2 nb
+    significant bits in a uint64, ceil(2 nb / 8) digit passes) instead of the
+    packed 48-bit layout.  Ids are spread over the whole range (relabelled
+    R-MAT), a triangle sits on the three largest ids, and the top 3 ids of
+    the range [0, 2^nb) are beyond n (so edges to them are rejected)."""
+    m_in = 400_000
+    src, dst = gen.rmat(nb, m_in, 31 + nb)
+    n = (1 << nb) - 3
+    top = np.array([n - 1, n - 2, n - 3], dtype=np.uint32)
+    src = np.concatenate([src, top, [n + 1, 5]]).astype(np.uint32)
+    dst = np.concatenate([dst, np.roll(top, 1), [7, n + 2]]).astype(np.uint32)
     r = run_both(src, dst, n, tau=2, omega=2, B=40, k=3_000, kg=2_000, seed=13)
+    assert (n - 1).bit_length() == nb
+    assert r["og"].degrees()[n - 1] >= 2
     check_all(r)
+
+
+def test_ids_of_32_bits():
+    """n = 2^32 - 1, the largest n: 64-bit keys u << 32 | w over eight digit
+    passes.  The adjacency is compared row by row on the vertices that have
+    edges (every other row must be empty) against the definition computed
+    sparsely: a dense oracle adjacency of 2^32 rows is not built."""
+    m_in = 300_000
+    src, dst = gen.rmat(32, m_in, 77)
+    n = (1 << 32) - 1
+    src[:10] = n - 1 - np.arange(10, dtype=np.uint32)
+    dst[:10] = n - 2 - np.arange(10, dtype=np.uint32)
+    src[10] = n                                   # id n is out of range
+    print(f"[parity] n={n} m_in={m_in} (32-bit ids)", flush=True)
+    g = W.build_csr(dev(src), dev(dst), n)
+    torch.cuda.synchronize()
+    verts, rowlen, cols, rejected = O.sparse_rows(src, dst, n)
+    assert g.rejected == rejected >= 1
+    assert g.m * 2 == cols.shape[0]
+    # rows with edges: their starts and lengths, in order of vertex id
+    rp = g.rowptr
+    starts = rp[torch.from_numpy(verts.astype(np.int64)).cuda()].cpu().numpy().view(np.uint64)
+    ends = rp[torch.from_numpy(verts.astype(np.int64) + 1).cuda()].cpu().numpy().view(np.uint64)
+    assert (ends - starts == rowlen).all()
+    expect_start = np.concatenate([[0], np.cumsum(rowlen)[:-1]]).astype(np.uint64)
+    assert (starts == expect_start).all()
+    # every other row is empty: the row starts only grow at those vertices
+    assert int(rp[-1].item()) == cols.shape[0] and int(rp[0].item()) == 0
+    nz = 0
+    step = 1 << 28
+    for a in range(0, n, step):
+        b = min(a + step, n)
+        nz += int((rp[a + 1: b + 1] != rp[a: b]).sum().item())
+    assert nz == verts.shape[0]
+    col = g.col[: 2 * g.m].cpu().numpy().view(np.uint32)
+    assert (col == cols).all()
 
 
 def test_bter_community_graph():

@@ -163,6 +163,29 @@ def test_exact_mode_matches_python_brute_force(seed):
     assert int(P[B, 3]) == 3 * t
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sparse_rows_match_python_brute_force(seed):
+    """The sparse adjacency (for n too large for dense rows) against the
+    pure-Python adjacency sets, with ids near 2^32 and rejected ids."""
+    rng = np.random.default_rng(seed)
+    n = (1 << 32) - 1
+    ids = [int(x) for x in rng.integers(n - 40, n, 12)] + [0, 1, 2]
+    edges = [(ids[int(rng.integers(len(ids)))], ids[int(rng.integers(len(ids)))])
+             for _ in range(60)] + [(n, 3), (5, n)]
+    src = np.array([e[0] for e in edges], dtype=np.uint32)
+    dst = np.array([e[1] for e in edges], dtype=np.uint32)
+    verts, deg, cols, rejected = O.sparse_rows(src, dst, n)
+    assert rejected == 2
+    adj = {}
+    for u, w in edges:
+        if u != w and u < n and w < n:
+            adj.setdefault(u, set()).add(w)
+            adj.setdefault(w, set()).add(u)
+    assert verts.tolist() == sorted(adj)
+    assert deg.tolist() == [len(adj[v]) for v in sorted(adj)]
+    assert cols.tolist() == [w for v in sorted(adj) for w in sorted(adj[v])]
+
+
 def test_identities_on_heavy_tailed_graph():
     n, s, d = gen.chung_lu_c1(1)
     g = O.build_graph(s, d, n)
