@@ -597,12 +597,140 @@ typedef struct {
 
 int wedge_triangle_box(const uint64_t* h_hist, uint32_t max_bins, wedge_triangle_box_row* h_out);
 
+/* ------------------------------------------------------------------------
+ * Control-variate estimator (host-only arithmetic; the estimand is c_b of
+ * Thm. cd-est).  Inputs are the integer moments of wedge_cv_moments,
+ * m = [count, sum X, 2^32 sum g, 2^32 sum g^2, 2^32 sum X g].  With
+ * n = m[0], mx = m[1]/n, mg = m[2]/2^32/n and (n - 1)-denominator
+ *   var_x = (m[1] - n mx^2)/(n-1),  var_g = (m[3]/2^32 - n mg^2)/(n-1),
+ *   cov   = (m[4]/2^32 - n mx mg)/(n-1),  var_z = var_x - 2 beta cov + beta^2 var_g,
+ * the estimate of a row is mean(X - beta g) + beta mu = mx - beta mg + beta mu.
+ * ---------------------------------------------------------------------- */
+
 /* Empirical-Bernstein half-width (Maurer & Pontil 2009, Thm. 4, two-sided,
  * each side at delta/2) of the mean of n i.i.d. values in an interval of
- * length R with sample variance var:
+ * length R with sample variance var (negative var taken as 0):
  *   sqrt(2 var ln(4/delta) / n) + 7 R ln(4/delta) / (3 (n - 1)).
  * Host-only; returns +inf for n < 2. */
 double wedge_eb_halfwidth(uint64_t n, double var, double R, double delta);
+
+/* Planning size for that bound to reach eps: with n - 1 taken as n, the
+ * positive root x = 1/sqrt(n) of a x + b x^2 = eps, a = sqrt(2 var ln(4/delta)),
+ * b = 7 R ln(4/delta) / 3; returns ceil(1/x^2) + 1 (0 for eps <= 0, R <= 0
+ * or delta outside (0, 1)).  A plan only: stopping uses the exact bound. */
+uint64_t wedge_eb_samples(double var, double R, double delta, double eps);
+
+/* Running total of a row's draws after round `round` >= 1 of a plan that
+ * starts at `first` and grows by `growth` per round:
+ * min(ceil(first growth^(round-1)), max_per_row); 0 for round 0. */
+uint64_t wedge_cv_round_size(uint64_t first, double growth, uint32_t round,
+                             uint64_t max_per_row);
+
+/* Fit of the control variate per row from held-out TRAIN moments (h_mom
+ * [rows][5]): beta = Cov(X, g) / Var(g) and rho^2 = Cov^2 / (Var X Var g) from
+ * n-denominator moments (0 when Var g <= 1e-14 or n < 2), var_x and var_z
+ * ((n - 1) denominators; 0.25 each when n < 2), and the first-round sizes
+ * wedge_eb_samples at delta / 2 for plain sampling (var_x, range 1) and for
+ * the control variate (var_z, range 1 + |beta|).  The fit uses no EVAL draw,
+ * so the estimate stays unbiased.  Errors: EINVAL. */
+typedef struct {
+  double beta, rho2, var_x, var_z;
+  uint64_t plan_plain, plan_cv;
+} wedge_cv_fit_row;
+int wedge_cv_fit(const int64_t* h_mom, uint32_t rows, double eps, double delta,
+                 wedge_cv_fit_row* h_out);
+
+/* Where the mean mu of g comes from. */
+enum { WEDGE_CV_PLAIN = 0,   /* beta ignored: the plain mean of X, range 1 */
+       WEDGE_CV_EXACT = 1,   /* mu = exact_mean (census): whole delta_i on the EVAL draws */
+       WEDGE_CV_AUX = 2,     /* mu = mean of g over AUX draws (an, ag, ag2) */
+       WEDGE_CV_CENTRE = 3   /* mu = mean of gbar over centre draws (an, ag, ag2);
+                                beta = 0 is the plain form */ };
+
+typedef struct {
+  int64_t n, sx, sg, sg2, sxg;   /* EVAL moments accumulated so far */
+  int64_t an, ag, ag2;           /* second sample: count, 2^32 sum, 2^32 sum of squares */
+  double beta;                   /* fixed before any EVAL draw */
+  double exact_mean;             /* WEDGE_CV_EXACT only */
+  uint32_t mode;                 /* WEDGE_CV_* */
+  uint32_t pad;
+  uint64_t done;                 /* EVAL draws taken so far (checked against the cap) */
+} wedge_cv_row;
+
+typedef struct {
+  double estimate;   /* NaN when a sample has fewer than 2 draws */
+  double halfwidth;  /* +inf then */
+  int32_t more;      /* 1: halfwidth > eps and done < max_per_row */
+  int32_t pad;
+} wedge_cv_result;
+
+/* Estimate, half-width and stop decision of every row after round `round`
+ * (>= 1) of the sequential rule: delta_i = delta / (round (round + 1)) (a
+ * union bound over rounds).  PLAIN: mx, EB(n, var_x, 1, delta_i).  EXACT:
+ * mx - beta mg + beta exact_mean, EB(n, var_z, 1 + |beta|, delta_i).  AUX and
+ * CENTRE (beta != 0): mx - beta mg + beta am with am, av the mean and
+ * (an - 1)-denominator variance of the second sample,
+ * EB(n, var_z, 1 + |beta|, delta_i/2) + |beta| EB(an, av, 1, delta_i/2).
+ * Errors: EINVAL (null pointer, round 0, eps <= 0, delta outside (0,1),
+ * unknown mode). */
+int wedge_cv_estimate(const wedge_cv_row* h_rows, uint32_t nrows, uint32_t round, double delta,
+                      double eps, uint64_t max_per_row, wedge_cv_result* h_out);
+
+/* Exact mean of g per bin from the per-key sums of wedge_cv_exact_mean:
+ * h_mean[b] = (sum of h_key_sum over keys of bin b) / (their wedge counts),
+ * summed in key order; h_mean[max_bins] = the same over every key (the
+ * global stream's mean); h_count[b] = wedges of the bin (p_b), and
+ * h_count[max_bins] = p.  Bins without keys get mean 0 and count 0.
+ * Errors: EINVAL (null pointer, a key's bin >= max_bins). */
+int wedge_cv_bin_means(const double* h_key_sum, const uint64_t* h_key_count,
+                       const uint32_t* h_key_bin, uint32_t nkeys, uint32_t max_bins,
+                       double* h_mean, uint64_t* h_count);
+
+/* Mean (2^32 sum / count; NaN for count 0) and (n - 1)-denominator variance
+ * (0 for count < 2, negative taken as 0) of the values whose moments are
+ * h_mom[rows][5] (entries 0, 2, 3 used). */
+int wedge_cv_mean_var(const int64_t* h_mom, uint32_t rows, double* h_mean, double* h_var);
+
+/* Modelled cost of one centre draw of row `row` (a bin < max_bins, or the
+ * global stream = max_bins) in EVAL draws: 1 + a d^b with d the degree whose
+ * C(d, 2) is the row's mean wedges per vertex (0.5 + sqrt(0.25 + 2 p_b / n_b));
+ * the global row averages the bins' d weighted by p_b. */
+double wedge_cv_centre_cost(const uint64_t* h_n_b, const uint64_t* h_p_b, uint32_t max_bins,
+                            uint32_t row, double a, double b);
+
+/* First-round plan of the centre form per row: with the fit, the variance
+ * of gbar from a pilot (h_centre_var) and the cost per centre draw (h_cost),
+ * the share t in {0.01, ..., 0.99} of eps given to the centre term that
+ * minimises wedge_eb_samples(var_z, 1+|beta|, delta/4, eps (1-t)) + cost
+ * wedge_eb_samples(var, 1, delta/4, eps t/|beta|); if that is not below the
+ * plain plan wedge_eb_samples(var_x, 1, delta/2, eps), or beta = 0, the row
+ * stays plain (h_centre = 0, h_beta = 0).  Outputs per row: EVAL draws,
+ * centre draws, beta used. */
+int wedge_cv_plan_centre(const wedge_cv_fit_row* h_fit, const double* h_centre_var,
+                         const double* h_cost, uint32_t rows, double eps, double delta,
+                         uint64_t* h_eval, uint64_t* h_centre, double* h_beta);
+
+/* Training of the control variate on TRAIN draws (key domain 2) of the rows
+ * h_rows[nrows] (increasing, bins < max_bins and/or the global stream
+ * max_bins): draws 0 .. n_fit - 1 of every row fit the network (fan-in
+ * initialisation from init_seed, then `epochs` passes of Adam on minibatches
+ * of per_row_batch draws of every row, lr, beta1 0.9, beta2 0.999, eps 1e-8),
+ * draws n_fit .. n_fit + n_hold - 1 are held out: their moments (h_mom
+ * [nrows][5], nullable) give h_fit[nrows] as wedge_cv_fit does.  h_loss
+ * (nullable): the last minibatch's mean loss.  d_state: the network state,
+ * trained in place.  Synchronises the stream (it reads the moments back).
+ * Workspace: wedge_cv_train_workspace(nrows, n_fit, n_hold, per_row_batch).
+ * Errors: EINVAL, ERANGE (max_bins > 4096), EWORKSPACE, and those of the
+ * calls it makes. */
+size_t wedge_cv_train_workspace(uint32_t rows, uint64_t n_fit, uint64_t n_hold,
+                                uint64_t per_row_batch);
+int wedge_cv_train(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
+                   const void* d_index, uint32_t max_bins, uint32_t tau, uint64_t omega,
+                   const uint32_t* h_rows, uint32_t nrows, uint64_t n_fit, uint64_t n_hold,
+                   uint64_t per_row_batch, uint32_t epochs, float lr, uint64_t seed,
+                   uint64_t init_seed, void* d_state, double eps, double delta,
+                   wedge_cv_fit_row* h_fit, int64_t* h_mom, float* h_loss, void* d_workspace,
+                   size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -96,9 +96,3 @@ extern "C" int wedge_estimate(const uint64_t* h_n_b, const uint64_t* h_p_b, cons
   h_global->t_bins_sum = tsum;
   return WEDGE_OK;
 }
-
-extern "C" double wedge_eb_halfwidth(uint64_t n, double var, double R, double delta) {
-  if (n < 2) return INFINITY;
-  const double L = log(4.0 / delta);
-  return sqrt(2.0 * var * L / (double)n) + 7.0 * R * L / (3.0 * (double)(n - 1));
-}

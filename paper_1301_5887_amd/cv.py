@@ -22,14 +22,14 @@ the two-sided empirical-Bernstein half-width at delta_i = delta / (i (i+1))
 gbar (or of g) with delta_i split in two for the centre (AUX) form.
 beta = 0 is plain wedge sampling with the same rule ("plain-EB").  All work
 runs in libwedge: the sampler in feature mode, the network's forward,
-gradient and Adam kernels, the census, the centre draws and the integer
-moment sums; this module only sequences the calls and evaluates the
-closed-form bounds and plans.
+gradient and Adam kernels, the census, the centre draws, the integer moment
+sums, and the estimator itself (wedge_cv_fit, wedge_cv_estimate,
+wedge_cv_bin_means, wedge_cv_plan_centre, wedge_cv_train); this module only
+marshals arguments and sequences the calls.
 """
 from __future__ import annotations
 
 import ctypes
-import math
 import time
 from dataclasses import dataclass, field
 
@@ -41,7 +41,6 @@ from . import wedge as W
 FEATURE_DTYPE = np.dtype([("dv", "<u4"), ("dlo", "<u4"), ("dhi", "<u4"), ("bin", "<u2"),
                           ("closed", "u1"), ("cls", "u1")])
 NPARAM = 4545
-Q32 = float(1 << 32)
 DOMAIN_SAMPLE, DOMAIN_TRAIN, DOMAIN_AUX, DOMAIN_EVAL, DOMAIN_CENTRE = 1, 2, 3, 4, 6
 
 
@@ -213,17 +212,18 @@ class Census:
         W._check(_L().wedge_cv_exact_mean(W._ptr(net.state), W._ptr(self.buf), self.bi.max_bins,
                                           W._ptr(ksum), W._ptr(kcnt), W._ptr(ws), ws.numel(),
                                           W._stream(stream)))
-        s = ksum.cpu().numpy()[: self.nkeys]
-        c = W.to_host_u64(kcnt)[: self.nkeys]
+        s = np.ascontiguousarray(ksum.cpu().numpy()[: self.nkeys])
+        c = np.ascontiguousarray(W.to_host_u64(kcnt)[: self.nkeys])
         B = self.bi.max_bins
-        num = np.zeros(B)
-        den = np.zeros(B, dtype=np.uint64)
-        for key in range(self.nkeys):          # keys in increasing degree order
-            num[self.key_bin[key]] += s[key]
-            den[self.key_bin[key]] += c[key]
-        out = {b: num[b] / float(den[b]) for b in range(B) if den[b] > 0}
-        out[B] = float(num.sum()) / float(den.sum()) if den.sum() > 0 else 0.0
-        self.counts = den
+        mean = np.zeros(B + 1, dtype=np.float64)
+        den = np.zeros(B + 1, dtype=np.uint64)
+        kb = np.ascontiguousarray(self.key_bin, dtype=np.uint32)
+        W._check(_L().wedge_cv_bin_means(s.ctypes.data_as(W._vp), c.ctypes.data_as(W._vp),
+                                         kb.ctypes.data_as(W._vp), self.nkeys, B,
+                                         mean.ctypes.data_as(W._vp), den.ctypes.data_as(W._vp)))
+        out = {b: float(mean[b]) for b in range(B) if den[b] > 0}
+        out[B] = float(mean[B])
+        self.counts = den[:B]
         return out
 
 
@@ -269,109 +269,33 @@ def _table_offset(max_bins: int) -> int:
     return r(8) + r(max_bins * 256 * 4) + 3 * r(cap * 4)
 
 
-@dataclass
-class RowStats:
-    n: int = 0
-    sx: int = 0
-    sg: int = 0
-    sg2: int = 0
-    sxg: int = 0
-    an: int = 0
-    ag: int = 0
-    ag2: int = 0
-    cn: int = 0     # centre draws: count, 2^32 sum gbar, 2^32 sum gbar^2
-    cg: int = 0
-    cg2: int = 0
+def fit_rows(mom: np.ndarray, eps: float, delta: float):
+    """wedge_cv_fit over moments [rows, 5]: per row (beta, rho^2, var_x,
+    var_z, first-round plan plain, plan control variate)."""
+    m = np.ascontiguousarray(mom, dtype=np.int64)
+    R = m.shape[0]
+    out = (W.CvFitRow * max(R, 1))()
+    W._check(_L().wedge_cv_fit(m.ctypes.data_as(W._vp), R, eps, delta, out))
+    return [out[i] for i in range(R)]
 
 
-def rho2_from_moments(m) -> float:
-    """Squared correlation of X and g (the fraction of Var X a control
-    variate with the best beta removes)."""
-    n, sx, sg, sg2, sxg = (int(v) for v in m)
-    if n < 2:
-        return 0.0
-    mx, mg = sx / n, sg / Q32 / n
-    cov = sxg / Q32 / n - mx * mg
-    vg = sg2 / Q32 / n - mg * mg
-    vx = mx - mx * mx
-    return cov * cov / (vx * vg) if vx > 0 and vg > 1e-14 else 0.0
+def estimate_rows(rows: list, round_i: int, delta: float, eps: float, max_per_row: int):
+    """wedge_cv_estimate over a list of W.CvRow: [(estimate, half-width, more)]."""
+    arr = (W.CvRow * max(len(rows), 1))(*rows)
+    out = (W.CvResult * max(len(rows), 1))()
+    W._check(_L().wedge_cv_estimate(arr, len(rows), round_i, delta, eps, max_per_row, out))
+    return [(out[i].estimate, out[i].halfwidth, bool(out[i].more)) for i in range(len(rows))]
 
 
-def beta_from_moments(m) -> float:
-    """Least-squares coefficient Cov(X, g) / Var(g) from integer moments."""
-    n, sx, sg, sg2, sxg = (int(v) for v in m)
-    if n < 2:
-        return 0.0
-    mx, mg = sx / n, sg / Q32 / n
-    cov = sxg / Q32 / n - mx * mg
-    var = sg2 / Q32 / n - mg * mg
-    return cov / var if var > 1e-14 else 0.0
-
-
-def cv_row_estimate(st: RowStats, beta: float, delta_i: float, use_aux: bool,
-                    exact_mean: float | None = None, centre: bool = False):
-    """(estimate, half-width) of one row from its moments; with exact_mean
-    the control variate's mean is known and the whole delta_i goes to the
-    EVAL bound; with centre=True the mean comes from the centre draws (each
-    side of the bound at delta_i / 2), and beta = 0 is the plain form."""
-    n = st.n
-    if n < 2:
-        return float("nan"), float("inf")
-    mx = st.sx / n
-    mg = st.sg / Q32 / n
-    vx = (st.sx - n * mx * mx) / (n - 1)
-    vg = (st.sg2 / Q32 - n * mg * mg) / (n - 1)
-    cxg = (st.sxg / Q32 - n * mx * mg) / (n - 1)
-    vz = vx - 2 * beta * cxg + beta * beta * vg
-    if centre:
-        if beta == 0.0:
-            return mx, eb_halfwidth(n, vx, 1.0, delta_i)
-        if st.cn < 2:
-            return float("nan"), float("inf")
-        cm = st.cg / Q32 / st.cn
-        cv = (st.cg2 / Q32 - st.cn * cm * cm) / (st.cn - 1)
-        hw = (eb_halfwidth(n, vz, 1.0 + abs(beta), delta_i / 2)
-              + abs(beta) * eb_halfwidth(st.cn, cv, 1.0, delta_i / 2))
-        return (mx - beta * mg) + beta * cm, hw
-    if exact_mean is not None:
-        return (mx - beta * mg) + beta * exact_mean, eb_halfwidth(n, vz, 1.0 + abs(beta),
-                                                                  delta_i)
-    if not use_aux:
-        return mx, eb_halfwidth(n, vx, 1.0, delta_i)
-    e_eval = eb_halfwidth(n, vz, 1.0 + abs(beta), delta_i / 2)
-    if st.an < 2:
-        return float("nan"), float("inf")
-    amg = st.ag / Q32 / st.an
-    avg = (st.ag2 / Q32 - st.an * amg * amg) / (st.an - 1)
-    e_aux = abs(beta) * eb_halfwidth(st.an, avg, 1.0, delta_i / 2)
-    est = (mx - beta * mg) + beta * amg
-    return est, e_eval + e_aux
-
-
-def eb_samples_closed(var, R, delta: float, eps):
-    """Planning size for an empirical-Bernstein half-width <= eps (the bound
-    of wedge_eb_halfwidth with n - 1 taken as n, then one sample added):
-    the positive root of a x + b x^2 = eps in x = 1 / sqrt(n) with
-    a = sqrt(2 var ln(4/delta)), b = 7 R ln(4/delta) / 3.  Vectorised over
-    numpy arrays; a plan only, the stopping rule uses the exact bound."""
-    L = math.log(4.0 / delta)
-    a = np.sqrt(2.0 * np.maximum(var, 0.0) * L)
-    b = 7.0 * np.asarray(R, dtype=np.float64) * L / 3.0
-    e = np.asarray(eps, dtype=np.float64)
-    x = 2.0 * e / (a + np.sqrt(a * a + 4.0 * b * e))
-    return np.ceil(1.0 / (x * x)) + 1.0
-
-
-def row_variances(m, beta: float):
-    """(Var X, Var(X - beta g)) from integer moments [n, sx, sg, sg2, sxg]."""
-    n, sx, sg, sg2, sxg = (int(v) for v in m)
-    if n < 2:
-        return 0.25, 0.25
-    mx, mg = sx / n, sg / Q32 / n
-    vx = (sx - n * mx * mx) / (n - 1)
-    vg = (sg2 / Q32 - n * mg * mg) / (n - 1)
-    cxg = (sxg / Q32 - n * mx * mg) / (n - 1)
-    return vx, max(vx - 2 * beta * cxg + beta * beta * vg, 0.0)
+def mean_var_rows(mom: np.ndarray):
+    """wedge_cv_mean_var over moments [rows, 5] of values without labels."""
+    m = np.ascontiguousarray(mom, dtype=np.int64)
+    R = m.shape[0]
+    mean = np.zeros(max(R, 1))
+    var = np.zeros(max(R, 1))
+    W._check(_L().wedge_cv_mean_var(m.ctypes.data_as(W._vp), R, mean.ctypes.data_as(W._vp),
+                                    var.ctypes.data_as(W._vp)))
+    return mean[:R], var[:R]
 
 
 @dataclass
@@ -417,7 +341,12 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
     rows = sorted(rows)
     t0 = time.perf_counter()
     res = SequentialResult()
-    stats = {r: RowStats() for r in rows}
+    mode = W.CV_PLAIN
+    if net is not None:
+        mode = (W.CV_CENTRE if centre is not None else
+                W.CV_EXACT if exact_means is not None else W.CV_AUX)
+    stats = {r: W.CvRow(beta=(beta or {}).get(r, 0.0) if net is not None else 0.0,
+                        exact_mean=(exact_means or {}).get(r, 0.0), mode=mode) for r in rows}
     done = {r: 0 for r in rows}
     cdone = {r: 0 for r in rows}
     use_centre = centre is not None and net is not None
@@ -430,7 +359,7 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
         incs = []
         for r in active:
             base = first.get(r, n0) if first else n0
-            target = min(int(math.ceil(base * growth ** (i - 1))), max_per_row)
+            target = int(_L().wedge_cv_round_size(int(base), growth, i, max_per_row))
             inc = max(target - done[r], 0)
             hk[r], sb[r] = inc, done[r]
             incs.append(inc)
@@ -456,7 +385,8 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             for r in active:
                 if beta.get(r, 0.0) == 0.0:
                     continue
-                target = min(int(math.ceil(centre_first[r] * growth ** (i - 1))), max_per_row)
+                target = int(_L().wedge_cv_round_size(int(centre_first[r]), growth, i,
+                                                       max_per_row))
                 if target > cdone[r]:
                     hc[r], sc[r] = target - cdone[r], cdone[r]
                     crow.append(r)
@@ -473,12 +403,10 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             agv = _ROUND_BUFFERS.take("aux_g", A * stride, torch.float32, dev)
             net.forward(arecs, A * stride, agv, stream=stream)
             am = _moments_per_row(arecs, agv, incs, stride, dev)
-        delta_i = delta / (i * (i + 1))
         for j, r in enumerate(crow):
             st = stats[r]
-            st.cn += int(cm[j, 0]); st.cg += int(cm[j, 2]); st.cg2 += int(cm[j, 3])
+            st.an += int(cm[j, 0]); st.ag += int(cm[j, 2]); st.ag2 += int(cm[j, 3])
             cdone[r] += int(cm[j, 0])
-        still = []
         for j, r in enumerate(active):
             st = stats[r]
             st.n += int(m[j, 0]); st.sx += int(m[j, 1]); st.sg += int(m[j, 2])
@@ -486,14 +414,15 @@ def sequential(g: W.Csr, bi: W.BinIndex, rows: list[int], eps: float, delta: flo
             if am is not None:
                 st.an += int(am[j, 0]); st.ag += int(am[j, 2]); st.ag2 += int(am[j, 3])
             done[r] += incs[j]
-            b = beta.get(r, 0.0) if beta else 0.0
-            em = exact_means.get(r) if (exact_means is not None and net is not None) else None
-            est, hw = cv_row_estimate(st, b, delta_i, use_aux=net is not None, exact_mean=em,
-                                      centre=use_centre)
+            st.done = done[r]
+        results = estimate_rows([stats[r] for r in active], i, delta, eps, max_per_row)
+        still = []
+        for r, (est, hw, more) in zip(active, results):
+            st = stats[r]
             res.estimates[r], res.halfwidth[r] = est, hw
             res.eval_samples[r] = st.n
-            res.aux_samples[r] = st.cn if use_centre else st.an
-            if hw > eps and done[r] < max_per_row:
+            res.aux_samples[r] = st.an
+            if more:
                 still.append(r)
         active = still
         res.rounds = i
@@ -511,58 +440,53 @@ class TrainResult:
     seconds: float
     rho2: dict = field(default_factory=dict)
     holdout: dict = field(default_factory=dict)   # row -> moments of the held-out draws
+    fit: dict = field(default_factory=dict)       # row -> W.CvFitRow
 
 
 def train(g: W.Csr, bi: W.BinIndex, rows: list[int], n_train: int, seed: int,
           epochs: int = 1, per_row_batch: int = 4096, lr: float = 2e-2, holdout: float = 0.2,
-          init_seed: int = 7, stream=None) -> TrainResult:
-    """TRAIN draws (exact labels) spread evenly over `rows`: the first
-    columns of every row fit the network (Adam on minibatches that hold every
-    row), the rest are held out for beta, the fitted correlation and the
-    round plans."""
+          init_seed: int = 7, eps: float = 1e-3, delta: float = 1e-3,
+          stream=None) -> TrainResult:
+    """wedge_cv_train: TRAIN draws (exact labels) spread evenly over `rows`;
+    the first columns of every row fit the network (Adam on minibatches that
+    hold every row), the rest are held out for beta, the fitted correlation
+    and the round plans (at eps, delta)."""
     dev = g.rowptr.device
-    B = bi.max_bins
     rows = sorted(rows)
-    R = len(rows)   # records are compact: row j is rows[j]
+    R = len(rows)
     t0 = time.perf_counter()
     per_row = max(n_train // R, 2 * per_row_batch)
     n_fit = int(per_row * (1 - holdout)) // per_row_batch * per_row_batch
     n_hold = per_row - n_fit
-    hk = np.zeros(B + 1, dtype=np.uint64)
-    sb = np.zeros(B + 1, dtype=np.uint64)
-    hk[rows] = n_fit
-    fit = _ROUND_BUFFERS.records("train_fit", R, n_fit, dev)
-    sample_features(g, bi, hk, 0, seed, DOMAIN_TRAIN, True, fit, n_fit, stream=stream)
-    hk[rows] = n_hold
-    sb[rows] = n_fit
-    hold = _ROUND_BUFFERS.records("train_hold", R, n_hold, dev)
-    sample_features(g, bi, hk, sb, seed, DOMAIN_TRAIN, True, hold, n_hold, stream=stream)
     net = Mlp(dev)
-    net.init(init_seed, stream=stream)
-    net.train(fit, R, n_fit, n_fit, per_row_batch, epochs, lr=lr, stream=stream)
-    losses = [float(net.loss.item())]
-    gv = _ROUND_BUFFERS.take("train_hold_g", R * n_hold, torch.float32, dev)
-    net.forward(hold, R * n_hold, gv, stream=stream)
-    mom = W.to_host_u64(moments(hold, gv, R, n_hold, n_hold)).view(np.int64).reshape(R, 5)
-    beta = {r: beta_from_moments(mom[i]) for i, r in enumerate(rows)}
-    rho2 = {r: rho2_from_moments(mom[i]) for i, r in enumerate(rows)}
-    torch.cuda.synchronize()
-    return TrainResult(net=net, beta=beta, losses=losses, train_samples=per_row * R,
-                       seconds=time.perf_counter() - t0, rho2=rho2,
-                       holdout={r: mom[i].copy() for i, r in enumerate(rows)})
+    ws = _ROUND_BUFFERS.take("train_ws", int(_L().wedge_cv_train_workspace(R, n_fit, n_hold,
+                                                                          per_row_batch)),
+                             torch.uint8, dev)
+    hr = np.ascontiguousarray(rows, dtype=np.uint32)
+    fit = (W.CvFitRow * R)()
+    mom = np.zeros((R, 5), dtype=np.int64)
+    loss = ctypes.c_float(0.0)
+    W._check(_L().wedge_cv_train(W._ptr(g.rowptr), W._ptr(g.col), g.n, g.m, W._ptr(bi.index),
+                                 bi.max_bins, bi.tau, bi.omega, hr.ctypes.data_as(W._vp), R,
+                                 n_fit, n_hold, per_row_batch, epochs, lr, seed, init_seed,
+                                 W._ptr(net.state), eps, delta, fit,
+                                 mom.ctypes.data_as(W._vp), ctypes.byref(loss), W._ptr(ws),
+                                 ws.numel(), W._stream(stream)))
+    net.t = epochs * (n_fit // per_row_batch)
+    return TrainResult(net=net, beta={r: fit[i].beta for i, r in enumerate(rows)},
+                       losses=[loss.value], train_samples=per_row * R,
+                       seconds=time.perf_counter() - t0,
+                       rho2={r: fit[i].rho2 for i, r in enumerate(rows)},
+                       holdout={r: mom[i].copy() for i, r in enumerate(rows)},
+                       fit={r: fit[i] for i, r in enumerate(rows)})
 
 
-def plans(tr: TrainResult, eps: float, delta: float):
-    """First-round sample counts per row from the held-out TRAIN draws: the
-    empirical-Bernstein n at delta / 2 (the first round's share) for plain
-    sampling (variance of X, range 1) and for the control variate (variance
-    of X - beta g, range 1 + |beta|).  They use no EVAL draw."""
-    plain, cv = {}, {}
-    for r, m in tr.holdout.items():
-        vx, vz = row_variances(m, tr.beta[r])
-        plain[r] = int(eb_samples_closed(vx, 1.0, delta / 2, eps))
-        cv[r] = int(eb_samples_closed(vz, 1.0 + abs(tr.beta[r]), delta / 2, eps))
-    return plain, cv
+def plans(tr: TrainResult):
+    """First-round sample counts per row from the held-out TRAIN draws (the
+    fit's empirical-Bernstein n at delta / 2) for plain sampling and for the
+    control variate.  They use no EVAL draw."""
+    return ({r: int(f.plan_plain) for r, f in tr.fit.items()},
+            {r: int(f.plan_cv) for r, f in tr.fit.items()})
 
 
 # Centre draws of the pilot start at this sample index, far past any draw an
@@ -585,56 +509,41 @@ def centre_pilot(g: W.Csr, bi: W.BinIndex, rows: list[int], table: CentreTable, 
     out = torch.empty(len(rows) * n, dtype=torch.float32, device=g.rowptr.device)
     centre_means(g, bi, table, hk, PILOT_BEGIN, seed, DOMAIN_CENTRE, out, n, stream=stream)
     m = _moments_per_row(None, out, [n] * len(rows), n, g.rowptr.device)
-    res = {}
-    for j, r in enumerate(rows):
-        cnt, sg, sg2 = int(m[j, 0]), m[j, 2] / Q32, m[j, 3] / Q32
-        mean = sg / cnt
-        res[r] = (mean, max((sg2 - cnt * mean * mean) / (cnt - 1), 0.0))
-    return res
+    mean, var = mean_var_rows(m)
+    return {r: (float(mean[j]), float(var[j])) for j, r in enumerate(rows)}
 
 
 def centre_cost(bi: W.BinIndex, r: int, model=CENTRE_COST) -> float:
-    """Modelled cost of a centre draw of row r in EVAL draws; d is taken as
-    the degree whose C(d, 2) is the row's mean wedges per vertex."""
-    B = bi.max_bins
-
-    def deg(b):
-        n_b, p_b = float(bi.h_n_b[b]), float(bi.h_p_b[b])
-        return 0.5 + math.sqrt(0.25 + 2.0 * p_b / n_b) if n_b > 0 else 0.0
-
-    if r < B:
-        d = deg(r)
-    else:
-        p = np.asarray(bi.h_p_b[:B], dtype=np.float64)
-        d = float(sum(p[b] * deg(b) for b in range(B) if p[b] > 0) / max(p.sum(), 1.0))
-    return 1.0 + model[0] * d ** model[1]
+    """wedge_cv_centre_cost: modelled cost of a centre draw of row r in EVAL
+    draws."""
+    nb = np.ascontiguousarray(bi.h_n_b, dtype=np.uint64)
+    pb = np.ascontiguousarray(bi.h_p_b, dtype=np.uint64)
+    return float(_L().wedge_cv_centre_cost(nb.ctypes.data_as(W._vp), pb.ctypes.data_as(W._vp),
+                                           bi.max_bins, r, model[0], model[1]))
 
 
 def plans_centre(tr: TrainResult, pilot: dict, bi: W.BinIndex, eps: float, delta: float,
                  model=CENTRE_COST):
-    """First-round EVAL and centre draws and the beta of every row for the
-    centre form, from the held-out TRAIN draws and the centre pilot (a row
-    without a pilot entry is planned at zero gbar variance, the cheapest
-    case): the eps share of the centre term that minimises the modelled
-    cost, or the plain form (beta = 0, all of eps and delta_1 on the EVAL
-    draws) where that is cheaper."""
-    n_eval, n_centre, beta_used = {}, {}, {}
-    t = np.arange(0.01, 1.0, 0.01)      # share of eps given to the centre term
-    for r, m in tr.holdout.items():
-        b = tr.beta[r]
-        vx, vz = row_variances(m, b)
-        plain = int(eb_samples_closed(vx, 1.0, delta / 2, eps))
-        n_eval[r], n_centre[r], beta_used[r] = plain, 0, 0.0
-        if b == 0.0:
-            continue
-        vc = pilot[r][1] if r in pilot else 0.0
-        ne = eb_samples_closed(vz, 1.0 + abs(b), delta / 4, eps * (1.0 - t))
-        nc = eb_samples_closed(vc, 1.0, delta / 4, eps * t / abs(b))
-        cost = ne + centre_cost(bi, r, model) * nc
-        j = int(np.argmin(cost))
-        if cost[j] < plain:
-            n_eval[r], n_centre[r], beta_used[r] = int(ne[j]), int(nc[j]), b
-    return n_eval, n_centre, beta_used
+    """wedge_cv_plan_centre: first-round EVAL and centre draws and the beta
+    of every row for the centre form, from the held-out TRAIN draws and the
+    centre pilot (a row without a pilot entry is planned at zero gbar
+    variance, the cheapest case)."""
+    rows = sorted(tr.fit)
+    R = len(rows)
+    fit = (W.CvFitRow * R)(*[tr.fit[r] for r in rows])
+    var = np.ascontiguousarray([pilot[r][1] if r in pilot else 0.0 for r in rows],
+                               dtype=np.float64)
+    cost = np.ascontiguousarray([centre_cost(bi, r, model) for r in rows], dtype=np.float64)
+    ne = np.zeros(R, dtype=np.uint64)
+    nc = np.zeros(R, dtype=np.uint64)
+    bu = np.zeros(R, dtype=np.float64)
+    W._check(_L().wedge_cv_plan_centre(fit, var.ctypes.data_as(W._vp),
+                                       cost.ctypes.data_as(W._vp), R, eps, delta,
+                                       ne.ctypes.data_as(W._vp), nc.ctypes.data_as(W._vp),
+                                       bu.ctypes.data_as(W._vp)))
+    return ({r: int(ne[j]) for j, r in enumerate(rows)},
+            {r: int(nc[j]) for j, r in enumerate(rows)},
+            {r: float(bu[j]) for j, r in enumerate(rows)})
 
 
 def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, seed: int = 11,
@@ -653,8 +562,9 @@ def compare(g: W.Csr, bi: W.BinIndex, eps: float = 1e-3, delta: float = 1e-3, se
     B = bi.max_bins
     rows = [r for r in range(B) if bi.h_p_b[r] > 0] + [B]
     torch.cuda.synchronize()
-    tr = train(g, bi, rows, n_train, seed, epochs=epochs, per_row_batch=per_row_batch, lr=lr)
-    plan_plain, plan_cv = plans(tr, eps, delta)
+    tr = train(g, bi, rows, n_train, seed, epochs=epochs, per_row_batch=per_row_batch, lr=lr,
+               eps=eps, delta=delta)
+    plan_plain, plan_cv = plans(tr)
     # rows where the held-out draws predict fewer samples without the control
     # variate (small rho^2: the wider range 1 + |beta| of the bound costs more
     # than the variance it removes) keep beta = 0, i.e. plain sampling

@@ -52,6 +52,27 @@ class WedgeGlobalEstimate(ctypes.Structure):
                 ("t_bins_sum", ctypes.c_double)]
 
 
+class CvFitRow(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("rho2", ctypes.c_double), ("var_x", ctypes.c_double),
+                ("var_z", ctypes.c_double), ("plan_plain", _c_u64), ("plan_cv", _c_u64)]
+
+
+class CvRow(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sx", ctypes.c_int64), ("sg", ctypes.c_int64),
+                ("sg2", ctypes.c_int64), ("sxg", ctypes.c_int64), ("an", ctypes.c_int64),
+                ("ag", ctypes.c_int64), ("ag2", ctypes.c_int64), ("beta", ctypes.c_double),
+                ("exact_mean", ctypes.c_double), ("mode", _c_u32), ("pad", _c_u32),
+                ("done", _c_u64)]
+
+
+class CvResult(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("halfwidth", ctypes.c_double),
+                ("more", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+CV_PLAIN, CV_EXACT, CV_AUX, CV_CENTRE = 0, 1, 2, 3
+
+
 class BatchDesc(ctypes.Structure):
     _fields_ = [("num_graphs", _c_u32), ("max_bins", _c_u32), ("tau", _c_u32), ("max_n", _c_u32),
                 ("omega", _c_u64), ("k_per_bin", _c_u64), ("k_global", _c_u64), ("seed", _c_u64),
@@ -142,6 +163,23 @@ SIGNATURES = {
     "wedge_triangle_box": (ctypes.c_int, [_vp, _c_u32, _vp]),
     "wedge_eb_halfwidth": (ctypes.c_double, [_c_u64, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double]),
+    "wedge_eb_samples": (_c_u64, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double]),
+    "wedge_cv_round_size": (_c_u64, [_c_u64, ctypes.c_double, _c_u32, _c_u64]),
+    "wedge_cv_fit": (ctypes.c_int, [_vp, _c_u32, ctypes.c_double, ctypes.c_double, _vp]),
+    "wedge_cv_estimate": (ctypes.c_int, [_vp, _c_u32, _c_u32, ctypes.c_double, ctypes.c_double,
+                                         _c_u64, _vp]),
+    "wedge_cv_bin_means": (ctypes.c_int, [_vp, _vp, _vp, _c_u32, _c_u32, _vp, _vp]),
+    "wedge_cv_mean_var": (ctypes.c_int, [_vp, _c_u32, _vp, _vp]),
+    "wedge_cv_centre_cost": (ctypes.c_double, [_vp, _vp, _c_u32, _c_u32, ctypes.c_double,
+                                               ctypes.c_double]),
+    "wedge_cv_plan_centre": (ctypes.c_int, [_vp, _vp, _vp, _c_u32, ctypes.c_double,
+                                            ctypes.c_double, _vp, _vp, _vp]),
+    "wedge_cv_train_workspace": (ctypes.c_size_t, [_c_u32, _c_u64, _c_u64, _c_u64]),
+    "wedge_cv_train": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _c_u32, _c_u64, _vp,
+                                      _c_u32, _c_u64, _c_u64, _c_u64, _c_u32, ctypes.c_float,
+                                      _c_u64, _c_u64, _vp, ctypes.c_double, ctypes.c_double,
+                                      _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "wedge_cv_census_bytes": (ctypes.c_size_t, [_c_u32, _c_u64, _c_u32]),
     "wedge_cv_census": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _c_u32, _c_u64,
                                        _vp, ctypes.c_size_t, _vp]),

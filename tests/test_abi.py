@@ -177,28 +177,183 @@ def test_eb_halfwidth_matches_oracle():
     assert W.lib().wedge_eb_halfwidth(1, 0.1, 1.0, 0.1) == float("inf")
 
 
-def test_cv_row_estimate_matches_oracle_formula():
-    from oracle import mlp_oracle as M
-    from paper_1301_5887_amd import cv as C
-    rng = np.random.default_rng(3)
-    X = (rng.random(20000) < 0.25).astype(np.int64)
-    g = rng.random(20000).astype(np.float32).astype(np.float64) * 0.5
-    ga = rng.random(9000).astype(np.float32).astype(np.float64) * 0.5
+def _cv_sample(seed, n=20000, na=9000, p=0.25):
+    """Labels X and network values g, g_aux on the 2^-16 grid, so the
+    integer moments (terms scaled by 2^32) are exact and the oracle sees
+    the same numbers."""
+    rng = np.random.default_rng(seed)
+    g = rng.integers(1, 1 << 15, n).astype(np.float64) / 2.0 ** 16
+    X = (rng.random(n) < p * (0.5 + g)).astype(np.int64)
+    ga = rng.integers(1, 1 << 15, na).astype(np.float64) / 2.0 ** 16
+    return X, g, ga
+
+
+def _mom(X, g):
     q = lambda v: np.rint(v * 2.0 ** 32).astype(np.int64)  # noqa: E731
-    st = C.RowStats(n=len(X), sx=int(X.sum()), sg=int(q(g).sum()), sg2=int(q(g * g).sum()),
-                    sxg=int((X * q(g)).sum()), an=len(ga), ag=int(q(ga).sum()),
-                    ag2=int(q(ga * ga).sum()))
-    beta = 0.6
-    est, hw = C.cv_row_estimate(st, beta, 1e-3, use_aux=True)
-    assert est == pytest.approx(M.cv_estimate(X, q(g) / 2.0 ** 32, q(ga) / 2.0 ** 32, beta),
-                                abs=1e-12)
+    return [len(g), int(X.sum()), int(q(g).sum()), int(q(g * g).sum()), int((X * q(g)).sum())]
+
+
+def _row(X, g, ga, beta, mode, mu=0.0, done=0):
+    m = _mom(X, g)
+    a = _mom(np.zeros(len(ga), np.int64), ga) if ga is not None else [0] * 5
+    return W.CvRow(n=m[0], sx=m[1], sg=m[2], sg2=m[3], sxg=m[4], an=a[0], ag=a[2], ag2=a[3],
+                   beta=beta, exact_mean=mu, mode=mode, done=done)
+
+
+def _est(rows, rnd, delta, eps, cap=1 << 40):
+    arr = (W.CvRow * len(rows))(*rows)
+    out = (W.CvResult * len(rows))()
+    assert W.lib().wedge_cv_estimate(arr, len(rows), rnd, delta, eps, cap, out) == EOK
+    return [(out[i].estimate, out[i].halfwidth, out[i].more) for i in range(len(rows))]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_cv_estimate_matches_oracle(seed):
+    """wedge_cv_estimate in every mode against the MLP oracle's control-
+    variate estimate and empirical-Bernstein half-width computed from the
+    raw values (two-pass variances), at 1e-12."""
+    from oracle import mlp_oracle as M
+    X, g, ga = _cv_sample(seed)
+    beta, mu, delta, eps, rnd = 0.7 + 0.1 * seed, 0.2 + 0.01 * seed, 1e-3, 1e-3, 3
+    di = delta / (rnd * (rnd + 1))
     z = X - beta * g
-    ref = M.eb_halfwidth(len(X), z.var(ddof=1), 1 + beta, 5e-4) + \
-        beta * M.eb_halfwidth(len(ga), ga.var(ddof=1), 1.0, 5e-4)
-    assert hw == pytest.approx(ref, rel=1e-6)
-    b = C.beta_from_moments([st.n, st.sx, st.sg, st.sg2, st.sxg])
-    ref_b = np.cov(X, g, bias=True)[0, 1] / np.var(g)
-    assert b == pytest.approx(ref_b, rel=1e-6)
+    rows = [_row(X, g, None, beta, W.CV_PLAIN), _row(X, g, None, beta, W.CV_EXACT, mu),
+            _row(X, g, ga, beta, W.CV_AUX), _row(X, g, ga, beta, W.CV_CENTRE),
+            _row(X, g, ga, 0.0, W.CV_CENTRE)]
+    res = _est(rows, rnd, delta, eps)
+    plain_hw = M.eb_halfwidth(len(X), X.var(ddof=1), 1.0, di)
+    two = (M.eb_halfwidth(len(X), z.var(ddof=1), 1 + beta, di / 2)
+           + beta * M.eb_halfwidth(len(ga), ga.var(ddof=1), 1.0, di / 2))
+    ref = [(X.mean(), plain_hw),
+           (M.cv_estimate(X, g, [mu], beta), M.eb_halfwidth(len(X), z.var(ddof=1), 1 + beta, di)),
+           (M.cv_estimate(X, g, ga, beta), two), (M.cv_estimate(X, g, ga, beta), two),
+           (X.mean(), plain_hw)]
+    for (e, h, more), (re, rh) in zip(res, ref):
+        assert e == pytest.approx(re, rel=1e-12, abs=1e-14)
+        assert h == pytest.approx(rh, rel=1e-12)
+        assert more == int(h > eps)
+
+
+def test_cv_estimate_stop_rule_and_errors():
+    X, g, ga = _cv_sample(7, n=3000, na=2000)
+    L = W.lib()
+    (e, h, more), = _est([_row(X, g, ga, 0.5, W.CV_AUX, done=3000)], 1, 1e-3, 1.0)
+    assert more == 0 and h < 1.0                    # half-width below eps
+    (e, h, more), = _est([_row(X, g, ga, 0.5, W.CV_AUX, done=3000)], 1, 1e-3, 1e-6, cap=3000)
+    assert more == 0                                # cap reached
+    (e, h, more), = _est([_row(X, g, ga, 0.5, W.CV_AUX, done=10)], 1, 1e-3, 1e-6, cap=3000)
+    assert more == 1
+    (e, h, more), = _est([_row(X[:1], g[:1], ga, 0.5, W.CV_EXACT)], 1, 1e-3, 1e-3)
+    assert math.isnan(e) and h == float("inf") and more == 1
+    (e, h, more), = _est([_row(X, g, ga[:1], 0.5, W.CV_AUX)], 1, 1e-3, 1e-3)
+    assert math.isnan(e) and h == float("inf")
+    arr = (W.CvRow * 1)(_row(X, g, ga, 0.5, 9))
+    out = (W.CvResult * 1)()
+    assert L.wedge_cv_estimate(arr, 1, 1, 1e-3, 1e-3, 10, out) == EINVAL
+    assert L.wedge_cv_estimate(arr, 1, 0, 1e-3, 1e-3, 10, out) == EINVAL
+    # delta_i = delta / (i (i + 1)): the half-width grows with the round
+    hws = [_est([_row(X, g, None, 0.0, W.CV_PLAIN)], i, 1e-3, 1e-3)[0][1] for i in (1, 2, 5)]
+    assert hws[0] < hws[1] < hws[2]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_cv_fit_matches_oracle(seed):
+    """wedge_cv_fit: beta and rho^2 against numpy's population covariance and
+    correlation, the variances against two-pass sample variances, and the
+    plans against a brute-force search of the oracle's half-width."""
+    from oracle import mlp_oracle as M
+    X, g, _ = _cv_sample(seed, n=50000)
+    m = np.array([_mom(X, g)], dtype=np.int64)
+    out = (W.CvFitRow * 1)()
+    eps, delta = 2e-3, 1e-3
+    assert W.lib().wedge_cv_fit(m.ctypes.data_as(W._vp), 1, eps, delta, out) == EOK
+    f = out[0]
+    cov = np.cov(X, g, bias=True)[0, 1]
+    assert f.beta == pytest.approx(cov / np.var(g), rel=1e-10)
+    assert f.rho2 == pytest.approx(np.corrcoef(X, g)[0, 1] ** 2, rel=1e-9)
+    assert f.var_x == pytest.approx(X.var(ddof=1), rel=1e-12)
+    assert f.var_z == pytest.approx((X - f.beta * g).var(ddof=1), rel=1e-10)
+
+    def smallest(var, R, d):
+        lo, hi = 2, 1 << 40
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if M.eb_halfwidth(mid, var, R, d) <= eps:
+                hi = mid
+            else:
+                lo = mid + 1
+        return lo
+
+    for plan, var, R in ((f.plan_plain, f.var_x, 1.0), (f.plan_cv, f.var_z, 1 + abs(f.beta))):
+        assert M.eb_halfwidth(plan, var, R, delta / 2) <= eps
+        assert plan <= smallest(var, R, delta / 2) * 1.001 + 2
+    assert W.lib().wedge_eb_samples(0.1, 1.0, 1e-3, 0.0) == 0
+    # fewer than two draws: no fit, the plans assume the widest variance
+    m1 = np.array([[1, 1, 0, 0, 0]], dtype=np.int64)
+    assert W.lib().wedge_cv_fit(m1.ctypes.data_as(W._vp), 1, eps, delta, out) == EOK
+    assert out[0].beta == 0.0 and out[0].var_x == 0.25
+
+
+def test_cv_bin_means_and_mean_var_match_numpy():
+    rng = np.random.default_rng(5)
+    B, nk = 6, 40
+    kbin = np.sort(rng.integers(2, B, nk)).astype(np.uint32)
+    kcnt = rng.integers(1, 10 ** 6, nk).astype(np.uint64)
+    ksum = kcnt * rng.random(nk)
+    mean = np.zeros(B + 1)
+    cnt = np.zeros(B + 1, dtype=np.uint64)
+    assert W.lib().wedge_cv_bin_means(ksum.ctypes.data_as(W._vp), kcnt.ctypes.data_as(W._vp),
+                                      kbin.ctypes.data_as(W._vp), nk, B,
+                                      mean.ctypes.data_as(W._vp), cnt.ctypes.data_as(W._vp)) == EOK
+    for b in range(B):
+        sel = kbin == b
+        assert int(cnt[b]) == int(kcnt[sel].sum())
+        if sel.any():
+            assert mean[b] == pytest.approx(ksum[sel].sum() / float(kcnt[sel].sum()), rel=1e-12)
+    assert mean[B] == pytest.approx(ksum.sum() / float(kcnt.sum()), rel=1e-12)
+    assert int(cnt[B]) == int(kcnt.sum())
+    _, g, _ = _cv_sample(9, n=7000)
+    m = np.array([_mom(np.zeros(len(g), np.int64), g)], dtype=np.int64)
+    mu, var = np.zeros(1), np.zeros(1)
+    assert W.lib().wedge_cv_mean_var(m.ctypes.data_as(W._vp), 1, mu.ctypes.data_as(W._vp),
+                                     var.ctypes.data_as(W._vp)) == EOK
+    assert mu[0] == pytest.approx(g.mean(), rel=1e-12)
+    assert var[0] == pytest.approx(g.var(ddof=1), rel=1e-10)
+
+
+def test_cv_plan_centre_choices():
+    """The centre plan keeps plain rows plain (beta = 0, or no variance to
+    remove), and where the network removes nearly all variance it takes
+    centre draws whose two bounds together reach eps in the first round."""
+    from oracle import mlp_oracle as M
+    eps, delta = 1e-3, 1e-3
+    fit = (W.CvFitRow * 3)(W.CvFitRow(beta=0.0, var_x=0.1, var_z=0.1),
+                           W.CvFitRow(beta=1.0, var_x=0.1, var_z=0.1),
+                           W.CvFitRow(beta=1.0, var_x=0.1, var_z=1e-5))
+    var = np.array([0.0, 0.5, 1e-6])
+    cost = np.array([1.0, 1.0, 1.0])
+    ne, nc, bu = np.zeros(3, np.uint64), np.zeros(3, np.uint64), np.zeros(3)
+    assert W.lib().wedge_cv_plan_centre(fit, var.ctypes.data_as(W._vp),
+                                        cost.ctypes.data_as(W._vp), 3, eps, delta,
+                                        ne.ctypes.data_as(W._vp), nc.ctypes.data_as(W._vp),
+                                        bu.ctypes.data_as(W._vp)) == EOK
+    plain = W.lib().wedge_eb_samples(0.1, 1.0, delta / 2, eps)
+    assert (ne[0], nc[0], bu[0]) == (plain, 0, 0.0)
+    assert (ne[1], nc[1], bu[1]) == (plain, 0, 0.0)
+    assert bu[2] == 1.0 and 0 < ne[2] + nc[2] < plain
+    assert (M.eb_halfwidth(int(ne[2]), 1e-5, 2.0, delta / 4)
+            + M.eb_halfwidth(int(nc[2]), 1e-6, 1.0, delta / 4)) <= eps * (1 + 1e-12)
+    # cost model: a bin of 10 vertices with 100 wedges has centres of degree 5
+    nb = np.array([0, 0, 10], dtype=np.uint64)
+    pb = np.array([0, 0, 100], dtype=np.uint64)
+    c = W.lib().wedge_cv_centre_cost(nb.ctypes.data_as(W._vp), pb.ctypes.data_as(W._vp), 3, 2,
+                                     0.15, 0.7)
+    assert c == pytest.approx(1.0 + 0.15 * 5.0 ** 0.7, rel=1e-14)
+    assert W.lib().wedge_cv_centre_cost(nb.ctypes.data_as(W._vp), pb.ctypes.data_as(W._vp), 3,
+                                        3, 0.15, 0.7) == pytest.approx(c, rel=1e-14)
+    assert W.lib().wedge_cv_round_size(1000, 1.1, 1, 10 ** 9) == 1000
+    assert W.lib().wedge_cv_round_size(1000, 1.1, 3, 10 ** 9) == math.ceil(1000 * 1.1 ** 2)
+    assert W.lib().wedge_cv_round_size(1000, 2.0, 30, 5000) == 5000
 
 
 @pytest.mark.parametrize("seed", range(4))
