@@ -761,7 +761,7 @@ def _pmc_groups(disp):
         elif "k_dedup" in nm:
             g["k_dedup"].append(i)
             in_sort = False
-        elif "index" in nm.lower() and cal is not None and i > cal:
+        elif "gather" in nm.lower() and cal is not None and i > cal:
             g["calibration_gather"].append(i)
     if g["calibration_gather"]:
         g["calibration_gather"] = [max(g["calibration_gather"], key=big)]
@@ -821,10 +821,12 @@ def pmc_summarize(dirs, workload_k: int, copy_gib: float, gather_lines: int, out
         out["copy_read_factor"] = round(factor, 4)
     gat = groups.get("calibration_gather", {})
     if gather_lines and gat.get("TCC_EA0_RDREQ_sum"):
-        # the gather also streams its index (8 B) and output (4 B) arrays
-        out["gather_requests_per_line"] = round(gat["TCC_EA0_RDREQ_sum"] / gather_lines, 3)
+        # the gather also streams its 8-byte index array (in 128-byte lines)
+        idx_lines = 8 * gather_lines / 128
+        out["gather_requests_per_random_line"] = round(
+            (gat["TCC_EA0_RDREQ_sum"] - idx_lines) / gather_lines, 4)
         if gat.get("read_bytes"):
-            out["gather_read_bytes_per_line"] = round(
+            out["gather_read_bytes_per_random_line"] = round(
                 (gat["read_bytes"] - 8 * gather_lines) / gather_lines, 2)
     samp = groups.get("k_sample_close", {})
     if samp.get("read_bytes") is not None:

@@ -41,7 +41,9 @@ typedef enum {
   WEDGE_ERANGE = -2,     /* a size or parameter outside the supported range */
   WEDGE_EWORKSPACE = -3, /* workspace or output buffer smaller than required */
   WEDGE_EHIP = -4,       /* a HIP runtime call or kernel launch failed */
-  WEDGE_ENOTSUP = -5     /* no usable gfx950 device */
+  WEDGE_ENOTSUP = -5,    /* no usable gfx950 device */
+  WEDGE_EGRAPH = -6      /* the adjacency is not a sorted simple undirected graph
+                            (only with WEDGE_VALIDATE=1; see wedge_validate_csr) */
 } wedge_status;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -92,6 +94,25 @@ size_t wedge_build_csr_workspace(uint64_t m_in, uint32_t n);
 int wedge_build_csr(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint32_t n,
                     uint64_t* d_rowptr, uint32_t* d_col, uint64_t* d_info, void* d_workspace,
                     size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * wedge_validate_csr -- device check that an adjacency has the form the path
+ * assumes: the paper's input is an undirected graph without repeated edges
+ * or self-loops (Sec. 4.1), so in sorted rows every row is strictly
+ * ascending, no vertex is in its own row, and w is in row v exactly when v
+ * is in row w.  wedge_build_csr always produces that form; callers that bring
+ * their own rowptr/col can check it.
+ * Out: d_counts[4] device uint64, overwritten: [0] entries not above their
+ *      predecessor in the row (unsorted or repeated), [1] self-loops, [2]
+ *      entries (v, w) without (w, v), [3] structural faults (rowptr[0] != 0,
+ *      rowptr decreasing, rowptr[n] != 2m, an id >= n).  All zero = valid.
+ * Asynchronous on the stream.  With the environment variable WEDGE_VALIDATE
+ * set (not "0"), wedge_sample_close runs this check first (its d_q as the
+ * counts), waits for it, and returns WEDGE_EGRAPH when a count is nonzero.
+ * Errors: EINVAL, ERANGE (n == 0), EHIP.
+ * ---------------------------------------------------------------------- */
+int wedge_validate_csr(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
+                       uint64_t* d_counts, void* stream);
 
 /* ------------------------------------------------------------------------
  * wedge_bin_counts -- wedges per vertex and per bin (Alg. phase1b, Sec. 2.1:
@@ -322,6 +343,28 @@ int wedge_batch_graph_destroy(void* h_graph);
 int wedge_batch_autotune(const wedge_batch_desc* d, const wedge_launch_shape* cands, int ncand,
                          int reps, uint64_t* d_q_ref, uint64_t* d_q_try, void* d_workspace,
                          size_t workspace_bytes, float* h_ms, int* h_best, void* stream);
+
+/* Autotuner of the plain sampler: times wedge_sample_close on this graph and
+ * index (with h_k, k_global and seed as given) under each candidate shape
+ * (lanes_in_flight, samples_per_tile; workgroups unused by this launch form),
+ * reps times each, h_ms[c] = the median ms; checks that every candidate's
+ * class counts equal the first one's (d_q_ref, d_q_try: device uint64
+ * [(max_bins+1)*4] scratch); *h_best = the fastest.  The pick is remembered
+ * for (current device, n, m, max_bins) in a process-wide table:
+ * wedge_sample_close then launches graphs of that size with it (results are
+ * identical for every shape).  Synchronises the stream.
+ * Errors: EINVAL (bad arguments, counts that differ), those of
+ * wedge_sample_close, EHIP. */
+int wedge_sample_close_autotune(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
+                                uint64_t m, const void* d_index, uint32_t max_bins,
+                                const uint64_t* h_k, uint64_t k_global, uint64_t seed,
+                                const wedge_launch_shape* cands, int ncand, int reps,
+                                uint64_t* d_q_ref, uint64_t* d_q_try, float* h_ms, int* h_best,
+                                void* stream);
+/* The shape wedge_sample_close uses for a graph of (n, m, max_bins) on the
+ * current device: the autotuner's pick, or the default (1, 256). */
+int wedge_sample_close_shape(uint32_t n, uint64_t m, uint32_t max_bins,
+                             wedge_launch_shape* h_shape);
 
 /* ------------------------------------------------------------------------
  * Learned control variate.  A small network g(x) in (0, 1) predicts the

@@ -104,6 +104,14 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
 // edges [eoff[g], eoff[g+1]) of the input carry local ids of graph g, whose
 // global ids are voff[g] + local.
 size_t csr_workspace_bytes(uint64_t m_in);
+// Device check of an adjacency (validate.hip); validate_or_fail also waits
+// for it and returns WEDGE_EGRAPH when it finds a fault.
+int validate_csr(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
+                 uint64_t* d_counts, hipStream_t st);
+bool validate_requested();
+int validate_or_fail(const char* who, const uint64_t* d_rowptr, const uint32_t* d_col,
+                     uint32_t n, uint64_t m, uint64_t* d_counts, hipStream_t st);
+
 int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint32_t n,
               const uint64_t* d_eoff, const uint32_t* d_voff, uint32_t G, uint64_t* d_rowptr,
               uint32_t* d_col, uint64_t* d_info, void* d_workspace, hipStream_t st);

@@ -22,6 +22,10 @@
 // pulls tiles of every (graph, bin) row of a batch from a device work queue.
 #include "common.hpp"
 #include "rng.hpp"
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "sample.hpp"
@@ -827,9 +831,106 @@ static int launch_centre_tasks(const SamplerCtx& A, TaskTable& T, const CentreAr
   return WEDGE_OK;
 }
 
+// Launch shapes picked by wedge_sample_close_autotune, per (device, n, m,
+// max_bins): wedge_sample_close uses the pick for a graph of that size on
+// that device from then on.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, uint32_t, uint64_t, uint32_t>, SampleTuning> g_tune;
+
+static bool cached_tuning(uint32_t n, uint64_t m, uint32_t max_bins, SampleTuning* t) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple(dev, n, m, max_bins));
+  if (it == g_tune.end()) return false;
+  *t = it->second;
+  return true;
+}
+
+static SampleTuning tuning_of(const wedge_launch_shape& s) {
+  SampleTuning t{s.lanes_in_flight, s.samples_per_tile, s.workgroups};
+  normalise(t);
+  return t;
+}
+
 }  // namespace wedge
 
 using namespace wedge;
+
+extern "C" int wedge_sample_close_autotune(const uint64_t* d_rowptr, const uint32_t* d_col,
+                                           uint32_t n, uint64_t m, const void* d_index,
+                                           uint32_t max_bins, const uint64_t* h_k,
+                                           uint64_t k_global, uint64_t seed,
+                                           const wedge_launch_shape* cands, int ncand, int reps,
+                                           uint64_t* d_q_ref, uint64_t* d_q_try, float* h_ms,
+                                           int* h_best, void* stream) {
+  clear_error();
+  if (!cands || ncand <= 0 || reps <= 0 || !d_q_ref || !d_q_try || !h_ms || !h_best)
+    return set_error(WEDGE_EINVAL, "wedge_sample_close_autotune: bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nq = ((size_t)max_bins + 1) * 4;
+  std::vector<uint64_t> ref(nq), got(nq);
+  hipEvent_t e0, e1;
+  WEDGE_HIP_TRY(hipEventCreate(&e0));
+  WEDGE_HIP_TRY(hipEventCreate(&e1));
+  int rc = WEDGE_OK, best = -1;
+  for (int c = 0; c < ncand && rc == WEDGE_OK; ++c) {
+    const SampleTuning t = tuning_of(cands[c]);
+    std::vector<float> ms(reps);
+    uint64_t* q = c == 0 ? d_q_ref : d_q_try;
+    for (int r = 0; r < reps && rc == WEDGE_OK; ++r) {
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = set_error(WEDGE_EHIP, "event record"); break; }
+      rc = sample_close_impl(d_rowptr, d_col, n, m, d_index, max_bins, h_k, k_global, seed, 0, q,
+                             nullptr, nullptr, 0, &t, st);
+      if (rc) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms[r], e0, e1) != hipSuccess) {
+        rc = set_error(WEDGE_EHIP, "wedge_sample_close_autotune: event timing failed");
+        break;
+      }
+    }
+    if (rc) break;
+    std::sort(ms.begin(), ms.end());
+    h_ms[c] = ms[reps / 2];
+    // every candidate must give the same counts (the result does not depend
+    // on the launch shape)
+    if (hipMemcpyAsync(c == 0 ? ref.data() : got.data(), q, nq * sizeof(uint64_t),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = set_error(WEDGE_EHIP, "wedge_sample_close_autotune: copy of the counts failed");
+      break;
+    }
+    if (c > 0 && got != ref) {
+      rc = set_error(WEDGE_EINVAL, "wedge_sample_close_autotune: counts of candidate %d differ", c);
+      break;
+    }
+    if (best < 0 || h_ms[c] < h_ms[best]) best = c;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  *h_best = best;
+  int dev = 0;
+  WEDGE_HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[std::make_tuple(dev, n, m, max_bins)] = tuning_of(cands[best]);
+  return WEDGE_OK;
+}
+
+extern "C" int wedge_sample_close_shape(uint32_t n, uint64_t m, uint32_t max_bins,
+                                        wedge_launch_shape* h_shape) {
+  clear_error();
+  if (!h_shape) return set_error(WEDGE_EINVAL, "wedge_sample_close_shape: null pointer");
+  SampleTuning t;
+  if (!cached_tuning(n, m, max_bins, &t)) {
+    t = default_tuning(0);
+    normalise(t);
+  }
+  h_shape->lanes_in_flight = t.U;
+  h_shape->samples_per_tile = (uint32_t)t.spt;
+  h_shape->workgroups = t.workgroups;
+  return WEDGE_OK;
+}
 
 extern "C" int wedge_sample_close(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
                                   uint64_t m, const void* d_index, uint32_t max_bins,
@@ -837,9 +938,16 @@ extern "C" int wedge_sample_close(const uint64_t* d_rowptr, const uint32_t* d_co
                                   uint32_t graph_id, uint64_t* d_q, uint64_t* d_probe_loads,
                                   wedge_sample_rec* d_dump, uint64_t dump_per_bin, void* stream) {
   clear_error();
+  if (validate_requested() && d_rowptr && d_q && n > 0 && (m == 0 || d_col)) {
+    const int rc = validate_or_fail("wedge_sample_close", d_rowptr, d_col, n, m, d_q,
+                                    (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  SampleTuning t;
+  const bool tuned = cached_tuning(n, m, max_bins, &t);
   return sample_close_impl(d_rowptr, d_col, n, m, d_index, max_bins, h_k, k_global, seed,
-                           graph_id, d_q, d_probe_loads, d_dump, dump_per_bin, nullptr,
-                           (hipStream_t)stream);
+                           graph_id, d_q, d_probe_loads, d_dump, dump_per_bin,
+                           tuned ? &t : nullptr, (hipStream_t)stream);
 }
 
 extern "C" int wedge_sample_close_tuned(const uint64_t* d_rowptr, const uint32_t* d_col,

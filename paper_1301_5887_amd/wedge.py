@@ -97,6 +97,7 @@ SIGNATURES = {
     "wedge_build_csr_workspace": (ctypes.c_size_t, [_c_u64, _c_u32]),
     "wedge_build_csr": (ctypes.c_int, [_vp, _vp, _c_u64, _c_u32, _vp, _vp, _vp, _vp,
                                        ctypes.c_size_t, _vp]),
+    "wedge_validate_csr": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _vp]),
     "wedge_index_bytes": (ctypes.c_size_t, [_c_u32, _c_u64, _c_u32]),
     "wedge_bin_counts_workspace": (ctypes.c_size_t, [_c_u32]),
     "wedge_bin_counts": (ctypes.c_int, [_vp, _c_u32, _c_u64, _c_u32, _c_u64, _c_u32, _vp, _vp,
@@ -125,6 +126,11 @@ SIGNATURES = {
     "wedge_batch_autotune": (ctypes.c_int, [_dp, _sp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
                                             ctypes.c_size_t, ctypes.POINTER(ctypes.c_float),
                                             ctypes.POINTER(ctypes.c_int), _vp]),
+    "wedge_sample_close_autotune": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _vp,
+                                                   _c_u64, _c_u64, _sp, ctypes.c_int, ctypes.c_int,
+                                                   _vp, _vp, ctypes.POINTER(ctypes.c_float),
+                                                   ctypes.POINTER(ctypes.c_int), _vp]),
+    "wedge_sample_close_shape": (ctypes.c_int, [_c_u32, _c_u64, _c_u32, _sp]),
     "wedge_sample_features": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _c_u32,
                                              _c_u64, _vp, _vp, _c_u64, _c_u32, _c_u32,
                                              ctypes.c_int, _vp, _c_u64, _vp, _vp]),
@@ -412,6 +418,32 @@ def sample_close(g: Csr, bi: BinIndex, h_k: np.ndarray, k_global: int, seed: int
                                             int(lanes_in_flight or 4),
                                             int(samples_per_tile or 4096), _stream(stream))
     _check(rc)
+    return out
+
+
+def sample_close_autotune(g: Csr, bi: BinIndex, h_k: np.ndarray, k_global: int, seed: int,
+                          cands: list, reps: int = 3, stream=None):
+    """wedge_sample_close_autotune: (best shape, median ms per candidate); the
+    pick is then used by wedge_sample_close for graphs of this size."""
+    dev = g.rowptr.device
+    hk = np.ascontiguousarray(h_k, dtype=np.uint64)
+    rows = bi.max_bins + 1
+    q0 = torch.empty(rows * 4, dtype=torch.int64, device=dev)
+    q1 = torch.empty(rows * 4, dtype=torch.int64, device=dev)
+    arr = (LaunchShape * len(cands))(*cands)
+    ms = (ctypes.c_float * len(cands))()
+    best = ctypes.c_int(-1)
+    _check(lib().wedge_sample_close_autotune(_ptr(g.rowptr), _ptr(g.col), g.n, g.m,
+                                             _ptr(bi.index), bi.max_bins,
+                                             hk.ctypes.data_as(ctypes.c_void_p), k_global, seed,
+                                             arr, len(cands), reps, _ptr(q0), _ptr(q1), ms,
+                                             ctypes.byref(best), _stream(stream)))
+    return cands[best.value], list(ms)
+
+
+def sample_close_shape(n: int, m: int, max_bins: int) -> LaunchShape:
+    out = LaunchShape()
+    _check(lib().wedge_sample_close_shape(n, m, max_bins, ctypes.byref(out)))
     return out
 
 

@@ -187,6 +187,56 @@ def test_ids_of_32_bits():
     assert (col == cols).all()
 
 
+WINDOW = 256   # ids of one window: neighbours that agree above the low 8 bits
+
+
+def _window_hub(hub, lo, count, rng, repeats=0):
+    """Edges from `hub` to `count` distinct ids in [lo, lo + WINDOW), plus
+    `repeats` repeats of them."""
+    nb = rng.choice(WINDOW, count, replace=False).astype(np.uint32) + np.uint32(lo)
+    nb = nb[nb != hub]
+    rep = nb[rng.integers(0, len(nb), repeats)] if repeats else nb[:0]
+    d = np.concatenate([nb, rep])
+    return np.full(len(d), hub, np.uint32), d
+
+
+@pytest.mark.parametrize("hub_sizes", [(2, 7, 50), (60, 200, 250), (255, 255, 255, 255)])
+def test_csr_groups_within_id_windows(hub_sizes):
+    """Ids of 24+ bits with hubs whose neighbours and repeated edges crowd
+    one 256-id window (runs of keys that differ only in their lowest digit,
+    sorted by that digit's pass alone), plus a self-loop each, on an R-MAT
+    background; several such hubs in one sort tile for the last case."""
+    rng = np.random.default_rng(sum(hub_sizes))
+    n = (1 << 24) + 77
+    src, dst = gen.rmat(24, 600_000, 5 + len(hub_sizes))
+    srcs, dsts = [src], [dst]
+    for i, c in enumerate(hub_sizes):
+        hub = int(rng.integers(0, n))
+        a, b = _window_hub(hub, int(rng.integers(0, n - WINDOW)), c, rng, repeats=c // 3)
+        srcs += [a, b[:1], np.array([hub], np.uint32)]
+        dsts += [b, a[:1], np.array([hub], np.uint32)]
+    src = np.concatenate(srcs).astype(np.uint32)
+    dst = np.concatenate(dsts).astype(np.uint32)
+    perm = rng.permutation(len(src))
+    r = run_both(src[perm], dst[perm], n, tau=2, omega=2, B=40, k=4_000, kg=3_000, seed=21)
+    check_all(r)
+
+
+def test_csr_group_overflowing_a_tile():
+    """Thousands of repeats of a few edges of one vertex (one run of equal
+    keys longer than a sort tile of 8,192 keys and than a dedup tile of
+    4,096): the repeats straddle tiles of every pass and of the dedup."""
+    rng = np.random.default_rng(3)
+    n = 1 << 25
+    src, dst = gen.rmat(25, 300_000, 9)
+    a, b = _window_hub(12345, 1 << 20, 200, rng, repeats=12_000)
+    src = np.concatenate([src, a, b]).astype(np.uint32)
+    dst = np.concatenate([dst, b, a]).astype(np.uint32)
+    r = run_both(src, dst, n, tau=2, omega=2, B=40, k=4_000, kg=3_000, seed=22)
+    check_all(r)
+    assert r["og"].degrees()[12345] >= 190
+
+
 def test_bter_community_graph():
     """BTER-like community graph (dense blocks of similar degree, Chung-Lu
     excess): CSR, bins, every dumped sample and the estimates."""
@@ -306,3 +356,31 @@ def test_csr_many_tiles_ragged_tail():
     assert g.m == og.m and g.rejected == og.rejected == 10
     assert (W.to_host_u64(g.rowptr) == og.rowptr).all()
     assert (g.col[: 2 * g.m].cpu().numpy().view(np.uint32) == og.col).all()
+
+
+def test_plain_autotune_pick_is_used():
+    """The plain sampler's autotuner times candidate shapes on the graph,
+    checks that their counts agree, and wedge_sample_close then launches
+    graphs of that size with the pick; counts stay bit-exact."""
+    n, src, dst = gen.rmat_graph500(14, 16, seed=8)
+    B, k, seed = 30, 30_000, 6
+    g = W.build_csr(dev(src), dev(dst), n)
+    bi = W.bin_counts(g, 2, 2, B)
+    hk = W.k_for_bins(bi.h_p_b, k)
+    torch.cuda.synchronize()
+    before = W.sample_close_shape(n, g.m, B)
+    assert (before.lanes_in_flight, before.samples_per_tile) == (1, 256)
+    cands = [W.make_shape(1, 256, 0), W.make_shape(2, 1024, 0), W.make_shape(4, 4096, 0),
+             W.make_shape(8, 8192, 0)]
+    best, ms = W.sample_close_autotune(g, bi, hk, k, seed, cands, reps=2)
+    print(f"[autotune] ms={['%.3f' % t for t in ms]} best=({best.lanes_in_flight}, "
+          f"{best.samples_per_tile})", flush=True)
+    assert len(ms) == 4 and all(t > 0 for t in ms)
+    after = W.sample_close_shape(n, g.m, B)
+    assert (after.lanes_in_flight, after.samples_per_tile) == (best.lanes_in_flight,
+                                                               best.samples_per_tile)
+    so = W.sample_close(g, bi, hk, k, seed)
+    q = W.to_host_u64(so.q).reshape(B + 1, 4)
+    og = O.build_graph(src, dst, n)
+    s = O.sample(og, 2, 2, B, hk, k, seed)
+    assert (q == s.q).all()
