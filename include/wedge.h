@@ -95,6 +95,22 @@ int wedge_build_csr(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in,
                     uint64_t* d_rowptr, uint32_t* d_col, uint64_t* d_info, void* d_workspace,
                     size_t workspace_bytes, void* stream);
 
+/* wedge_build_csr_noalloc -- wedge_build_csr with no workspace argument and
+ * no device allocation, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same inputs, outputs, results and device-side conditions as
+ * wedge_build_csr for m_in <= 2^20 input edges; the workspace is a
+ * file-scope device array of the library (36 MiB per GPU the library runs
+ * on, held until the process ends), which the call clears where the build
+ * needs zeros.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (on different streams or host threads) race and give
+ * wrong results; serialise them.
+ * Errors: EWORKSPACE (m_in > 2^20), ERANGE (n == 0), EINVAL (null or
+ *         misaligned pointer), EHIP. */
+int wedge_build_csr_noalloc(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in,
+                            uint32_t n, uint64_t* d_rowptr, uint32_t* d_col, uint64_t* d_info,
+                            void* stream);
+
 /* ------------------------------------------------------------------------
  * wedge_validate_csr -- device check that an adjacency has the form the path
  * assumes: the paper's input is an undirected graph without repeated edges

@@ -13,6 +13,8 @@
 // 2. One pass over the sorted keys: a key is kept iff it is not a self-loop
 //    and differs from its predecessor; its exclusive count is its position
 //    in col, and every change of src writes the row starts it spans.
+#include <mutex>
+
 #include "common.hpp"
 #include "radix.hpp"
 #include "scan.hpp"
@@ -230,9 +232,68 @@ int csr_build(const uint32_t* d_src, const uint32_t* d_dst, uint64_t m_in, uint3
   return os_flag_stalls(osc, d_info, ~0ULL, st);
 }
 
+// ------------------------------------------------------ allocation-free form
+// The build's workspace, for edge lists of at most kNoAllocMaxEdges input
+// edges, as a file-scope device array.  Host code never passes the array's
+// name to a kernel (in host code it is a host-side stand-in, not a device
+// address): the address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and kept per device.  Each device holds
+// its own copy of the array until the process ends.
+constexpr uint64_t kNoAllocMaxEdges = 1ULL << 20;
+constexpr size_t kNoAllocScratchBytes = 36ULL << 20;  // >= csr_workspace_bytes(2^20)
+constexpr int kNoAllocMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+static int scratch_address(void** out) {
+  int dev = 0;
+  WEDGE_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return set_error(WEDGE_ERANGE, "wedge_build_csr_noalloc: device %d beyond %d", dev,
+                     kNoAllocMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    WEDGE_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_error(WEDGE_EHIP, "wedge_build_csr_noalloc: no address for the scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return WEDGE_OK;
+}
+
 }  // namespace wedge
 
 using namespace wedge;
+
+extern "C" int wedge_build_csr_noalloc(const uint32_t* d_src, const uint32_t* d_dst,
+                                       uint64_t m_in, uint32_t n, uint64_t* d_rowptr,
+                                       uint32_t* d_col, uint64_t* d_info, void* stream) {
+  clear_error();
+  if (n == 0) return set_error(WEDGE_ERANGE, "wedge_build_csr_noalloc: n must be >= 1");
+  if (m_in > kNoAllocMaxEdges)
+    return set_error(WEDGE_EWORKSPACE,
+                     "wedge_build_csr_noalloc: m_in = %llu exceeds the %llu input edges its "
+                     "static scratch holds",
+                     (unsigned long long)m_in, (unsigned long long)kNoAllocMaxEdges);
+  if (!d_rowptr || !d_info) return set_error(WEDGE_EINVAL, "wedge_build_csr_noalloc: null rowptr/info");
+  if (m_in > 0 && (!d_src || !d_dst || !d_col))
+    return set_error(WEDGE_EINVAL, "wedge_build_csr_noalloc: null src/dst/col with m_in > 0");
+  if (!aligned(d_rowptr, 8) || !aligned(d_info, 8) || !aligned(d_src, 4) || !aligned(d_dst, 4) ||
+      !aligned(d_col, 4))
+    return set_error(WEDGE_EINVAL, "wedge_build_csr_noalloc: misaligned pointer");
+  if (csr_workspace_bytes(m_in) > kNoAllocScratchBytes)
+    return set_error(WEDGE_EWORKSPACE, "wedge_build_csr_noalloc: scratch too small");
+  void* ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc) return rc;
+  // every counter and status word the build uses is cleared by the build
+  // itself (fill kernels), so the array's previous contents do not matter
+  return csr_build(d_src, d_dst, m_in, n, nullptr, nullptr, 1, d_rowptr, d_col, d_info, ws,
+                   (hipStream_t)stream);
+}
 
 extern "C" size_t wedge_build_csr_workspace(uint64_t m_in, uint32_t n) {
   (void)n;

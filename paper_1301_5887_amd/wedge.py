@@ -97,6 +97,7 @@ SIGNATURES = {
     "wedge_build_csr_workspace": (ctypes.c_size_t, [_c_u64, _c_u32]),
     "wedge_build_csr": (ctypes.c_int, [_vp, _vp, _c_u64, _c_u32, _vp, _vp, _vp, _vp,
                                        ctypes.c_size_t, _vp]),
+    "wedge_build_csr_noalloc": (ctypes.c_int, [_vp, _vp, _c_u64, _c_u32, _vp, _vp, _vp, _vp]),
     "wedge_validate_csr": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _vp]),
     "wedge_index_bytes": (ctypes.c_size_t, [_c_u32, _c_u64, _c_u32]),
     "wedge_bin_counts_workspace": (ctypes.c_size_t, [_c_u32]),
