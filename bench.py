@@ -138,6 +138,8 @@ def parse_args():
     ap.add_argument("--cv-repeats", type=int, default=3,
                     help="timed runs of the estimator comparison after one warm-up run; "
                          "each estimator's time is the median over them")
+    ap.add_argument("--no-hash", action="store_true",
+                    help="skip the closure-by-edge-table leg")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched workload (512 R-MAT graphs)")
     ap.add_argument("--batch-graphs", type=int, default=512)
@@ -325,6 +327,8 @@ def plain_workload(args, torch, n, src, dst, workload):
     alloc = alloc_comparison(args, torch, W, g, bi, hk, kg, k) if args.alloc_seeds > 0 else None
     join = closure_join(args, torch, W, g, bi, hk, kg, src, dst) if args.join else None
     tri = triangle_sample(args, torch, g, bi, est) if args.triangles > 0 else None
+    hashp = None if args.no_hash else hash_probe(args, torch, W, g, bi, hk, kg, q_step,
+                                                  avg["sample_close"], probes)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -363,6 +367,7 @@ def plain_workload(args, torch, n, src, dst, workload):
         "roofline_csr": roofline_csr,
         "estimators": cvcmp,
         "triangle_sample": tri,
+        "hash_probe": hashp,
         "closure_join": join,
         "allocation_form": alloc,
         "estimates": {"c": est.glob["c"], "c_global": est.glob["c_global"], "t": est.glob["t"],
@@ -540,6 +545,42 @@ def closure_join(args, torch, W, g, bi, hk, kg, src, dst):
     log(f"[bench] closure join: {qa.numel()} wedges against {m_in} streamed edges in "
         f"{t_join * 1e3:.1f} ms")
     return join
+
+
+def hash_probe(args, torch, W, g, bi, hk, kg, q_step, t_search_ms, search_probes):
+    """The closure test by lookup in an edge table instead of the search on
+    the same graph and samples: the table's build time (HIP events, it is not
+    part of the step), the sampler launch with it, its slots read per sample,
+    and its counts against the step's."""
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    build, samp = [], []
+    h = None
+    for r in range(3):
+        e[0].record(stream)
+        h = W.edge_hash(g, table=None if h is None else h.table)
+        e[1].record(stream)
+        out = W.sample_close_hashed(g, bi, h, hk, kg, args.seed)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        if r > 0:
+            build.append(e[0].elapsed_time(e[1]))
+            samp.append(e[1].elapsed_time(e[2]))
+    qh = W.to_host_u64(out.q).reshape(q_step.shape)
+    K = int(hk.sum()) + kg
+    res = {"table_bits": h.bits, "table_bytes": 8 << h.bits, "load": round(g.m / (1 << h.bits), 4),
+           "keys_without_slot": int(h.full.item()),
+           "build_ms": round(float(np.median(build)), 3),
+           "sample_close_ms": round(float(np.median(samp)), 4),
+           "search_sample_close_ms": round(t_search_ms, 4),
+           "slots_per_sample": round(int(out.probe_loads.item()) / K, 4),
+           "search_words_per_sample": round(search_probes / K, 4),
+           "counts_equal_search": bool((qh == q_step).all())}
+    log(f"[bench] edge table: built in {res['build_ms']} ms, sampler {res['sample_close_ms']} ms "
+        f"(search {res['search_sample_close_ms']} ms), counts equal {res['counts_equal_search']}")
+    del h, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def triangle_sample(args, torch, g, bi, est):

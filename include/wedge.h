@@ -230,6 +230,35 @@ int wedge_sample_close_tuned(const uint64_t* d_rowptr, const uint32_t* d_col, ui
                              int lanes_in_flight, uint64_t samples_per_tile, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Closure by an edge table (Alg. phase3b matches a wedge's endpoint pair
+ * against the edge set by key; here the match is a lookup).  The table holds
+ * every edge once as the key min << 32 | max in 2^bits slots of 8 bytes
+ * (linear probing, a Fibonacci hash of the key; empty slot = all bits set),
+ * with 2^bits >= 2m so at most half the slots are used.
+ *
+ * wedge_edge_hash_bits(m): the least bits >= 4 with 2^bits >= 2m.
+ * wedge_edge_hash_build: clears d_table (device uint64[2^bits], caller-owned)
+ *   and inserts the edge {v, w}, v < w, of every adjacency entry; d_full
+ *   (device uint64[1], overwritten) counts keys that found no empty slot
+ *   (not expected at that load).  Asynchronous.
+ *   Errors: EINVAL, ERANGE (n == 0, bits outside [4, 40] or 2^bits < 2m), EHIP.
+ * wedge_sample_close_hashed: wedge_sample_close (same samples, same counts,
+ *   same dump) with the closure test a lookup in the table built from the
+ *   same rowptr/col; d_probe_loads counts table slots read instead of
+ *   adjacency words.  Errors: as wedge_sample_close, plus EINVAL (table) and
+ *   ERANGE (bits).
+ * ---------------------------------------------------------------------- */
+uint32_t wedge_edge_hash_bits(uint64_t m);
+int wedge_edge_hash_build(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n, uint64_t m,
+                          uint64_t* d_table, uint32_t bits, uint64_t* d_full, void* stream);
+int wedge_sample_close_hashed(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,
+                              uint64_t m, const void* d_index, uint32_t max_bins,
+                              const uint64_t* h_k, uint64_t k_global, uint64_t seed,
+                              uint32_t graph_id, uint64_t* d_q, uint64_t* d_probe_loads,
+                              wedge_sample_rec* d_dump, uint64_t dump_per_bin,
+                              const uint64_t* d_table, uint32_t bits, void* stream);
+
+/* ------------------------------------------------------------------------
  * wedge_estimate -- Alg. phase4c summary and Eq. global_est, host FP64, in
  * this order (no FMA contraction):
  *   c_b = (q1+q2+q3) / k_b;   t_b = (p_b * (6 q1 + 3 q2 + 2 q3)) / (6 k_b)

@@ -28,6 +28,7 @@
 #include <tuple>
 #include <vector>
 
+#include "hash.hpp"
 #include "sample.hpp"
 #include "scan.hpp"
 
@@ -218,6 +219,19 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
     //    search it may save is long.
     uint64_t da[U], dc[U], my[U];
     bool in_a[U];
+    if (A.hash) {
+      // closure by lookup in the edge table; the endpoints' degrees are read
+      // only where a class or a record needs them
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        found[u] = act[u] && A.closure && hash_has_edge(A.hash, A.hash_bits, a[u], c[u], &probes);
+        da[u] = dc[u] = 0;
+        if (act[u] && (A.feat || (found[u] && !global))) {
+          da[u] = (A.ix.vmeta[a[u] + 1] & kRowMask) - (A.ix.vmeta[a[u]] & kRowMask);
+          dc[u] = (A.ix.vmeta[c[u] + 1] & kRowMask) - (A.ix.vmeta[c[u]] & kRowMask);
+        }
+      }
+    } else {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       uint64_t ma = 0, mc = 0;
@@ -321,6 +335,7 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
         if (in_a[u]) dc[u] = dy; else da[u] = dy;
       }
     }
+    }  // search form
     // 5. class and tallies
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -671,7 +686,8 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
                       const void* d_index, uint32_t max_bins, const uint64_t* h_k,
                       uint64_t k_global, uint64_t seed, uint32_t graph_id, uint64_t* d_q,
                       uint64_t* d_probe_loads, wedge_sample_rec* d_dump, uint64_t dump_per_bin,
-                      const SampleTuning* tuning, hipStream_t st) {
+                      const SampleTuning* tuning, hipStream_t st,
+                      const uint64_t* d_hash = nullptr, int hash_bits = 0) {
   if (n == 0) return set_error(WEDGE_ERANGE, "wedge_sample_close: n must be >= 1");
   if (max_bins == 0 || max_bins > 4096)
     return set_error(WEDGE_ERANGE, "wedge_sample_close: max_bins must be in [1, 4096]");
@@ -717,6 +733,8 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
   A.omega = 2;
   A.tau = 1;
   A.closure = 1;
+  A.hash = d_hash;
+  A.hash_bits = hash_bits;
   TaskTable T;
   T.graph_word = graph_id;
   T.ntask = 0;
@@ -962,6 +980,25 @@ extern "C" int wedge_sample_close_tuned(const uint64_t* d_rowptr, const uint32_t
   return sample_close_impl(d_rowptr, d_col, n, m, d_index, max_bins, h_k, k_global, seed,
                            graph_id, d_q, d_probe_loads, d_dump, dump_per_bin, &t,
                            (hipStream_t)stream);
+}
+
+extern "C" int wedge_sample_close_hashed(const uint64_t* d_rowptr, const uint32_t* d_col,
+                                         uint32_t n, uint64_t m, const void* d_index,
+                                         uint32_t max_bins, const uint64_t* h_k,
+                                         uint64_t k_global, uint64_t seed, uint32_t graph_id,
+                                         uint64_t* d_q, uint64_t* d_probe_loads,
+                                         wedge_sample_rec* d_dump, uint64_t dump_per_bin,
+                                         const uint64_t* d_table, uint32_t bits, void* stream) {
+  clear_error();
+  if (!d_table || !aligned(d_table, 8))
+    return set_error(WEDGE_EINVAL, "wedge_sample_close_hashed: null or misaligned table");
+  if (bits < 4 || bits > 40 || (1ULL << bits) < 2 * m)
+    return set_error(WEDGE_ERANGE, "wedge_sample_close_hashed: 2^bits must be >= 2m");
+  SampleTuning t;
+  const bool tuned = cached_tuning(n, m, max_bins, &t);
+  return sample_close_impl(d_rowptr, d_col, n, m, d_index, max_bins, h_k, k_global, seed,
+                           graph_id, d_q, d_probe_loads, d_dump, dump_per_bin,
+                           tuned ? &t : nullptr, (hipStream_t)stream, d_table, (int)bits);
 }
 
 extern "C" int wedge_sample_features(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t n,

@@ -46,6 +46,9 @@ struct SamplerCtx {
   // allocation form: centres from per-vertex counts instead of word 0
   const AllocRow* alloc = nullptr;     // [rows], nullable
   const uint64_t* alloc_pre = nullptr; // exclusive prefix of the counts
+  // closure by lookup in the edge table of hash.hpp instead of the search
+  const uint64_t* hash = nullptr;      // nullable
+  int hash_bits = 0;
 };
 
 struct Task {

@@ -110,6 +110,11 @@ SIGNATURES = {
     "wedge_sample_close_tuned": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _vp,
                                                 _c_u64, _c_u64, _c_u32, _vp, _vp, _vp, _c_u64,
                                                 ctypes.c_int, _c_u64, _vp]),
+    "wedge_edge_hash_bits": (_c_u32, [_c_u64]),
+    "wedge_edge_hash_build": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _vp, _vp]),
+    "wedge_sample_close_hashed": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _vp,
+                                                 _c_u64, _c_u64, _c_u32, _vp, _vp, _vp, _c_u64,
+                                                 _vp, _c_u32, _vp]),
     "wedge_estimate": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_u32, _c_u32, _c_u64, _c_u64,
                                       ctypes.c_double, _vp, _vp]),
     "wedge_batch_workspace_bytes": (ctypes.c_size_t, [_dp]),
@@ -419,6 +424,48 @@ def sample_close(g: Csr, bi: BinIndex, h_k: np.ndarray, k_global: int, seed: int
                                             int(lanes_in_flight or 4),
                                             int(samples_per_tile or 4096), _stream(stream))
     _check(rc)
+    return out
+
+
+@dataclass
+class EdgeHash:
+    table: torch.Tensor   # int64[2^bits]
+    bits: int
+    full: torch.Tensor    # int64[1]: keys without an empty slot (expected 0)
+
+
+def edge_hash(g: Csr, stream=None, table: torch.Tensor | None = None) -> EdgeHash:
+    """wedge_edge_hash_build (asynchronous): the graph's edge table."""
+    _require_gpu(g.rowptr, g.col)
+    bits = int(lib().wedge_edge_hash_bits(g.m))
+    if table is None or table.numel() < (1 << bits):
+        table = torch.empty(1 << bits, dtype=torch.int64, device=g.rowptr.device)
+    full = torch.empty(1, dtype=torch.int64, device=g.rowptr.device)
+    _check(lib().wedge_edge_hash_build(_ptr(g.rowptr), _ptr(g.col), g.n, g.m, _ptr(table), bits,
+                                       _ptr(full), _stream(stream)))
+    return EdgeHash(table=table, bits=bits, full=full)
+
+
+def sample_close_hashed(g: Csr, bi: BinIndex, h: EdgeHash, h_k: np.ndarray, k_global: int,
+                        seed: int, graph_id: int = 0, dump_per_bin: int = 0, stream=None,
+                        out: SampleOut | None = None) -> SampleOut:
+    """wedge_sample_close_hashed (asynchronous)."""
+    _require_gpu(g.rowptr, g.col, bi.index, h.table)
+    dev = g.rowptr.device
+    hk = np.ascontiguousarray(h_k, dtype=np.uint64)
+    assert hk.shape[0] == bi.max_bins
+    rows = bi.max_bins + 1
+    if out is None:
+        q = torch.empty(rows * 4, dtype=torch.int64, device=dev)
+        probe = torch.empty(1, dtype=torch.int64, device=dev)
+        dump = (torch.zeros((rows * dump_per_bin, 4), dtype=torch.int32, device=dev)
+                if dump_per_bin > 0 else None)
+        out = SampleOut(q=q, probe_loads=probe, dump=dump, h_k=hk, k_global=k_global)
+    _check(lib().wedge_sample_close_hashed(_ptr(g.rowptr), _ptr(g.col), g.n, g.m, _ptr(bi.index),
+                                           bi.max_bins, hk.ctypes.data_as(ctypes.c_void_p),
+                                           k_global, seed, graph_id, _ptr(out.q),
+                                           _ptr(out.probe_loads), _ptr(out.dump), dump_per_bin,
+                                           _ptr(h.table), h.bits, _stream(stream)))
     return out
 
 

@@ -384,3 +384,39 @@ def test_plain_autotune_pick_is_used():
     og = O.build_graph(src, dst, n)
     s = O.sample(og, 2, 2, B, hk, k, seed)
     assert (q == s.q).all()
+
+
+@pytest.mark.parametrize("case", ["worked", "rmat16", "ids25", "bter"])
+def test_hashed_closure_matches_search(case):
+    """Closure by lookup in the edge table (wedge_edge_hash_build +
+    wedge_sample_close_hashed): every dumped sample and every class count
+    equal to the search's and to the oracle's."""
+    if case == "worked":
+        e = np.array([[1, 2], [1, 3], [2, 4], [3, 4], [3, 5], [4, 5], [4, 6]], dtype=np.uint32)
+        n, src, dst = 7, e[:, 0], e[:, 1]
+    elif case == "rmat16":
+        n, src, dst = gen.rmat_graph500(16, 16, seed=7)
+    elif case == "ids25":
+        src, dst = gen.rmat(25, 400_000, 56)
+        n = 1 << 25
+    else:
+        n = 30_000
+        src, dst = gen.bter(n, 2.1, 10, 3_000, 11)
+    B, k, kg, seed = 40, 20_000, 15_000, 31
+    print(f"[hash] {case} n={n} m_in={len(src)}", flush=True)
+    g = W.build_csr(dev(src), dev(dst), n)
+    bi = W.bin_counts(g, 2, 2, B)
+    hk = W.k_for_bins(bi.h_p_b, k)
+    h = W.edge_hash(g)
+    so = W.sample_close(g, bi, hk, kg, seed, dump_per_bin=k)
+    sh = W.sample_close_hashed(g, bi, h, hk, kg, seed, dump_per_bin=k)
+    torch.cuda.synchronize()
+    assert int(h.full.item()) == 0
+    q = W.to_host_u64(so.q).reshape(B + 1, 4)
+    qh = W.to_host_u64(sh.q).reshape(B + 1, 4)
+    assert (q == qh).all()
+    assert torch.equal(so.dump, sh.dump)
+    assert int(sh.probe_loads.item()) >= int(hk.sum()) + kg
+    og = O.build_graph(src, dst, n)
+    s = O.sample(og, 2, 2, B, hk, kg, seed)
+    assert (qh == s.q).all()
