@@ -129,6 +129,9 @@ def parse_args():
     ap.add_argument("--alloc-seeds", type=int, default=0,
                     help="compare the Phase 2a allocation sampler with the i.i.d. one over "
                          "this many seeds (0: skip)")
+    ap.add_argument("--stream", action="store_true",
+                    help="also run the streamed path (edge list in host memory, no adjacency "
+                         "on the device) on the step graph's simple edge list")
     ap.add_argument("--join", action="store_true",
                     help="also test the step's wedges by a join against the edge list "
                          "streamed from host memory")
@@ -326,6 +329,7 @@ def plain_workload(args, torch, n, src, dst, workload):
                                                          avg["sample_close"])
     alloc = alloc_comparison(args, torch, W, g, bi, hk, kg, k) if args.alloc_seeds > 0 else None
     join = closure_join(args, torch, W, g, bi, hk, kg, src, dst) if args.join else None
+    streamed = stream_leg(args, torch, W, g, bi, k, kg, q_step) if args.stream else None
     tri = triangle_sample(args, torch, g, bi, est) if args.triangles > 0 else None
     hashp = None if args.no_hash else hash_probe(args, torch, W, g, bi, hk, kg, q_step,
                                                   avg["sample_close"], probes)
@@ -369,6 +373,7 @@ def plain_workload(args, torch, n, src, dst, workload):
         "triangle_sample": tri,
         "hash_probe": hashp,
         "closure_join": join,
+        "streamed": streamed,
         "allocation_form": alloc,
         "estimates": {"c": est.glob["c"], "c_global": est.glob["c_global"], "t": est.glob["t"],
                       "t_global": est.glob["t_global"], "eps": est.glob["eps_global"]},
@@ -545,6 +550,61 @@ def closure_join(args, torch, W, g, bi, hk, kg, src, dst):
     log(f"[bench] closure join: {qa.numel()} wedges against {m_in} streamed edges in "
         f"{t_join * 1e3:.1f} ms")
     return join
+
+
+def stream_leg(args, torch, W, g, bi, k, kg, q_step):
+    """The step's samples by the streamed path: the graph's simple edge list
+    (each edge once, random order and orientation) in pinned host memory,
+    degrees, draws, gathered rows and the closure join all from passes over
+    it, no adjacency on the device; its counts against the step's."""
+    n, m = g.n, g.m
+    deg = g.rowptr[1:] - g.rowptr[:-1]
+    rows = torch.repeat_interleave(torch.arange(n, dtype=torch.int32, device=g.col.device), deg)
+    col = g.col[: 2 * m]
+    keep = col > rows
+    u, w = rows[keep], col[keep]
+    del rows, col, keep, deg
+    gen_ = torch.Generator(device=g.col.device)
+    gen_.manual_seed(args.seed)
+    perm = torch.randperm(m, device=g.col.device, generator=gen_)
+    u, w = u[perm], w[perm]
+    del perm
+    flip = torch.rand(m, device=g.col.device, generator=gen_) < 0.5
+    a, b = torch.where(flip, w, u), torch.where(flip, u, w)
+    del u, w, flip
+    ha = torch.empty(m, dtype=torch.int32, pin_memory=True)
+    hb = torch.empty(m, dtype=torch.int32, pin_memory=True)
+    ha.copy_(a)
+    hb.copy_(b)
+    del a, b
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    B = bi.max_bins
+    hk_req = np.full(B, k, dtype=np.uint64)
+    cap = m   # half the edge ends per gather round
+    ws = W.Workspace(g.col.device)
+    runs = []
+    out = None
+    for _ in range(2):          # the second, warm run is reported
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = W.sample_stream(ha, hb, n, hk_req, kg, args.seed, 2, 2, B, gather_cap=cap, ws=ws)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+    q = W.to_host_u64(out.q).reshape(B + 1, 4)
+    K = int(out.h_k.sum()) + out.k_global
+    passes = 3 + out.rounds
+    res = {"edges": m, "host_bytes": 8 * m, "gather_cap": cap, "rounds": out.rounds,
+           "edge_ends_gathered": out.gathered, "edge_passes": passes,
+           "seconds": round(runs[-1], 4), "seconds_first_run": round(runs[0], 4),
+           "closure_checks_per_s": K / runs[-1],
+           "host_link_GBps": round(passes * 8 * m / runs[-1] / 1e9, 2),
+           "counts_equal_search": bool((q == q_step).all())}
+    log(f"[bench] streamed path: {K} checks over {passes} passes of {m} edges in "
+        f"{runs[-1]:.3f} s, counts equal {res['counts_equal_search']}")
+    del ha, hb, ws, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def hash_probe(args, torch, W, g, bi, hk, kg, q_step, t_search_ms, search_probes):

@@ -15,8 +15,9 @@
  *    every buffer (sizes come from the *_workspace / *_bytes queries); the
  *    library allocates nothing.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
- *    enqueued asynchronously on it; no call synchronises except
- *    wedge_index_status, which says so.
+ *    enqueued asynchronously on it; no call synchronises except those whose
+ *    description says so (wedge_index_status, the autotuners, calls that
+ *    read a count back before sizing their next step, wedge_sample_stream).
  *  - Return value: WEDGE_OK (0) or a negative wedge_status.  Arguments are
  *    validated on the host before anything is enqueued; on error nothing is
  *    enqueued, outputs are untouched and wedge_last_error() returns a message
@@ -43,7 +44,8 @@ typedef enum {
   WEDGE_EHIP = -4,       /* a HIP runtime call or kernel launch failed */
   WEDGE_ENOTSUP = -5,    /* no usable gfx950 device */
   WEDGE_EGRAPH = -6      /* the adjacency is not a sorted simple undirected graph
-                            (only with WEDGE_VALIDATE=1; see wedge_validate_csr) */
+                            (only with WEDGE_VALIDATE=1; see wedge_validate_csr),
+                            or a streamed edge list is not simple */
 } wedge_status;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -631,6 +633,61 @@ int wedge_closure_join(const uint32_t* d_a, const uint32_t* d_c, uint64_t k,
                        const uint32_t* h_src, const uint32_t* h_dst, uint64_t m_in,
                        uint64_t chunk_edges, uint8_t* d_closed, void* d_workspace,
                        size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * wedge_sample_stream -- wedge_bin_counts + wedge_sample_close on an edge
+ * list held in host memory, with no adjacency on the device (the paper's
+ * setting: every phase is a pass over the edge list, Alg. phase1a to
+ * phase4c).  The edge list streams in chunks of chunk_edges (0: 2^24),
+ * copies on a second stream overlapping the kernels:
+ *   a degree pass (Alg. phase1a: a count per endpoint), then the bins and
+ *   the sampling index (Alg. phase1b); the draws of wedge_sample_close (same
+ *   Philox stream, centres and neighbour ranks i, j) without reading an
+ *   adjacency; gather passes that collect and sort the edges of the drawn
+ *   centres, a vertex range of at most gather_cap edge ends at a time, which
+ *   turns (i, j) into the endpoints (Alg. phase2c: a centre sees all its
+ *   edges); a closure join (Alg. phase3b, as wedge_closure_join); the
+ *   classes of Alg. phase4c from the streamed degrees.
+ * The input must be simple (no repeated edge, in either orientation; Sec.
+ * 4.1 states the input that way): a degree is then a count.  Self-loops are
+ * skipped; edges with an id >= n are skipped and counted in h_info[1].  For
+ * such a list the bins, counts and records equal those of wedge_build_csr +
+ * wedge_bin_counts + wedge_sample_close on the same list.
+ *
+ * In:  h_src[m_in], h_dst[m_in]  host uint32 edge list (pinned memory lets
+ *                     the copies overlap); read in 3 + (gather rounds)
+ *                     passes; must not change during the call.
+ *      n, tau, omega, max_bins as wedge_bin_counts; h_k[max_bins],
+ *      k_global, seed as wedge_sample_close (graph_id 0); a bin whose p_b
+ *      turns out 0 gets no samples.
+ *      gather_cap     largest number of edge ends one gather round holds
+ *                     (its sort buffers: 16 bytes per end); it must be at
+ *                     least the largest degree of a drawn centre.
+ * Out: d_n_b[max_bins], d_p_b[max_bins] as wedge_bin_counts;
+ *      d_q[(max_bins+1)*4] and d_dump (nullable, dump_per_bin records per
+ *      row) as wedge_sample_close.
+ *      h_info         nullable host uint64[4]: m (edges counted), edges
+ *                     skipped for an id >= n, gather rounds, edge ends
+ *                     gathered.
+ * Workspace: wedge_sample_stream_workspace(n, m_in, max_bins, h_k, k_global,
+ *            gather_cap, chunk_edges) bytes (256-byte aligned).
+ * Unlike the other calls this one synchronises `stream` (it sizes later
+ * passes from earlier results).
+ * Errors: EINVAL, ERANGE (n == 0, tau == 0, omega < 2, max_bins outside
+ *         [1, 4096], gather_cap outside [1, 2^40), a k above 2^40),
+ *         EWORKSPACE (workspace, or a drawn centre's degree above
+ *         gather_cap), EGRAPH (repeated edges found in a drawn centre's
+ *         row; the results are then not those of the simple graph), EHIP.
+ * ---------------------------------------------------------------------- */
+size_t wedge_sample_stream_workspace(uint32_t n, uint64_t m_in, uint32_t max_bins,
+                                     const uint64_t* h_k, uint64_t k_global,
+                                     uint64_t gather_cap, uint64_t chunk_edges);
+int wedge_sample_stream(const uint32_t* h_src, const uint32_t* h_dst, uint64_t m_in, uint32_t n,
+                        uint32_t tau, uint64_t omega, uint32_t max_bins, const uint64_t* h_k,
+                        uint64_t k_global, uint64_t seed, uint64_t gather_cap,
+                        uint64_t chunk_edges, uint64_t* d_n_b, uint64_t* d_p_b, uint64_t* d_q,
+                        wedge_sample_rec* d_dump, uint64_t dump_per_bin, uint64_t* h_info,
+                        void* d_workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Triangle sample and degree assortativity (Sec. 3 theorem on sampled

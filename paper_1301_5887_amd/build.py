@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libwedge.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["abi.cpp", "radix.hip", "csr.hip", "bins.hip", "sample.hip", "batch.hip", "mlp.hip",
-           "census.hip", "triangles.hip", "join.hip", "cv_est.cpp", "validate.hip", "hash.hip"]
+           "census.hip", "triangles.hip", "join.hip", "cv_est.cpp", "validate.hip", "hash.hip", "stream.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -1,0 +1,59 @@
+// Chunked pass over an edge list held in host memory: chunk j is copied on a
+// second stream of the device into one of two buffer pairs while the caller's
+// stream runs the consumer on chunk j - 1 (pinned host memory lets the copies
+// overlap the kernels).
+#pragma once
+
+#include "common.hpp"
+
+namespace wedge {
+
+constexpr uint64_t kEdgeChunk = 1ULL << 24;
+
+// One copy stream per device, created on first use (default priority) and
+// kept until the process ends.
+int copy_stream(hipStream_t* out);
+
+// consume(src, dst, ne) enqueues the work on chunk (src, dst) of ne edges on
+// st; buf[b][0] and buf[b][1] hold chunk uint32 each.  Returns the first
+// error of a copy, an event call or the consumer.
+template <class Consume>
+int stream_edges(const uint32_t* h_src, const uint32_t* h_dst, uint64_t m_in, uint64_t chunk,
+                 uint32_t* buf[2][2], hipStream_t st, Consume consume) {
+  if (m_in == 0) return WEDGE_OK;
+  hipStream_t cs;
+  int rc = copy_stream(&cs);
+  if (rc) return rc;
+  hipEvent_t start, copied[2], used[2];
+  WEDGE_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  for (int b = 0; b < 2; ++b) {
+    WEDGE_HIP_TRY(hipEventCreateWithFlags(&copied[b], hipEventDisableTiming));
+    WEDGE_HIP_TRY(hipEventCreateWithFlags(&used[b], hipEventDisableTiming));
+  }
+  // the copies may only overwrite the buffers once earlier work on the
+  // caller's stream is done with them
+  WEDGE_HIP_TRY(hipEventRecord(start, st));
+  WEDGE_HIP_TRY(hipStreamWaitEvent(cs, start, 0));
+  const uint64_t nchunks = (m_in + chunk - 1) / chunk;
+  for (uint64_t j = 0; j < nchunks && rc == WEDGE_OK; ++j) {
+    const int b = (int)(j & 1);
+    const uint64_t e0 = j * chunk;
+    const uint64_t ne = (m_in - e0) < chunk ? (m_in - e0) : chunk;
+    if (j >= 2) WEDGE_HIP_TRY(hipStreamWaitEvent(cs, used[b], 0));
+    WEDGE_HIP_TRY(hipMemcpyAsync(buf[b][0], h_src + e0, ne * 4, hipMemcpyHostToDevice, cs));
+    WEDGE_HIP_TRY(hipMemcpyAsync(buf[b][1], h_dst + e0, ne * 4, hipMemcpyHostToDevice, cs));
+    WEDGE_HIP_TRY(hipEventRecord(copied[b], cs));
+    WEDGE_HIP_TRY(hipStreamWaitEvent(st, copied[b], 0));
+    rc = consume((const uint32_t*)buf[b][0], (const uint32_t*)buf[b][1], ne);
+    WEDGE_HIP_TRY(hipEventRecord(used[b], st));
+  }
+  // events may be destroyed while work that records them is pending
+  WEDGE_HIP_TRY(hipEventDestroy(start));
+  for (int b = 0; b < 2; ++b) {
+    WEDGE_HIP_TRY(hipEventDestroy(copied[b]));
+    WEDGE_HIP_TRY(hipEventDestroy(used[b]));
+  }
+  return rc;
+}
+
+}  // namespace wedge

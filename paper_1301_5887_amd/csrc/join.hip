@@ -8,6 +8,7 @@
 #include <mutex>
 
 #include "common.hpp"
+#include "edge_stream.hpp"
 #include "scan.hpp"
 
 namespace wedge {
@@ -106,16 +107,14 @@ static size_t join_layout(uint64_t k, uint64_t chunk, JoinWorkspace* w, void* ba
   return off;
 }
 
-constexpr uint64_t kJoinChunk = 1ULL << 24;
+constexpr uint64_t kJoinChunk = kEdgeChunk;
 
-// One copy stream per device, created on first use and kept until the
-// process ends.
-static int copy_stream(hipStream_t* out) {
+int copy_stream(hipStream_t* out) {
   static std::mutex mu;
   static hipStream_t streams[64] = {};
   int dev = 0;
   WEDGE_HIP_TRY(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64) return set_error(WEDGE_ERANGE, "wedge_closure_join: device id");
+  if (dev < 0 || dev >= 64) return set_error(WEDGE_ERANGE, "copy_stream: device id");
   std::lock_guard<std::mutex> lock(mu);
   if (!streams[dev]) WEDGE_HIP_TRY(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
   *out = streams[dev];
@@ -154,41 +153,16 @@ extern "C" int wedge_closure_join(const uint32_t* d_a, const uint32_t* d_c, uint
   if (rc || (rc = fill<uint8_t>(w.mark, cap, 0, st))) return rc;
   k_join_insert<<<2048, 256, 0, st>>>(d_a, d_c, k, w.table, mask);
   WEDGE_LAUNCH_CHECK("k_join_insert");
-  hipStream_t cs;
-  if ((rc = copy_stream(&cs))) return rc;
-  hipEvent_t start, copied[2], used[2];
-  WEDGE_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-  for (int b = 0; b < 2; ++b) {
-    WEDGE_HIP_TRY(hipEventCreateWithFlags(&copied[b], hipEventDisableTiming));
-    WEDGE_HIP_TRY(hipEventCreateWithFlags(&used[b], hipEventDisableTiming));
-  }
-  // the copies may only overwrite the buffers once earlier work on the
-  // caller's stream is done with the workspace
-  WEDGE_HIP_TRY(hipEventRecord(start, st));
-  WEDGE_HIP_TRY(hipStreamWaitEvent(cs, start, 0));
-  const uint64_t nchunks = (m_in + chunk - 1) / chunk;
-  for (uint64_t j = 0; j < nchunks; ++j) {
-    const int b = (int)(j & 1);
-    const uint64_t e0 = j * chunk;
-    const uint64_t ne = (m_in - e0) < chunk ? (m_in - e0) : chunk;
-    if (j >= 2) WEDGE_HIP_TRY(hipStreamWaitEvent(cs, used[b], 0));
-    WEDGE_HIP_TRY(hipMemcpyAsync(w.buf[b][0], h_src + e0, ne * 4, hipMemcpyHostToDevice, cs));
-    WEDGE_HIP_TRY(hipMemcpyAsync(w.buf[b][1], h_dst + e0, ne * 4, hipMemcpyHostToDevice, cs));
-    WEDGE_HIP_TRY(hipEventRecord(copied[b], cs));
-    WEDGE_HIP_TRY(hipStreamWaitEvent(st, copied[b], 0));
-    unsigned blocks = (unsigned)((ne + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
-    k_join_probe<<<blocks, 256, 0, st>>>(w.buf[b][0], w.buf[b][1], ne, w.table, mask, w.mark);
-    WEDGE_LAUNCH_CHECK("k_join_probe");
-    WEDGE_HIP_TRY(hipEventRecord(used[b], st));
-  }
+  rc = stream_edges(h_src, h_dst, m_in, chunk, w.buf, st,
+                    [&](const uint32_t* src, const uint32_t* dst, uint64_t ne) -> int {
+                      unsigned blocks = (unsigned)((ne + 255) / 256);
+                      if (blocks > 4096) blocks = 4096;
+                      k_join_probe<<<blocks, 256, 0, st>>>(src, dst, ne, w.table, mask, w.mark);
+                      WEDGE_LAUNCH_CHECK("k_join_probe");
+                      return WEDGE_OK;
+                    });
+  if (rc) return rc;
   k_join_resolve<<<2048, 256, 0, st>>>(d_a, d_c, k, w.table, mask, w.mark, d_closed);
   WEDGE_LAUNCH_CHECK("k_join_resolve");
-  // events may be destroyed while work that records them is pending
-  WEDGE_HIP_TRY(hipEventDestroy(start));
-  for (int b = 0; b < 2; ++b) {
-    WEDGE_HIP_TRY(hipEventDestroy(copied[b]));
-    WEDGE_HIP_TRY(hipEventDestroy(used[b]));
-  }
   return WEDGE_OK;
 }

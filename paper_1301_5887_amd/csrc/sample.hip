@@ -121,7 +121,8 @@ __device__ inline uint64_t alloc_vertex(const SamplerCtx& A, const AllocRow& R, 
 }
 
 // One tile: samples [s0, s1) of index row f (graph g, bin word bword).
-template <int U, bool kAlloc = false>
+// kDraw: stop after the draws and record (centre, i, j) (streamed path).
+template <int U, bool kAlloc = false, bool kDraw = false>
 __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint32_t bword,
                             uint64_t gword, uint64_t s0, uint64_t s1, uint64_t fslot,
                             uint64_t sbase) {
@@ -204,6 +205,20 @@ __device__ void sample_tile(const SamplerCtx& A, TileSmem& sm, uint64_t f, uint3
         ia[u] = i;
         ic[u] = r + (r >= i ? 1 : 0);
       }
+    }
+    if (kDraw) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (act[u] && s[u] - sbase < A.dump_per_bin) {
+          wedge_sample_rec rec;
+          rec.v = v[u];
+          rec.a = (uint32_t)ia[u];
+          rec.c = (uint32_t)ic[u];
+          rec.cls = 0;
+          A.dump[f * A.dump_per_bin + (s[u] - sbase)] = rec;
+        }
+      }
+      continue;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -397,7 +412,7 @@ __device__ inline bool header_ok(const SamplerCtx& A) {
          H->num_graphs == A.num_graphs;
 }
 
-template <int U, bool kAlloc = false>
+template <int U, bool kAlloc = false, bool kDraw = false>
 __global__ __launch_bounds__(kSampWG, U == 1 ? 8 : 1) void k_sample_close(const SamplerCtx A, const TaskTable T) {
   __shared__ TileSmem sm;
   const uint64_t tile = blockIdx.x;
@@ -412,8 +427,8 @@ __global__ __launch_bounds__(kSampWG, U == 1 ? 8 : 1) void k_sample_close(const 
     if (threadIdx.x == 0) atomicAdd((unsigned long long*)&A.ix.hdr->mismatch, 1ULL);
     return;
   }
-  sample_tile<U, kAlloc>(A, sm, T.task[e].row, T.task[e].bword, T.graph_word, s0, s1,
-                         T.task[e].slot, sbase);
+  sample_tile<U, kAlloc, kDraw>(A, sm, T.task[e].row, T.task[e].bword, T.graph_word, s0, s1,
+                                T.task[e].slot, sbase);
 }
 
 // Persistent form: tiles of all (graph, row) pairs of a batch come from a
@@ -656,6 +671,11 @@ static int launch_tasks(const SamplerCtx& A, TaskTable& T, int U, hipStream_t st
     WEDGE_LAUNCH_CHECK("k_sample_close");
     return WEDGE_OK;
   }
+  if (A.draw_only) {
+    k_sample_close<1, false, true><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T);
+    WEDGE_LAUNCH_CHECK("k_sample_close");
+    return WEDGE_OK;
+  }
   switch (U) {
     case 1: k_sample_close<1><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T); break;
     case 2: k_sample_close<2><<<(unsigned)tiles, kSampWG, 0, st>>>(A, T); break;
@@ -687,7 +707,8 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
                       uint64_t k_global, uint64_t seed, uint32_t graph_id, uint64_t* d_q,
                       uint64_t* d_probe_loads, wedge_sample_rec* d_dump, uint64_t dump_per_bin,
                       const SampleTuning* tuning, hipStream_t st,
-                      const uint64_t* d_hash = nullptr, int hash_bits = 0) {
+                      const uint64_t* d_hash = nullptr, int hash_bits = 0,
+                      bool draw_only = false) {
   if (n == 0) return set_error(WEDGE_ERANGE, "wedge_sample_close: n must be >= 1");
   if (max_bins == 0 || max_bins > 4096)
     return set_error(WEDGE_ERANGE, "wedge_sample_close: max_bins must be in [1, 4096]");
@@ -704,9 +725,10 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
   }
   if (k_global > (1ULL << 48))
     return set_error(WEDGE_ERANGE, "wedge_sample_close: k_global above 2^48");
-  if (total > 0 && (m == 0 || !d_col))
+  if (total > 0 && (m == 0 || (!d_col && !draw_only)))
     return set_error(WEDGE_EINVAL, "wedge_sample_close: samples requested of a graph without edges");
   if (d_dump && dump_per_bin == 0) d_dump = nullptr;
+  if (draw_only && !d_dump) return set_error(WEDGE_EINVAL, "sample_draws: no record buffer");
   int rc;
   if ((rc = fill<uint64_t>(d_q, ((uint64_t)max_bins + 1) * 4, 0, st))) return rc;
   if (d_probe_loads && (rc = fill<uint64_t>(d_probe_loads, 1, 0, st))) return rc;
@@ -735,6 +757,7 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
   A.closure = 1;
   A.hash = d_hash;
   A.hash_bits = hash_bits;
+  A.draw_only = draw_only ? 1 : 0;
   TaskTable T;
   T.graph_word = graph_id;
   T.ntask = 0;
@@ -755,6 +778,17 @@ int sample_close_impl(const uint64_t* d_rowptr, const uint32_t* d_col, uint32_t 
   }
   if (T.ntask > 0 && (rc = launch_tasks(A, T, t.U, st))) return rc;
   return WEDGE_OK;
+}
+
+int sample_draws(const uint64_t* d_rowptr, uint32_t n, uint64_t m, const void* d_index,
+                 uint32_t max_bins, const uint64_t* h_k, uint64_t k_global, uint64_t seed,
+                 wedge_sample_rec* d_rec, uint64_t stride, uint64_t* d_q, hipStream_t st) {
+  uint64_t kmax = k_global;
+  for (uint32_t b = 0; b < max_bins; ++b) kmax = h_k[b] > kmax ? h_k[b] : kmax;
+  if (stride < kmax) return set_error(WEDGE_ERANGE, "sample_draws: stride below a row's k");
+  const SampleTuning t{1, 0, 0};
+  return sample_close_impl(d_rowptr, nullptr, n, m, d_index, max_bins, h_k, k_global, seed, 0,
+                           d_q, nullptr, d_rec, stride, &t, st, nullptr, 0, true);
 }
 
 // ------------------------------------------------------- allocation form

@@ -49,6 +49,9 @@ struct SamplerCtx {
   // closure by lookup in the edge table of hash.hpp instead of the search
   const uint64_t* hash = nullptr;      // nullable
   int hash_bits = 0;
+  // draws only: the dump receives (centre, i, j, 0) of every sample and no
+  // adjacency is read (the streamed path resolves i, j later)
+  int draw_only = 0;
 };
 
 struct Task {
@@ -76,6 +79,15 @@ struct SampleTuning {
 
 SampleTuning default_tuning(uint64_t total_samples);
 void normalise(SampleTuning& t);
+
+// Draws only (see SamplerCtx::draw_only) of wedge_sample_close's samples:
+// record s of row r (bin r, or max_bins for the global stream) goes to
+// d_rec[r * stride + s] for every s < h_k[r] (k_global for the global row);
+// stride must be >= every row's k.  Only rowptr (degrees) and the index are
+// read; d_q ((max_bins + 1) * 4 uint64) is cleared and left at zero.
+int sample_draws(const uint64_t* d_rowptr, uint32_t n, uint64_t m, const void* d_index,
+                 uint32_t max_bins, const uint64_t* h_k, uint64_t k_global, uint64_t seed,
+                 wedge_sample_rec* d_rec, uint64_t stride, uint64_t* d_q, hipStream_t st);
 
 int launch_persistent(const SamplerCtx& A, const uint64_t* task_k, const uint64_t* tile_begin,
                       uint64_t nrows, unsigned long long* ticket, const SampleTuning& t,

@@ -166,6 +166,11 @@ SIGNATURES = {
     "wedge_sample_alloc": (ctypes.c_int, [_vp, _vp, _c_u32, _c_u64, _vp, _c_u32, _vp, _c_u64,
                                           _c_u64, _vp, _vp, _vp, _c_u64, _vp, ctypes.c_size_t,
                                           _vp]),
+    "wedge_sample_stream_workspace": (ctypes.c_size_t, [_c_u32, _c_u64, _c_u32, _vp, _c_u64,
+                                                        _c_u64, _c_u64]),
+    "wedge_sample_stream": (ctypes.c_int, [_vp, _vp, _c_u64, _c_u32, _c_u32, _c_u64, _c_u32, _vp,
+                                           _c_u64, _c_u64, _c_u64, _c_u64, _vp, _vp, _vp, _vp,
+                                           _c_u64, _vp, _vp, ctypes.c_size_t, _vp]),
     "wedge_closure_join_workspace": (ctypes.c_size_t, [_c_u64, _c_u64]),
     "wedge_closure_join": (ctypes.c_int, [_vp, _vp, _c_u64, _vp, _vp, _c_u64, _c_u64, _vp, _vp,
                                           ctypes.c_size_t, _vp]),
@@ -536,6 +541,59 @@ def closure_join(a: torch.Tensor, c: torch.Tensor, h_src: torch.Tensor, h_dst: t
                                     _vp(h_dst.data_ptr()), h_src.numel(), chunk_edges,
                                     _ptr(closed), _ptr(wbuf), wbuf.numel(), _stream(stream)))
     return closed[:k]
+
+
+@dataclass
+class StreamOut:
+    bins: BinIndex        # n_b, p_b (device and host); index is None (kept inside)
+    q: torch.Tensor       # int64[(max_bins + 1) * 4]
+    dump: torch.Tensor | None
+    h_k: np.ndarray       # samples per bin actually drawn (0 where p_b = 0)
+    k_global: int
+    m: int                # edges counted
+    rejected: int         # edges with an id >= n
+    rounds: int           # gather rounds
+    gathered: int         # edge ends gathered
+
+
+def sample_stream(h_src: torch.Tensor, h_dst: torch.Tensor, n: int, h_k: np.ndarray,
+                  k_global: int, seed: int, tau: int = 2, omega: int = 2, max_bins: int = 64,
+                  gather_cap: int | None = None, chunk_edges: int = 0, dump_per_bin: int = 0,
+                  device=None, ws: Workspace | None = None, stream=None) -> StreamOut:
+    """wedge_sample_stream: bins, samples and closure tests of a simple edge
+    list held in host memory (h_src, h_dst: int32 CPU tensors, preferably
+    pinned); no adjacency is built on the device.  Synchronises the stream.
+    gather_cap defaults to every edge end (one gather round)."""
+    _require_gpu()
+    assert not h_src.is_cuda and not h_dst.is_cuda and h_src.numel() == h_dst.numel()
+    dev = torch.device(device if device is not None else "cuda")
+    m_in = h_src.numel()
+    hk = np.ascontiguousarray(h_k, dtype=np.uint64)
+    assert hk.shape[0] == max_bins
+    cap = int(gather_cap) if gather_cap else max(2 * m_in, 1)
+    rows = max_bins + 1
+    n_b = torch.empty(max_bins, dtype=torch.int64, device=dev)
+    p_b = torch.empty(max_bins, dtype=torch.int64, device=dev)
+    q = torch.empty(rows * 4, dtype=torch.int64, device=dev)
+    dump = (torch.zeros((rows * dump_per_bin, 4), dtype=torch.int32, device=dev)
+            if dump_per_bin > 0 else None)
+    hk_p = hk.ctypes.data_as(ctypes.c_void_p)
+    need = int(lib().wedge_sample_stream_workspace(n, m_in, max_bins, hk_p, k_global, cap,
+                                                  chunk_edges))
+    wbuf = (ws or Workspace(dev)).get(need)
+    info = np.zeros(4, dtype=np.uint64)
+    _check(lib().wedge_sample_stream(_vp(h_src.data_ptr()), _vp(h_dst.data_ptr()), m_in, n, tau,
+                                     omega, max_bins, hk_p, k_global, seed, cap, chunk_edges,
+                                     _ptr(n_b), _ptr(p_b), _ptr(q), _ptr(dump), dump_per_bin,
+                                     info.ctypes.data_as(ctypes.c_void_p), _ptr(wbuf),
+                                     wbuf.numel(), _stream(stream)))
+    h_p_b = p_b.cpu().numpy().astype(np.uint64)
+    bi = BinIndex(n=n, m=int(info[0]), tau=tau, omega=omega, max_bins=max_bins, n_b=n_b, p_b=p_b,
+                  index=None, h_n_b=n_b.cpu().numpy().astype(np.uint64), h_p_b=h_p_b)
+    drawn = np.where(h_p_b > 0, hk, 0).astype(np.uint64)
+    kg = int(k_global) if int(h_p_b.sum()) > 0 else 0
+    return StreamOut(bins=bi, q=q, dump=dump, h_k=drawn, k_global=kg, m=int(info[0]),
+                     rejected=int(info[1]), rounds=int(info[2]), gathered=int(info[3]))
 
 
 @dataclass
