@@ -142,29 +142,95 @@ __global__ void k_os_flag(const unsigned long long* __restrict__ stalls,
   if (threadIdx.x == 0 && *stalls != 0) *target = value;
 }
 
-// base[p][d] = number of keys whose digit p is below d.
+// base[p][d] = number of keys whose digit p is below d; narrow[p] = 1 when
+// every digit of pass p holds fewer than 2^26 keys.
 __global__ __launch_bounds__(256) void k_os_base(const uint64_t* __restrict__ hist,
-                                                 uint64_t* __restrict__ base, OsShifts S) {
+                                                 uint64_t* __restrict__ base,
+                                                 uint32_t* __restrict__ narrow, OsShifts S) {
   __shared__ uint64_t s_w[4];
+  __shared__ uint32_t s_big[4];
   const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
   for (int p = 0; p < S.npass; ++p) {
     const int hp = S.mirror[p] >= 0 ? S.mirror[p] : p;
     const uint64_t c = hist[hp * 256 + d];
     const uint64_t incl = wave_incl_scan(c, lane);
+    const uint64_t big = __ballot(c > (uint64_t)kOs32Value);
     if (lane == 63) s_w[wave] = incl;
+    if (lane == 0) s_big[wave] = big != 0;
     __syncthreads();
     uint64_t before = 0;
     for (int w = 0; w < wave; ++w) before += s_w[w];
     base[p * 256 + d] = before + incl - c;
+    if (d == 0) narrow[p] = (s_big[0] | s_big[1] | s_big[2] | s_big[3]) ? 0u : 1u;
     __syncthreads();
   }
 }
 
-__device__ inline unsigned long long os_load(const unsigned long long* p) {
+template <class W>
+__device__ inline W os_load(const W* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void os_store(unsigned long long* p, unsigned long long v) {
+template <class W>
+__device__ inline void os_store(W* p, W v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Status word layouts: wide (pass tag in bits 56..63) and narrow (pass tag in
+// bits 28..31); `tag64` is the wide tag (pass + 1) << 56.
+template <class W>
+struct OsWord;
+template <>
+struct OsWord<unsigned long long> {
+  static constexpr unsigned long long kAgg = kOsAgg, kInc = kOsInc, kValue = kOsValue;
+  __device__ static unsigned long long tag(uint64_t tag64) { return tag64; }
+};
+template <>
+struct OsWord<unsigned int> {
+  static constexpr unsigned int kAgg = kOs32Agg, kInc = kOs32Inc, kValue = kOs32Value;
+  __device__ static unsigned int tag(uint64_t tag64) { return (unsigned int)(tag64 >> 28); }
+};
+
+// Exclusive prefix of digit d over the tiles before `tile`: walk back four
+// tiles per step (four status loads in flight), adding published counts in
+// order until an inclusive prefix is met.  A tile that has not published yet
+// is running (tiles are taken in ticket order) and publishes without waiting,
+// so the wait ends; the bound only guarantees that the wave exits (counted in
+// *stalls).
+template <class W>
+__device__ inline uint64_t os_lookback(const W* __restrict__ status, uint64_t tile, int d,
+                                       W tag, unsigned long long* stalls) {
+  using Wd = OsWord<W>;
+  uint64_t excl = 0;
+  uint64_t t = tile - 1;
+  uint32_t spins = 0;
+  bool done = false;
+  while (!done) {
+    const uint64_t nload = t + 1 < 4 ? t + 1 : 4;
+    W xs[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xs[j] = (uint64_t)j < nload ? os_load(status + (t - j) * 256 + d) : W(0);
+    uint64_t used = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (done || used != (uint64_t)j || (uint64_t)j >= nload) continue;
+      const W x = xs[j];
+      if ((W)(x & ~(Wd::kValue | Wd::kAgg | Wd::kInc)) != tag || (x & (Wd::kAgg | Wd::kInc)) == 0)
+        continue;
+      excl += x & Wd::kValue;
+      ++used;
+      if (x & Wd::kInc) done = true;
+    }
+    if (done) break;
+    t -= used;
+    if (used < nload) {
+      if (++spins > (1u << 24)) {
+        atomicAdd(stalls, 1ULL);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  return excl;
 }
 
 // One digit pass.  kEdges: the input keys are made from the edge list.
@@ -174,7 +240,10 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
                                                    int shift, uint64_t tag,
                                                    const uint64_t* __restrict__ base,
                                                    unsigned long long* __restrict__ status,
-                                                   unsigned long long* __restrict__ ticket) {
+                                                   unsigned int* __restrict__ status32,
+                                                   const uint32_t* __restrict__ narrow,
+                                                   unsigned long long* __restrict__ ticket,
+                                                   unsigned long long* __restrict__ stalls) {
   constexpr int kWaves = kOsWG / 64;
   __shared__ uint64_t s_keys[kOsTile];
   __shared__ uint32_t s_cnt[kWaves][256];
@@ -310,8 +379,12 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
     }
     cnt = run;
     // publish this tile's count before looking back
-    unsigned long long* mine = status + tile * 256 + d;
-    os_store(mine, tag | (tile == 0 ? kOsInc : kOsAgg) | (uint64_t)cnt);
+    if (*narrow)
+      os_store(status32 + tile * 256 + d,
+               OsWord<unsigned int>::tag(tag) | (tile == 0 ? kOs32Inc : kOs32Agg) | cnt);
+    else
+      os_store(status + tile * 256 + d,
+               (unsigned long long)(tag | (tile == 0 ? kOsInc : kOsAgg) | (uint64_t)cnt));
   }
   // tile-local exclusive offsets of the digits (waves 0..3 hold digits)
   {
@@ -331,40 +404,14 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
     const int d = tid;
     uint64_t excl = 0;
     if (tile > 0) {
-      // walk back four tiles per step (four status loads in flight), adding
-      // published counts in order until an inclusive prefix is met
-      uint64_t t = tile - 1;
-      uint32_t spins = 0;
-      bool done = false;
-      while (!done) {
-        const uint64_t nload = t + 1 < 4 ? t + 1 : 4;
-        unsigned long long xs[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) xs[j] = (uint64_t)j < nload ? os_load(status + (t - j) * 256 + d) : 0;
-        uint64_t used = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (done || used != (uint64_t)j || (uint64_t)j >= nload) continue;
-          const unsigned long long x = xs[j];
-          if ((x & ~(kOsValue | kOsAgg | kOsInc)) != tag || (x & (kOsAgg | kOsInc)) == 0) continue;
-          excl += x & kOsValue;
-          ++used;
-          if (x & kOsInc) done = true;
-        }
-        if (done) break;
-        t -= used;
-        if (used < nload) {
-          // tile t has not published yet: every earlier tile is running and
-          // publishes without waiting, so this ends; the bound only
-          // guarantees that the wave exits
-          if (++spins > (1u << 24)) {
-            atomicAdd(ticket + kOsMaxPasses, 1ULL);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
+      if (*narrow) {
+        const unsigned int tag32 = OsWord<unsigned int>::tag(tag);
+        excl = os_lookback<unsigned int>(status32, tile, d, tag32, stalls);
+        os_store(status32 + tile * 256 + d, tag32 | kOs32Inc | (unsigned int)(excl + cnt));
+      } else {
+        excl = os_lookback<unsigned long long>(status, tile, d, (unsigned long long)tag, stalls);
+        os_store(status + tile * 256 + d, (unsigned long long)(tag | kOsInc | (excl + cnt)));
       }
-      os_store(status + tile * 256 + d, tag | kOsInc | (excl + cnt));
     }
     s_glob[d] = base[d] + excl - s_tile_off[d];
   }
@@ -418,6 +465,7 @@ int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int
   }
   if ((rc = fill<uint64_t>(sc.hist, kOsMaxPasses * 256, 0, st))) return rc;
   if ((rc = fill<unsigned long long>(sc.status, nt * 256, 0, st))) return rc;
+  if ((rc = fill<unsigned int>(sc.status32, nt * 256, 0u, st))) return rc;
   {
     uint64_t blocks = ceil_div(E.m_in, (uint64_t)kOsWG * 16);
     if (blocks > 2048) blocks = 2048;
@@ -425,27 +473,31 @@ int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int
     k_os_hist_edges<<<(unsigned)blocks, kOsWG, 0, st>>>(E, S, sc.hist);
     WEDGE_LAUNCH_CHECK("k_os_hist_edges");
   }
-  k_os_base<<<1, 256, 0, st>>>(sc.hist, sc.base, S);
+  k_os_base<<<1, 256, 0, st>>>(sc.hist, sc.base, sc.narrow, S);
   WEDGE_LAUNCH_CHECK("k_os_base");
   uint64_t* src = nullptr;
   uint64_t* dst = a;
   for (int p = 0; p < npass; ++p) {
     const uint64_t tag = (uint64_t)(p + 1) << 56;
     const uint64_t* base = sc.base + p * 256;
+    const dim3 grid((unsigned)nt), block(kOsWG);
+    unsigned long long* stalls = sc.tickets + kOsMaxPasses;
     if (E.ks > 24) {
       if (p == 0)
-        k_os_pass<true><<<(unsigned)nt, kOsWG, 0, st>>>(E, nullptr, dst, N, shifts[p], tag, base,
-                                                         sc.status, sc.tickets + p);
+        k_os_pass<true><<<grid, block, 0, st>>>(E, nullptr, dst, N, shifts[p], tag, base, sc.status,
+                                                 sc.status32, sc.narrow + p, sc.tickets + p, stalls);
       else
-        k_os_pass<false><<<(unsigned)nt, kOsWG, 0, st>>>(E, src, dst, N, shifts[p], tag, base,
-                                                          sc.status, sc.tickets + p);
+        k_os_pass<false><<<grid, block, 0, st>>>(E, src, dst, N, shifts[p], tag, base, sc.status,
+                                                  sc.status32, sc.narrow + p, sc.tickets + p, stalls);
     } else {
       if (p == 0)
-        k_os_pass<true, true><<<(unsigned)nt, kOsWG, 0, st>>>(E, nullptr, dst, N, shifts[p], tag,
-                                                               base, sc.status, sc.tickets + p);
+        k_os_pass<true, true><<<grid, block, 0, st>>>(E, nullptr, dst, N, shifts[p], tag, base,
+                                                       sc.status, sc.status32, sc.narrow + p,
+                                                       sc.tickets + p, stalls);
       else
-        k_os_pass<false, true><<<(unsigned)nt, kOsWG, 0, st>>>(E, src, dst, N, shifts[p], tag,
-                                                                base, sc.status, sc.tickets + p);
+        k_os_pass<false, true><<<grid, block, 0, st>>>(E, src, dst, N, shifts[p], tag, base,
+                                                        sc.status, sc.status32, sc.narrow + p,
+                                                        sc.tickets + p, stalls);
     }
     WEDGE_LAUNCH_CHECK("k_os_pass");
     src = dst;
@@ -469,13 +521,14 @@ int onesweep_sort_keys(uint64_t* a, uint64_t* b, uint64_t N, const int* shifts, 
   }
   if ((rc = fill<uint64_t>(sc.hist, kOsMaxPasses * 256, 0, st))) return rc;
   if ((rc = fill<unsigned long long>(sc.status, nt * 256, 0, st))) return rc;
+  if ((rc = fill<unsigned int>(sc.status32, nt * 256, 0u, st))) return rc;
   {
     uint64_t blocks = ceil_div(N, (uint64_t)kOsWG * 16);
     if (blocks > 2048) blocks = 2048;
     k_os_hist_keys<<<(unsigned)blocks, kOsWG, 0, st>>>(a, N, S, sc.hist);
     WEDGE_LAUNCH_CHECK("k_os_hist_keys");
   }
-  k_os_base<<<1, 256, 0, st>>>(sc.hist, sc.base, S);
+  k_os_base<<<1, 256, 0, st>>>(sc.hist, sc.base, sc.narrow, S);
   WEDGE_LAUNCH_CHECK("k_os_base");
   const EdgeSource none{nullptr, nullptr, 0, 0, nullptr, nullptr, 1, nullptr};
   uint64_t* src = a;
@@ -483,8 +536,9 @@ int onesweep_sort_keys(uint64_t* a, uint64_t* b, uint64_t N, const int* shifts, 
   for (int p = 0; p < npass; ++p) {
     const uint64_t tag = (uint64_t)(p + 1) << 56;
     k_os_pass<false><<<(unsigned)nt, kOsWG, 0, st>>>(none, src, dst, N, shifts[p], tag,
-                                                      sc.base + p * 256, sc.status,
-                                                      sc.tickets + p);
+                                                      sc.base + p * 256, sc.status, sc.status32,
+                                                      sc.narrow + p, sc.tickets + p,
+                                                      sc.tickets + kOsMaxPasses);
     WEDGE_LAUNCH_CHECK("k_os_pass");
     uint64_t* t = src;
     src = dst;

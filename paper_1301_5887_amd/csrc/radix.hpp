@@ -27,24 +27,32 @@ constexpr int kOsMaxPasses = 8;
 constexpr uint64_t kOsAgg = 1ULL << 54;
 constexpr uint64_t kOsInc = 2ULL << 54;
 constexpr uint64_t kOsValue = (1ULL << 54) - 1;
+// Narrow status word, used by a pass whose every digit holds fewer than 2^26
+// keys (so every count and prefix fits): pass tag (4 bits) | flag (2) |
+// count (26).  It halves the look-back's status traffic.
+constexpr uint32_t kOs32Agg = 1u << 26;
+constexpr uint32_t kOs32Inc = 2u << 26;
+constexpr uint32_t kOs32Value = (1u << 26) - 1;
 
 struct OsScratch {
   uint64_t* hist;                // [kOsMaxPasses][256] global digit counts
   uint64_t* base;                // [kOsMaxPasses][256] exclusive prefix over digits
   unsigned long long* tickets;   // [kOsMaxPasses] per pass, then a count of stalled look-backs
+  uint32_t* narrow;              // [kOsMaxPasses] 1: the pass uses the narrow status words
   unsigned long long* status;    // [tiles][256]
+  unsigned int* status32;        // [tiles][256], narrow passes
 };
 
 inline uint64_t os_tiles(uint64_t N) { return ceil_div(N, kOsTile); }
 inline size_t os_scratch_bytes(uint64_t N) {
   uint64_t t = os_tiles(N);
   if (t == 0) t = 1;
-  return round_up(kOsMaxPasses * 256 * 8, 256) * 2 + 256 + round_up(t * 256 * 8, 256);
+  return round_up(kOsMaxPasses * 256 * 8, 256) * 2 + 256 + 256 + round_up(t * 256 * 8, 256) +
+         round_up(t * 256 * 4, 256);
 }
 inline OsScratch os_scratch(void* p, uint64_t N) {
   uint64_t t = os_tiles(N);
   if (t == 0) t = 1;
-  (void)t;
   char* c = (char*)p;
   OsScratch s;
   s.hist = (uint64_t*)c;
@@ -53,7 +61,11 @@ inline OsScratch os_scratch(void* p, uint64_t N) {
   c += round_up(kOsMaxPasses * 256 * 8, 256);
   s.tickets = (unsigned long long*)c;
   c += 256;
+  s.narrow = (uint32_t*)c;
+  c += 256;
   s.status = (unsigned long long*)c;
+  c += round_up(t * 256 * 8, 256);
+  s.status32 = (unsigned int*)c;
   return s;
 }
 

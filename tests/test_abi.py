@@ -414,3 +414,58 @@ def test_sample_alloc_validation():
     assert L.wedge_sample_alloc(z, z, 10, 5, z, 8, hk, 0, 1, z, tot, None, 0, z, 16, None) == -3
     hk[3] = (1 << 48) + 1
     assert L.wedge_sample_alloc(z, z, 10, 5, z, 8, hk, 0, 1, z, tot, None, 0, z, big, None) == -2
+
+
+def test_sample_stream_validation():
+    L = W.lib()
+    z = ctypes.c_void_p(256)
+    hk = (ctypes.c_uint64 * 8)(*([100] * 8))
+    big = 1 << 34
+    ws = L.wedge_sample_stream_workspace(1000, 5000, 8, hk, 100, 10_000, 0)
+    assert ws > 0
+    # more samples, a larger gather capacity or longer chunks need more workspace
+    hk2 = (ctypes.c_uint64 * 8)(*([200] * 8))
+    assert L.wedge_sample_stream_workspace(1000, 5000, 8, hk2, 100, 10_000, 0) > ws
+    assert L.wedge_sample_stream_workspace(1000, 5000, 8, hk, 100, 20_000, 0) > ws
+    assert L.wedge_sample_stream_workspace(1000, 5000, 8, hk, 100, 10_000, 1 << 25) > ws
+    assert L.wedge_sample_stream_workspace(1000, 5000, 0, hk, 100, 10_000, 0) == 0
+    args = lambda **kw: dict(dict(src=z, dst=z, m=5000, n=1000, tau=2, omega=2, B=8, hk=hk,
+                                  kg=100, cap=10_000, nb=z, pb=z, q=z, ws=z, wsb=big), **kw)
+
+    def call(a):
+        return L.wedge_sample_stream(a["src"], a["dst"], a["m"], a["n"], a["tau"], a["omega"],
+                                     a["B"], a["hk"], a["kg"], 1, a["cap"], 0, a["nb"], a["pb"],
+                                     a["q"], None, 0, None, a["ws"], a["wsb"], None)
+
+    assert call(args(n=0)) == ERANGE
+    assert call(args(tau=0)) == ERANGE
+    assert call(args(omega=1)) == ERANGE
+    assert call(args(B=0)) == ERANGE
+    assert call(args(src=None)) == EINVAL
+    assert call(args(q=None)) == EINVAL
+    assert call(args(ws=ctypes.c_void_p(257))) == EINVAL
+    assert call(args(cap=0)) == ERANGE
+    assert call(args(wsb=16)) == EWORKSPACE
+    hk[2] = (1 << 40) + 1
+    assert call(args()) == ERANGE
+    assert b"k[2]" in L.wedge_last_error()
+
+
+def test_edge_hash_host_checks():
+    L = W.lib()
+    z = ctypes.c_void_p(256)
+    # least bits >= 4 with 2^bits >= 2m
+    assert L.wedge_edge_hash_bits(0) == 4
+    assert L.wedge_edge_hash_bits(8) == 4
+    assert L.wedge_edge_hash_bits(9) == 5
+    assert L.wedge_edge_hash_bits(260_385_838) == 29
+    assert L.wedge_edge_hash_bits(4_236_149_362) == 33
+    assert L.wedge_edge_hash_build(z, z, 0, 10, z, 5, z, None) == ERANGE
+    assert L.wedge_edge_hash_build(z, z, 100, 10, z, 4, z, None) == ERANGE   # 2^4 < 2m
+    assert L.wedge_edge_hash_build(z, z, 100, 10, None, 5, z, None) == EINVAL
+    hk = (ctypes.c_uint64 * 8)()
+    q = ctypes.c_void_p(512)
+    assert L.wedge_sample_close_hashed(z, z, 100, 10, z, 8, hk, 0, 1, 0, q, None, None, 0,
+                                       None, 5, None) == EINVAL
+    assert L.wedge_sample_close_hashed(z, z, 100, 10, z, 8, hk, 0, 1, 0, q, None, None, 0,
+                                       z, 4, None) == ERANGE
