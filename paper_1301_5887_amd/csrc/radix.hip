@@ -190,9 +190,12 @@ struct OsWord<unsigned int> {
   __device__ static unsigned int tag(uint64_t tag64) { return (unsigned int)(tag64 >> 28); }
 };
 
-// Exclusive prefix of digit d over the tiles before `tile`: walk back four
-// tiles per step (four status loads in flight), adding published counts in
-// order until an inclusive prefix is met.  A tile that has not published yet
+// Tiles a look-back step inspects (status loads in flight per digit).
+constexpr int kOsLookTiles = 4;
+
+// Exclusive prefix of digit d over the tiles before `tile`: walk back
+// kOsLookTiles tiles per step (that many status loads in flight), adding
+// published counts in order until an inclusive prefix is met.  A tile that has not published yet
 // is running (tiles are taken in ticket order) and publishes without waiting,
 // so the wait ends; the bound only guarantees that the wave exits (counted in
 // *stalls).
@@ -205,13 +208,14 @@ __device__ inline uint64_t os_lookback(const W* __restrict__ status, uint64_t ti
   uint32_t spins = 0;
   bool done = false;
   while (!done) {
-    const uint64_t nload = t + 1 < 4 ? t + 1 : 4;
-    W xs[4];
+    const uint64_t nload = t + 1 < (uint64_t)kOsLookTiles ? t + 1 : (uint64_t)kOsLookTiles;
+    W xs[kOsLookTiles];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) xs[j] = (uint64_t)j < nload ? os_load(status + (t - j) * 256 + d) : W(0);
+    for (int j = 0; j < kOsLookTiles; ++j)
+      xs[j] = (uint64_t)j < nload ? os_load(status + (t - j) * 256 + d) : W(0);
     uint64_t used = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kOsLookTiles; ++j) {
       if (done || used != (uint64_t)j || (uint64_t)j >= nload) continue;
       const W x = xs[j];
       if ((W)(x & ~(Wd::kValue | Wd::kAgg | Wd::kInc)) != tag || (x & (Wd::kAgg | Wd::kInc)) == 0)
