@@ -299,6 +299,12 @@ def plain_workload(args, torch, n, src, dst, workload):
 
     roofline = sampler_roofline(args, K, q_step, probes, avg["sample_close"])
     roofline_csr = csr_roofline(n, m_in, m, avg["build_csr"])
+    stream = stream_copy_rate(torch, dev)
+    roofline["stream_copy_GBps"] = roofline_csr["stream_copy_GBps"] = stream
+    if roofline.get("traffic_GBps_at_this_launch_time"):
+        roofline["frac_of_stream_copy"] = round(roofline["traffic_GBps_at_this_launch_time"] /
+                                                stream, 4)
+    roofline_csr["frac_sort_of_stream_copy"] = round(roofline_csr["achieved_sort"] / stream, 4)
 
     if args.calibrate_copy_gib > 0:
         nbytes = int(args.calibrate_copy_gib * (1 << 30))
@@ -412,6 +418,29 @@ def sampler_roofline(args, K, qh, probes, t_ms):
                 if key in pmc:
                     out[key] = pmc[key]
     return out
+
+
+def stream_copy_rate(torch, dev, gib: int = 4, reps: int = 5) -> float:
+    """Achieved streaming bandwidth of this GPU: a device-to-device copy of
+    `gib` GiB (read + write bytes per second, median of `reps` HIP-event timed
+    copies on the current stream), the practical ceiling beside the 8 TB/s
+    vendor peak."""
+    nbytes = gib << 30
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device=dev).fill_(1)
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    b.copy_(a)
+    times = []
+    for _ in range(reps):
+        ev[0].record(st)
+        b.copy_(a)
+        ev[1].record(st)
+        torch.cuda.synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / (float(np.median(times)) / 1e3) / 1e9, 1)
 
 
 def csr_roofline(n, m_in, m, t_ms):
