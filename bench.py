@@ -299,12 +299,15 @@ def plain_workload(args, torch, n, src, dst, workload):
 
     roofline = sampler_roofline(args, K, q_step, probes, avg["sample_close"])
     roofline_csr = csr_roofline(n, m_in, m, avg["build_csr"])
-    stream = stream_copy_rate(torch, dev)
+    # the streaming ceiling (left out of counter runs, whose calibration copy
+    # must be the only large copy)
+    stream = stream_copy_rate(torch, dev) if args.calibrate_copy_gib <= 0 else None
     roofline["stream_copy_GBps"] = roofline_csr["stream_copy_GBps"] = stream
-    if roofline.get("traffic_GBps_at_this_launch_time"):
+    if stream and roofline.get("traffic_GBps_at_this_launch_time"):
         roofline["frac_of_stream_copy"] = round(roofline["traffic_GBps_at_this_launch_time"] /
                                                 stream, 4)
-    roofline_csr["frac_sort_of_stream_copy"] = round(roofline_csr["achieved_sort"] / stream, 4)
+    if stream:
+        roofline_csr["frac_sort_of_stream_copy"] = round(roofline_csr["achieved_sort"] / stream, 4)
 
     if args.calibrate_copy_gib > 0:
         nbytes = int(args.calibrate_copy_gib * (1 << 30))

@@ -25,5 +25,5 @@ def test_profile_options_exist():
     assert r.returncode == 0
     for opt in ("--steps", "--warmup", "--no-cv", "--no-cpu-baseline", "--triangles",
                 "--calibrate-copy-gib", "--pmc-summarize", "--graph", "--scale", "--join",
-                "--alloc-seeds"):
+                "--alloc-seeds", "--stream", "--no-hash", "--no-batch", "--calibrate-gather"):
         assert opt in r.stdout, opt
