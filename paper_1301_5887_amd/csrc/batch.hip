@@ -45,7 +45,7 @@ static size_t batch_layout(const wedge_batch_desc* d, BatchLayout* L, void* base
   char* c = (char*)base;
   size_t off = 0;
   auto take = [&](size_t bytes) {
-    char* p = c + off;
+    char* p = c ? c + off : nullptr;  // sizing calls pass no base
     off += round_up(bytes ? bytes : 1, 256);
     return (void*)p;
   };

@@ -75,7 +75,7 @@ static size_t census_layout(uint32_t max_bins, uint64_t n, uint64_t class_cap, C
   char* c = (char*)base;
   size_t off = 0;
   auto take = [&](size_t bytes) {
-    char* p = c + off;
+    char* p = c ? c + off : nullptr;  // sizing calls pass no base
     off += round_up(bytes, 256);
     return (void*)p;
   };

@@ -94,7 +94,7 @@ static size_t join_layout(uint64_t k, uint64_t chunk, JoinWorkspace* w, void* ba
   char* c = (char*)base;
   size_t off = 0;
   auto take = [&](size_t bytes) {
-    char* p = c + off;
+    char* p = c ? c + off : nullptr;  // sizing calls pass no base
     off += round_up(bytes, 256);
     return p;
   };

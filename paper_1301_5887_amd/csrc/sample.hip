@@ -1124,7 +1124,7 @@ static size_t alloc_layout(uint32_t n, uint32_t max_bins, AllocWorkspace* w, voi
   const uint64_t rows = (uint64_t)max_bins + 1;
   const uint64_t N = 2 * (uint64_t)n + 1;
   auto take = [&](size_t bytes) {
-    char* p = c + off;
+    char* p = c ? c + off : nullptr;  // sizing calls pass no base
     off += round_up(bytes, 256);
     return p;
   };

@@ -15,7 +15,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libwedge.so")
+# WEDGE_LIB selects another build of the same library (the host-sanitizer
+# build of the checks); by default the in-tree libwedge.so.
+LIB_PATH = os.environ.get("WEDGE_LIB") or os.path.join(_HERE, "libwedge.so")
 
 _c_u64 = ctypes.c_uint64
 _c_u32 = ctypes.c_uint32
