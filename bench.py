@@ -352,7 +352,7 @@ def plain_workload(args, torch, n, src, dst, workload):
                "dump": so.dump.view(B + 1, DUMP_PER_ROW, 4).cpu().numpy().view(np.uint32),
                "n_b": h_nb.numpy().view(np.uint64).copy(),
                "p_b": h_pb.numpy().view(np.uint64).copy(), "rowptr": rowptr, "col": col,
-               "m": int(m)}
+               "m": int(m), "est": [est.glob[x] for x in ("c", "t", "c_global", "t_global")]}
         del so
         cpu = cpu_baseline(args, torch, src, dst, n, B, k, hk, kg, workload, gpu)
 
@@ -751,6 +751,11 @@ def cpu_baseline(args, torch, src, dst, n, B, k, hk, kg, workload, gpu):
             samples_match = False
     log(f"[bench] oracle sampled {Ks} wedges in {dt:.2f}s ({threads} threads): counts match="
         f"{counts_match}, first {DUMP_PER_ROW} samples of every row match={samples_match}")
+    # the estimate phase (Alg. phase4c, Eq. global_est) on the oracle's counts
+    t1 = time.perf_counter()
+    _, glob = O.estimate(p_b, s.q, kb, kgo, args.delta)
+    t_est = time.perf_counter() - t1
+    est_match = all(abs(a - b) <= 1e-12 * max(1.0, abs(b)) for a, b in zip(gpu["est"], glob))
     # one thread, the first samples of every row (the thread count is
     # process-wide, so it is set back afterwards)
     k1 = np.minimum(kb, np.uint64(args.cpu_one_thread_per_row)).astype(np.uint64)
@@ -772,7 +777,9 @@ def cpu_baseline(args, torch, src, dst, n, B, k, hk, kg, workload, gpu):
                            "sample": f"first {args.cpu_one_thread_per_row} samples of every row"},
             "csr_seconds": round(t_graph, 3), "csr_threads": threads,
             "bins_seconds": round(t_bins, 3),
+            "estimate_seconds": round(t_est, 6),
             "host": hi,
+            "estimates_match": est_match,
             "gpu_counts_match": counts_match, "csr_match": csr_match, "bins_match": bins_match,
             "sample_counts_match": rows_match, "samples_match": samples_match,
             "samples_compared": samples_compared, "one_thread_rows_match": one_match}
