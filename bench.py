@@ -625,7 +625,7 @@ def stream_leg(args, torch, W, g, bi, k, kg, q_step):
         runs.append(time.perf_counter() - t0)
     q = W.to_host_u64(out.q).reshape(B + 1, 4)
     K = int(out.h_k.sum()) + out.k_global
-    passes = 3 + out.rounds
+    passes = 2 + out.rounds   # the degree pass, one per gather round, the join
     res = {"edges": m, "host_bytes": 8 * m, "gather_cap": cap, "rounds": out.rounds,
            "edge_ends_gathered": out.gathered, "edge_passes": passes,
            "seconds": round(runs[-1], 4), "seconds_first_run": round(runs[0], 4),

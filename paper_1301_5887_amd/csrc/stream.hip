@@ -113,23 +113,64 @@ __global__ void k_next_cut(const uint64_t* __restrict__ pre, uint32_t n, uint32_
 }
 
 // Keys u << 32 | w of every edge end u that is marked and in [lo, hi), both
-// orientations of each edge.
-__global__ void k_stream_gather(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
-                                uint64_t ne, uint32_t n, const uint8_t* __restrict__ flag,
-                                uint32_t lo, uint32_t hi, uint64_t* __restrict__ keys,
-                                unsigned long long* __restrict__ cursor, uint64_t cap) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += stride) {
-    const uint32_t u = src[i], w = dst[i];
-    if (u >= n || w >= n || u == w) continue;
-    if (u >= lo && u < hi && flag[u]) {
-      const uint64_t at = atomicAdd(cursor, 1ULL);
-      if (at < cap) keys[at] = ((uint64_t)u << 32) | w;
+// orientations of each edge.  A workgroup takes kGatherEdges edges per step
+// (kGatherPer per thread, strided for coalesced loads) and reserves the slots
+// of all its keys with one atomic add on the cursor, placing each thread's
+// keys by a prefix over lanes and waves: adds on the one cursor word are
+// serialised, so they are kept to one per kGatherEdges edges.
+constexpr int kGatherWG = 256;
+constexpr int kGatherPer = 4;
+constexpr uint64_t kGatherEdges = (uint64_t)kGatherWG * kGatherPer;
+
+__global__ __launch_bounds__(kGatherWG) void k_stream_gather(
+    const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst, uint64_t ne, uint32_t n,
+    const uint8_t* __restrict__ flag, uint32_t lo, uint32_t hi, uint64_t* __restrict__ keys,
+    unsigned long long* __restrict__ cursor, uint64_t cap) {
+  constexpr int kWaves = kGatherWG / 64;
+  __shared__ uint32_t s_wave[kWaves];
+  __shared__ unsigned long long s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (uint64_t e0 = (uint64_t)blockIdx.x * kGatherEdges; e0 < ne;
+       e0 += (uint64_t)gridDim.x * kGatherEdges) {
+    uint32_t u[kGatherPer], w[kGatherPer], take = 0, cnt = 0;  // take: bit 2j u, bit 2j+1 w
+#pragma unroll
+    for (int j = 0; j < kGatherPer; ++j) {
+      const uint64_t i = e0 + (uint64_t)j * kGatherWG + tid;
+      u[j] = w[j] = 0;
+      if (i < ne) {
+        u[j] = src[i];
+        w[j] = dst[i];
+        if (u[j] < n && w[j] < n && u[j] != w[j]) {
+          if (u[j] >= lo && u[j] < hi && flag[u[j]]) take |= 1u << (2 * j);
+          if (w[j] >= lo && w[j] < hi && flag[w[j]]) take |= 2u << (2 * j);
+        }
+      }
     }
-    if (w >= lo && w < hi && flag[w]) {
-      const uint64_t at = atomicAdd(cursor, 1ULL);
-      if (at < cap) keys[at] = ((uint64_t)w << 32) | u;
+    cnt = __popc(take);
+    const uint32_t incl = wave_incl_scan<uint32_t>(cnt, lane);
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t total = 0;
+#pragma unroll
+      for (int x = 0; x < kWaves; ++x) total += s_wave[x];
+      s_base = total ? atomicAdd(cursor, (unsigned long long)total) : 0ULL;
     }
+    __syncthreads();
+    uint64_t at = s_base + incl - cnt;
+    for (int x = 0; x < wave; ++x) at += s_wave[x];
+#pragma unroll
+    for (int j = 0; j < kGatherPer; ++j) {
+      if ((take >> (2 * j)) & 1u) {
+        if (at < cap) keys[at] = ((uint64_t)u[j] << 32) | w[j];
+        ++at;
+      }
+      if ((take >> (2 * j + 1)) & 1u) {
+        if (at < cap) keys[at] = ((uint64_t)w[j] << 32) | u[j];
+        ++at;
+      }
+    }
+    __syncthreads();  // s_wave and s_base are rewritten by the next step
   }
 }
 
@@ -468,7 +509,9 @@ extern "C" int wedge_sample_stream(const uint32_t* h_src, const uint32_t* h_dst,
       if ((rc = fill<unsigned long long>(L.ctr + kCtrCursor, 1, 0ULL, st))) return rc;
       rc = stream_edges(h_src, h_dst, m_in, chunk, L.buf, st,
                         [&](const uint32_t* src, const uint32_t* dst, uint64_t ne) -> int {
-                          k_stream_gather<<<grid_for(ne, 4096), 256, 0, st>>>(
+                          uint64_t groups = ceil_div(ne, kGatherEdges);
+                          if (groups > 4096) groups = 4096;
+                          k_stream_gather<<<(unsigned)groups, kGatherWG, 0, st>>>(
                               src, dst, ne, n, L.flag, lo, hi, L.keys_a, L.ctr + kCtrCursor,
                               gather_cap);
                           WEDGE_LAUNCH_CHECK("k_stream_gather");
