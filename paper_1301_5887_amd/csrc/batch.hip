@@ -418,8 +418,13 @@ extern "C" int wedge_batch_autotune(const wedge_batch_desc* d, const wedge_launc
       unsigned int diff = 0;
       if ((rc = fill<unsigned int>(d_diff, 1, 0u, st))) break;
       k_compare_u64<<<256, 256, 0, st>>>(d_q_ref, d_q_try, nq, d_diff);
-      hipMemcpyAsync(&diff, d_diff, sizeof(diff), hipMemcpyDeviceToHost, st);
-      hipStreamSynchronize(st);
+      const hipError_t e1 = hipMemcpyAsync(&diff, d_diff, sizeof(diff), hipMemcpyDeviceToHost, st);
+      const hipError_t e2 = hipStreamSynchronize(st);  // also when the copy was refused
+      if (e1 != hipSuccess || e2 != hipSuccess) {
+        rc = set_error(WEDGE_EHIP, "wedge_batch_autotune: reading the comparison failed: %s",
+                       hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        break;
+      }
       if (diff) {
         rc = set_error(WEDGE_EINVAL, "wedge_batch_autotune: counts of candidate %d differ", c);
         break;

@@ -364,10 +364,14 @@ extern "C" int wedge_cv_train(const uint64_t* d_rowptr, const uint32_t* d_col, u
   if ((rc = wedge_cv_moments(hold, g, nrows, n_hold, n_hold, nullptr, mom, stream))) return rc;
   std::vector<int64_t> hm((size_t)nrows * 5);
   float hl = 0.0f;
-  WEDGE_HIP_TRY(hipMemcpyAsync(hm.data(), mom, hm.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
-                               st));
-  WEDGE_HIP_TRY(hipMemcpyAsync(&hl, loss, sizeof(float), hipMemcpyDeviceToHost, st));
-  WEDGE_HIP_TRY(hipStreamSynchronize(st));
+  // both copies land in host memory of this frame, so the stream is drained
+  // before any return
+  hipError_t e = hipMemcpyAsync(hm.data(), mom, hm.size() * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hl, loss, sizeof(float), hipMemcpyDeviceToHost, st);
+  const hipError_t es = hipStreamSynchronize(st);
+  WEDGE_HIP_TRY(e);
+  WEDGE_HIP_TRY(es);
   if (h_mom) memcpy(h_mom, hm.data(), hm.size() * sizeof(int64_t));
   if (h_loss) *h_loss = hl;
   return wedge_cv_fit(hm.data(), nrows, eps, delta, h_fit);

@@ -465,6 +465,8 @@ extern "C" int wedge_sample_stream(const uint32_t* h_src, const uint32_t* h_dst,
     WEDGE_HIP_TRY(hipMemcpyAsync(L.rows_k, rk.data(), nrows * 8, hipMemcpyHostToDevice, st));
     WEDGE_HIP_TRY(hipMemcpyAsync(L.rows_off, roff.data(), nrows * 8, hipMemcpyHostToDevice, st));
     WEDGE_HIP_TRY(hipMemcpyAsync(L.rows_bin, rbin.data(), nrows * 4, hipMemcpyHostToDevice, st));
+    // the host vectors must outlive the copies, also on an early error return
+    WEDGE_HIP_TRY(hipStreamSynchronize(st));
     const DrawRows R{L.rows_k, L.rows_off, L.rows_bin, nrows, z.kmax};
     const uint64_t kmax_used = *std::max_element(rk.begin(), rk.end());
     const dim3 rgrid(grid_for(kmax_used, 2048), nrows);
@@ -504,8 +506,8 @@ extern "C" int wedge_sample_stream(const uint32_t* h_src, const uint32_t* h_dst,
       const uint32_t hi = (uint32_t)cut;
       if (hi <= lo) return set_error(WEDGE_EHIP, "wedge_sample_stream: empty gather range");
       uint64_t want[2] = {0, 0};
-      WEDGE_HIP_TRY(hipMemcpyAsync(&want[0], L.pre + lo, 8, hipMemcpyDeviceToHost, st));
-      WEDGE_HIP_TRY(hipMemcpyAsync(&want[1], L.pre + hi, 8, hipMemcpyDeviceToHost, st));
+      if ((rc = read_back(&want[0], L.pre + lo, 1, st))) return rc;
+      if ((rc = read_back(&want[1], L.pre + hi, 1, st))) return rc;
       if ((rc = fill<unsigned long long>(L.ctr + kCtrCursor, 1, 0ULL, st))) return rc;
       rc = stream_edges(h_src, h_dst, m_in, chunk, L.buf, st,
                         [&](const uint32_t* src, const uint32_t* dst, uint64_t ne) -> int {
