@@ -237,6 +237,57 @@ def test_csr_group_overflowing_a_tile():
     assert r["og"].degrees()[12345] >= 190
 
 
+def csr_only(src, dst, n):
+    """The adjacency of one edge list on the GPU against the oracle's."""
+    print(f"[parity] csr n={n} m_in={len(src)}", flush=True)
+    g = W.build_csr(dev(src), dev(dst), n)
+    torch.cuda.synchronize()
+    og = O.build_graph(src, dst, n)
+    assert g.m == og.m and g.rejected == og.rejected
+    assert (W.to_host_u64(g.rowptr) == og.rowptr).all()
+    assert (g.col[: 2 * g.m].cpu().numpy().view(np.uint32) == og.col).all()
+    return og
+
+
+@pytest.mark.parametrize("n", [1 << 20, (1 << 24) - 3, (1 << 26) + 5])
+def test_csr_low_byte_groups_of_every_size(n):
+    """Runs of keys equal above their low byte (one source, 256 consecutive
+    destination ids), which only the first digit pass orders: runs of 1 to
+    300 keys, with repeats and a self-loop in some, in both key layouts, many
+    of them in one sort or dedup tile and straddling tile ends."""
+    rng = np.random.default_rng(n & 0xFFFF)
+    srcs, dsts = [], []
+    for h in range(400):
+        hub = int(rng.integers(0, n))
+        lo = int(rng.integers(0, n - WINDOW)) & ~0xFF
+        size = int(rng.choice([1, 2, 31, 32, 33, 34, 64, 200, 256, 300]))
+        nb = (lo + rng.integers(0, WINDOW, size)).astype(np.uint32)
+        srcs.append(np.full(size, hub, np.uint32))
+        dsts.append(nb)
+        if h % 7 == 0:      # a self-loop inside the group when the hub is in the window
+            srcs.append(np.array([hub], np.uint32))
+            dsts.append(np.array([hub], np.uint32))
+    src, dst = gen.rmat(20, 200_000, 31)
+    src = np.concatenate([src % np.uint32(n)] + srcs).astype(np.uint32)
+    dst = np.concatenate([dst % np.uint32(n)] + dsts).astype(np.uint32)
+    perm = rng.permutation(len(src))
+    csr_only(src[perm], dst[perm], n)
+
+
+@pytest.mark.parametrize("n", [2, 200, 256, 257, 600])
+def test_csr_ids_within_one_low_byte(n):
+    """Every destination id in the low byte (n <= 256: one digit pass orders
+    a whole row), or one bit above it, with rows of thousands of repeated
+    keys spanning several sort and dedup tiles."""
+    rng = np.random.default_rng(n)
+    m_in = 60_000
+    src = rng.integers(0, n, m_in).astype(np.uint32)
+    dst = rng.integers(0, n, m_in).astype(np.uint32)
+    src[:50] = dst[:50]
+    r = run_both(src, dst, n, B=24, k=2_000, seed=n)
+    check_all(r)
+
+
 def test_bter_community_graph():
     """BTER-like community graph (dense blocks of similar degree, Chung-Lu
     excess): CSR, bins, every dumped sample and the estimates."""
