@@ -8,8 +8,11 @@
 // Because BinId is monotone in the degree, each bin of each graph is then
 // one contiguous run, and within it vertices of equal degree form a "class"
 // of equally likely centres: the sampler keeps one cumulative wedge count per
-// (graph, distinct degree) instead of one per vertex.  A single graph is the
-// case G = 1 (no graph digits).
+// (graph, distinct degree) instead of one per vertex.  For a single graph
+// (G = 1) one stable pass by min(degree, 255) reads the row starts in id
+// order and writes the order of every vertex of degree < 255 and its row
+// start directly; only the vertices of higher degree (at most 2m / 255) are
+// sorted by their degree digits, as keys.
 #include <math.h>
 
 #include "common.hpp"
@@ -94,6 +97,116 @@ __global__ void k_deg_keys(const uint64_t* __restrict__ rowptr, uint32_t n,
     keys[v] = key;
   }
 }
+
+// One graph: degree code and row word per vertex (as k_deg_keys) and the
+// counts of min(degree, kRowsDirect).  Lane group lane / 8 adds to its own
+// copy of the counters (most vertices share a few small degrees).
+constexpr int kDegCopies = 8;
+__global__ __launch_bounds__(256) void k_deg_hist(const uint64_t* __restrict__ rowptr, uint32_t n,
+                                                  uint8_t* __restrict__ vcode,
+                                                  uint64_t* __restrict__ vmeta,
+                                                  uint64_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[256][kDegCopies];
+  const int tid = threadIdx.x;
+  const int cp = (tid & 63) >> 3;
+  for (int i = tid; i < 256 * kDegCopies; i += 256) (&s_h[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + tid; v < n; v += stride) {
+    const uint64_t r0 = rowptr[v], d = rowptr[v + 1] - r0;
+    vcode[v] = degree_code(d);
+    vmeta[v] = r0 | ((uint64_t)degree_code(d) << 56);
+    if (v == (uint64_t)n - 1) vmeta[n] = rowptr[n];
+    atomicAdd(&s_h[d < kRowsDirect ? d : kRowsDirect][cp], 1u);
+  }
+  __syncthreads();
+  uint64_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kDegCopies; ++j) c += s_h[tid][j];
+  if (c) atomicAdd((unsigned long long*)&hist[tid], (unsigned long long)c);
+}
+
+// One graph, after the pass by min(degree, kRowsDirect): a class per degree
+// d < kRowsDirect that occurs (starting at base[d]), the count and first
+// position of the higher-degree vertices, and their key tail big[nbig ..
+// bound) set to ~0 so that it sorts last.
+__global__ __launch_bounds__(256) void k_rows_classes(const uint64_t* __restrict__ hist,
+                                                      const uint64_t* __restrict__ base,
+                                                      uint64_t cap, IndexView ix,
+                                                      uint64_t* __restrict__ meta) {
+  __shared__ uint32_t s_w[4];
+  const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
+  const bool occ = d < (int)kRowsDirect && hist[d] > 0;
+  const uint64_t m = __ballot(occ);
+  if (lane == 0) s_w[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t j = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  for (int w = 0; w < wave; ++w) j += s_w[w];
+  if (occ) {
+    if (j < cap) {
+      ix.cls_deg[j] = (uint32_t)d;
+      ix.cls_start[j] = (uint32_t)base[d];
+    } else {
+      atomicAdd((unsigned long long*)&ix.hdr->overflow, 1ULL);
+    }
+  }
+  if (d == 0) {
+    const uint64_t nsmall = (uint64_t)s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    meta[0] = hist[kRowsDirect];
+    meta[1] = base[kRowsDirect];
+    meta[2] = nsmall;
+    ix.hdr->num_classes = (uint32_t)(nsmall < cap ? nsmall : cap);
+  }
+}
+
+__global__ void k_rows_tail(uint64_t* __restrict__ big, uint64_t bound,
+                            const uint64_t* __restrict__ meta) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = meta[0] + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bound;
+       i += stride)
+    big[i] = ~0ULL;
+}
+
+// The higher-degree vertices, sorted as keys degree << 32 | id: their
+// positions after the lower degrees, their row starts and their classes.
+struct BigClassLoad {
+  const uint64_t* k;
+  const uint64_t* meta;
+  __device__ uint64_t operator()(uint64_t i) const {
+    if (i >= meta[0]) return 0;
+    return (i == 0 || (k[i] >> 32) != (k[i - 1] >> 32)) ? 1 : 0;
+  }
+};
+
+struct BigClassApply {
+  const uint64_t* k;
+  const uint64_t* rowptr;
+  const uint64_t* meta;
+  uint64_t cap;
+  IndexView ix;
+  __device__ void operator()(uint64_t i, uint64_t prefix, uint64_t first) const {
+    const uint64_t nbig = meta[0];
+    if (i >= nbig) return;
+    const uint64_t x = k[i];
+    const uint64_t pos = meta[1] + i;
+    ix.vlist[pos] = (uint32_t)x;
+    ix.vrow[pos] = rowptr[(uint32_t)x];
+    const uint64_t cls = meta[2] + prefix;
+    if (first) {
+      if (cls < cap) {
+        ix.cls_deg[cls] = (uint32_t)(x >> 32);
+        ix.cls_start[cls] = (uint32_t)pos;
+      } else {
+        atomicAdd((unsigned long long*)&ix.hdr->overflow, 1ULL);
+      }
+    }
+    if (i == nbig - 1) {
+      const uint64_t c = cls + first;
+      ix.hdr->num_classes = (uint32_t)(c < cap ? c : cap);
+    }
+  }
+};
 
 struct ClassLoad {
   const uint64_t* k;
@@ -244,6 +357,8 @@ struct BinsWorkspace {
   uint64_t* keys_b;
   uint64_t* scan_ws;
   uint32_t* first_cls;
+  uint64_t* meta;  // one graph: [0] vertices of degree >= kRowsDirect, [1] their first
+                   // position, [2] classes of lower degree
   void* radix;
 };
 
@@ -260,6 +375,8 @@ static size_t bins_layout(uint64_t n, uint32_t G, uint32_t max_bins, BinsWorkspa
   off += round_up(scan_ws_elems(n + 1) * 8, 256);
   if (w) w->first_cls = (uint32_t*)(c + off);
   off += round_up(4 * ((size_t)G * ((size_t)max_bins + 1) + 2), 256);
+  if (w) w->meta = (uint64_t*)(c + off);
+  off += 256;
   if (w) w->radix = (void*)(c + off);
   off += os_scratch_bytes(n);
   return off;
@@ -284,27 +401,63 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
   if ((rc = fill<uint64_t>((uint64_t*)ix.hdr, sizeof(IndexHeader) / 8, 0, st))) return rc;
   if ((rc = fill<uint64_t>(d_n_b, (uint64_t)G * max_bins, 0, st))) return rc;
   if ((rc = fill<uint64_t>(d_p_b, (uint64_t)G * max_bins, 0, st))) return rc;
-  {
-    uint64_t blocks = ceil_div(n, 256);
-    if (blocks > 65536) blocks = 65536;
-    k_deg_keys<<<(unsigned)blocks, 256, 0, st>>>(d_rowptr, (uint32_t)n, d_voff, G, gshift, dmask,
-                                                 w.keys_a, ix.vcode, ix.vmeta);
-    WEDGE_LAUNCH_CHECK("k_deg_keys");
-  }
-  // sort by the degree digits, then by the graph digits; ids stay ascending
   uint64_t dbound = (uint64_t)(max_n ? max_n : 1) - 1;
   if (m_total < dbound) dbound = m_total;
-  int shifts[16];
-  int np = 0;
-  for (int s = 0; s < bit_width(dbound); s += 8) shifts[np++] = 32 + s;
-  for (int s = 0; s < gbits; s += 8) shifts[np++] = gshift + s;
-  uint64_t* sorted = nullptr;
   const OsScratch osc = os_scratch(w.radix, n);
-  rc = onesweep_sort_keys(w.keys_a, w.keys_b, n, shifts, np, osc, st, &sorted);
-  if (rc) return rc;
-  rc = scan_apply<uint64_t>(ClassLoad{sorted}, ClassApply{sorted, d_rowptr, n, cap, dmask, ix}, n,
-                            w.scan_ws, st);
-  if (rc) return rc;
+  if (G == 1 && n > 0) {
+    if ((rc = fill<uint64_t>(osc.hist, 256, 0, st))) return rc;
+    {
+      uint64_t blocks = ceil_div(n, 256);
+      if (blocks > 65536) blocks = 65536;
+      k_deg_hist<<<(unsigned)blocks, 256, 0, st>>>(d_rowptr, (uint32_t)n, ix.vcode, ix.vmeta,
+                                                   osc.hist);
+      WEDGE_LAUNCH_CHECK("k_deg_hist");
+    }
+    if ((rc = onesweep_rows(RowSink{d_rowptr, ix.vlist, ix.vrow, w.keys_a}, n, osc, st)))
+      return rc;
+    k_rows_classes<<<1, 256, 0, st>>>(osc.hist, osc.base, cap, ix, w.meta);
+    WEDGE_LAUNCH_CHECK("k_rows_classes");
+    // vertices of degree >= kRowsDirect: at most 2m / kRowsDirect of them
+    uint64_t bound = 2 * m_total / kRowsDirect;
+    if (bound > n) bound = n;
+    if (bound > 0) {
+      {
+        uint64_t blocks = ceil_div(bound, 256);
+        if (blocks > 4096) blocks = 4096;
+        k_rows_tail<<<(unsigned)blocks, 256, 0, st>>>(w.keys_a, bound, w.meta);
+        WEDGE_LAUNCH_CHECK("k_rows_tail");
+      }
+      int shifts[16];
+      int np = 0;
+      for (int s = 0; s < bit_width(dbound); s += 8) shifts[np++] = 32 + s;
+      uint64_t* sorted = nullptr;
+      rc = onesweep_sort_keys(w.keys_a, w.keys_b, bound, shifts, np, osc, st, &sorted);
+      if (rc) return rc;
+      rc = scan_apply<uint64_t>(BigClassLoad{sorted, w.meta},
+                                BigClassApply{sorted, d_rowptr, w.meta, cap, ix}, bound,
+                                w.scan_ws, st);
+      if (rc) return rc;
+    }
+  } else {
+    {
+      uint64_t blocks = ceil_div(n, 256);
+      if (blocks > 65536) blocks = 65536;
+      k_deg_keys<<<(unsigned)blocks, 256, 0, st>>>(d_rowptr, (uint32_t)n, d_voff, G, gshift,
+                                                   dmask, w.keys_a, ix.vcode, ix.vmeta);
+      WEDGE_LAUNCH_CHECK("k_deg_keys");
+    }
+    // sort by the degree digits, then by the graph digits; ids stay ascending
+    int shifts[16];
+    int np = 0;
+    for (int s = 0; s < bit_width(dbound); s += 8) shifts[np++] = 32 + s;
+    for (int s = 0; s < gbits; s += 8) shifts[np++] = gshift + s;
+    uint64_t* sorted = nullptr;
+    rc = onesweep_sort_keys(w.keys_a, w.keys_b, n, shifts, np, osc, st, &sorted);
+    if (rc) return rc;
+    rc = scan_apply<uint64_t>(ClassLoad{sorted}, ClassApply{sorted, d_rowptr, n, cap, dmask, ix},
+                              n, w.scan_ws, st);
+    if (rc) return rc;
+  }
   rc = scan_apply<uint64_t>(WedgeLoad{ix, n}, CumwApply{ix}, cap, w.scan_ws, st);
   if (rc) return rc;
   {

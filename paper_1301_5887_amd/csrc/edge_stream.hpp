@@ -14,6 +14,16 @@ constexpr uint64_t kEdgeChunk = 1ULL << 24;
 // kept until the process ends.
 int copy_stream(hipStream_t* out);
 
+// The events of one pass; destroyed with the pass, on every return path
+// (an event may be destroyed while work that records it is pending).
+struct EdgeStreamEvents {
+  hipEvent_t e[5] = {};  // start, copied[2], used[2]
+  ~EdgeStreamEvents() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
 // consume(src, dst, ne) enqueues the work on chunk (src, dst) of ne edges on
 // st; buf[b][0] and buf[b][1] hold chunk uint32 each.  Returns the first
 // error of a copy, an event call or the consumer.
@@ -24,12 +34,10 @@ int stream_edges(const uint32_t* h_src, const uint32_t* h_dst, uint64_t m_in, ui
   hipStream_t cs;
   int rc = copy_stream(&cs);
   if (rc) return rc;
-  hipEvent_t start, copied[2], used[2];
-  WEDGE_HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-  for (int b = 0; b < 2; ++b) {
-    WEDGE_HIP_TRY(hipEventCreateWithFlags(&copied[b], hipEventDisableTiming));
-    WEDGE_HIP_TRY(hipEventCreateWithFlags(&used[b], hipEventDisableTiming));
-  }
+  EdgeStreamEvents ev;
+  for (hipEvent_t& x : ev.e) WEDGE_HIP_TRY(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+  hipEvent_t start = ev.e[0];
+  const hipEvent_t copied[2] = {ev.e[1], ev.e[2]}, used[2] = {ev.e[3], ev.e[4]};
   // the copies may only overwrite the buffers once earlier work on the
   // caller's stream is done with them
   WEDGE_HIP_TRY(hipEventRecord(start, st));
@@ -46,12 +54,6 @@ int stream_edges(const uint32_t* h_src, const uint32_t* h_dst, uint64_t m_in, ui
     WEDGE_HIP_TRY(hipStreamWaitEvent(st, copied[b], 0));
     rc = consume((const uint32_t*)buf[b][0], (const uint32_t*)buf[b][1], ne);
     WEDGE_HIP_TRY(hipEventRecord(used[b], st));
-  }
-  // events may be destroyed while work that records them is pending
-  WEDGE_HIP_TRY(hipEventDestroy(start));
-  for (int b = 0; b < 2; ++b) {
-    WEDGE_HIP_TRY(hipEventDestroy(copied[b]));
-    WEDGE_HIP_TRY(hipEventDestroy(used[b]));
   }
   return rc;
 }

@@ -250,7 +250,9 @@ __device__ inline uint64_t os_lookback(const W* __restrict__ status, uint64_t ti
 }
 
 // One digit pass.  kEdges: the input keys are made from the edge list.
-template <bool kEdges, bool kPacked = false>
+// kRows: the keys are min(degree, 255) << 32 | v of the vertices v < N, made
+// from R.rowptr, and the output is the centre order (RowSink).
+template <bool kEdges, bool kPacked = false, bool kRows = false>
 __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t* __restrict__ in,
                                                    uint64_t* __restrict__ out, uint64_t N,
                                                    int shift, uint64_t tag,
@@ -259,7 +261,8 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
                                                    unsigned int* __restrict__ status32,
                                                    const uint32_t* __restrict__ narrow,
                                                    unsigned long long* __restrict__ ticket,
-                                                   unsigned long long* __restrict__ stalls) {
+                                                   unsigned long long* __restrict__ stalls,
+                                                   RowSink R) {
   constexpr int kWaves = kOsWG / 64;
   __shared__ uint64_t s_keys[kOsTile];
   __shared__ uint32_t s_cnt[kWaves][256];
@@ -322,6 +325,15 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
         key[2 * it + 1] = k1;
         ok[2 * it] = ok[2 * it + 1] = valid;
       }
+    }
+  } else if (kRows) {
+#pragma unroll
+    for (int it = 0; it < kOsItems; ++it) {
+      const uint64_t g = tbase + (uint64_t)wave * 64 * kOsItems + (uint64_t)it * 64 + lane;
+      ok[it] = g < N;
+      uint64_t d = 0;
+      if (ok[it]) d = R.rowptr[g + 1] - R.rowptr[g];
+      key[it] = ((d < kRowsDirect ? d : (uint64_t)kRowsDirect) << 32) | g;
     }
   } else {
 #pragma unroll
@@ -446,7 +458,15 @@ __global__ __launch_bounds__(kOsWG) void k_os_pass(EdgeSource E, const uint64_t*
     const uint32_t d = (uint32_t)(k >> shift) & 255;
     const uint64_t at = s_glob[d] + (uint64_t)j;
     if (at < N) {
-      if (kPacked) {
+      if (kRows) {
+        const uint32_t v = (uint32_t)k;
+        if (d < kRowsDirect) {
+          R.vlist[at] = v;
+          R.vrow[at] = R.rowptr[v];
+        } else {
+          R.big[at - base[kRowsDirect]] = ((R.rowptr[v + 1] - R.rowptr[v]) << 32) | v;
+        }
+      } else if (kPacked) {
         uint32_t* out_lo = (uint32_t*)out;
         uint16_t* out_hi = (uint16_t*)(out_lo + N);
         out_lo[at] = (uint32_t)k;
@@ -501,19 +521,19 @@ int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int
     if (E.ks > 24) {
       if (p == 0)
         k_os_pass<true><<<grid, block, 0, st>>>(E, nullptr, dst, N, shifts[p], tag, base, sc.status,
-                                                 sc.status32, sc.narrow + p, sc.tickets + p, stalls);
+                                                 sc.status32, sc.narrow + p, sc.tickets + p, stalls, RowSink{});
       else
         k_os_pass<false><<<grid, block, 0, st>>>(E, src, dst, N, shifts[p], tag, base, sc.status,
-                                                  sc.status32, sc.narrow + p, sc.tickets + p, stalls);
+                                                  sc.status32, sc.narrow + p, sc.tickets + p, stalls, RowSink{});
     } else {
       if (p == 0)
         k_os_pass<true, true><<<grid, block, 0, st>>>(E, nullptr, dst, N, shifts[p], tag, base,
                                                        sc.status, sc.status32, sc.narrow + p,
-                                                       sc.tickets + p, stalls);
+                                                       sc.tickets + p, stalls, RowSink{});
       else
         k_os_pass<false, true><<<grid, block, 0, st>>>(E, src, dst, N, shifts[p], tag, base,
                                                         sc.status, sc.status32, sc.narrow + p,
-                                                        sc.tickets + p, stalls);
+                                                        sc.tickets + p, stalls, RowSink{});
     }
     WEDGE_LAUNCH_CHECK("k_os_pass");
     src = dst;
@@ -554,13 +574,36 @@ int onesweep_sort_keys(uint64_t* a, uint64_t* b, uint64_t N, const int* shifts, 
     k_os_pass<false><<<(unsigned)nt, kOsWG, 0, st>>>(none, src, dst, N, shifts[p], tag,
                                                       sc.base + p * 256, sc.status, sc.status32,
                                                       sc.narrow + p, sc.tickets + p,
-                                                      sc.tickets + kOsMaxPasses);
+                                                      sc.tickets + kOsMaxPasses, RowSink{});
     WEDGE_LAUNCH_CHECK("k_os_pass");
     uint64_t* t = src;
     src = dst;
     dst = t;
   }
   *result = src;
+  return WEDGE_OK;
+}
+
+int onesweep_rows(RowSink R, uint64_t n, OsScratch sc, hipStream_t st) {
+  if (n == 0) return WEDGE_OK;
+  const uint64_t nt = os_tiles(n);
+  int rc = fill<unsigned long long>(sc.tickets, kOsMaxPasses + 1, 0, st);
+  if (rc) return rc;
+  if ((rc = fill<unsigned long long>(sc.status, nt * 256, 0, st))) return rc;
+  if ((rc = fill<unsigned int>(sc.status32, nt * 256, 0u, st))) return rc;
+  OsShifts S;
+  S.npass = 1;
+  for (int p = 0; p < kOsMaxPasses; ++p) {
+    S.s[p] = 32;
+    S.mirror[p] = -1;
+  }
+  k_os_base<<<1, 256, 0, st>>>(sc.hist, sc.base, sc.narrow, S);
+  WEDGE_LAUNCH_CHECK("k_os_base");
+  const EdgeSource none{nullptr, nullptr, 0, 0, nullptr, nullptr, 1, nullptr};
+  k_os_pass<false, false, true><<<(unsigned)nt, kOsWG, 0, st>>>(
+      none, nullptr, nullptr, n, 32, 1ULL << 56, sc.base, sc.status, sc.status32, sc.narrow,
+      sc.tickets, sc.tickets + kOsMaxPasses, R);
+  WEDGE_LAUNCH_CHECK("k_os_pass");
   return WEDGE_OK;
 }
 

@@ -118,6 +118,24 @@ int onesweep_sort_edges(const EdgeSource& E, uint64_t* a, uint64_t* b, const int
 int onesweep_sort_keys(uint64_t* a, uint64_t* b, uint64_t N, const int* shifts, int npass,
                        OsScratch sc, hipStream_t st, uint64_t** result);
 
+// The centre order of one graph straight from its row starts: vertices of
+// degree d < kRowsDirect in order of (d, id) at positions base[d].. of vlist
+// (their ids) and vrow (their row starts); the others as keys
+// degree << 32 | id, in id order, at big[0..) (their count is the pass's
+// count of digit kRowsDirect).
+constexpr uint32_t kRowsDirect = 255;
+struct RowSink {
+  const uint64_t* rowptr;  // [n + 1]
+  uint32_t* vlist;         // [n]
+  uint64_t* vrow;          // [n]
+  uint64_t* big;           // [vertices of degree >= kRowsDirect]
+};
+
+// One stable pass over the vertices 0..n-1 by min(degree, kRowsDirect) into
+// R; sc.hist[0..256) must hold the counts of that digit.  Leaves the digit
+// offsets in sc.base[0..256).
+int onesweep_rows(RowSink R, uint64_t n, OsScratch sc, hipStream_t st);
+
 // After a sort on stream st: *target = value if any look-back of that sort
 // gave up waiting (its output is then not sorted).  Every tile a look-back
 // waits on is already running, so this is not expected; the flag makes it
