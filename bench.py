@@ -299,6 +299,7 @@ def plain_workload(args, torch, n, src, dst, workload):
 
     roofline = sampler_roofline(args, K, q_step, probes, avg["sample_close"])
     roofline_csr = csr_roofline(n, m_in, m, avg["build_csr"])
+    roofline_bins = bins_roofline(n, avg["bin_counts"])
     # the streaming ceiling (left out of counter runs, whose calibration copy
     # must be the only large copy)
     stream = stream_copy_rate(torch, dev) if args.calibrate_copy_gib <= 0 else None
@@ -308,6 +309,8 @@ def plain_workload(args, torch, n, src, dst, workload):
                                                 stream, 4)
     if stream:
         roofline_csr["frac_sort_of_stream_copy"] = round(roofline_csr["achieved_sort"] / stream, 4)
+        roofline_bins["frac_pass_of_stream_copy"] = round(roofline_bins["achieved_pass"] / stream,
+                                                          4)
 
     if args.calibrate_copy_gib > 0:
         nbytes = int(args.calibrate_copy_gib * (1 << 30))
@@ -378,6 +381,7 @@ def plain_workload(args, torch, n, src, dst, workload):
         "phase_ms": {kx: round(vx, 4) for kx, vx in avg.items()},
         "roofline": roofline,
         "roofline_csr": roofline_csr,
+        "roofline_bins": roofline_bins,
         "estimators": cvcmp,
         "triangle_sample": tri,
         "hash_probe": hashp,
@@ -444,6 +448,23 @@ def stream_copy_rate(torch, dev, gib: int = 4, reps: int = 5) -> float:
     del a, b
     torch.cuda.empty_cache()
     return round(2 * nbytes / (float(np.median(times)) / 1e3) / 1e9, 1)
+
+
+def bins_roofline(n, t_ms):
+    """wedge_bin_counts against the HBM peak: the least bytes of a degree
+    pass plus a counting sort of the vertices by degree (read rowptr, read
+    the degrees and write the vertex order: 20 B per vertex), and the bytes
+    of this build (the degree pass reads rowptr and writes the degree code
+    and row word of every vertex; the pass by degree reads rowptr again and
+    writes the order and each vertex's row start: 37 B per vertex; the sort
+    of the few vertices of degree >= 255 is left out)."""
+    t = t_ms / 1000.0
+    least, ours = 20 * n, 37 * n
+    return {"phase": "wedge_bin_counts", "bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "min_bytes": least, "achieved_min": round(least / t / 1e9, 2),
+            "frac_min": round(least / t / 1e9 / PEAK_HBM_GBS, 5),
+            "pass_bytes": ours, "achieved_pass": round(ours / t / 1e9, 2),
+            "frac_pass": round(ours / t / 1e9 / PEAK_HBM_GBS, 5)}
 
 
 def csr_roofline(n, m_in, m, t_ms):
