@@ -407,8 +407,10 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
   if (G == 1 && n > 0) {
     if ((rc = fill<uint64_t>(osc.hist, 256, 0, st))) return rc;
     {
+      // few enough workgroups that their global adds (one per nonzero
+      // counter) do not queue on the 256 counters
       uint64_t blocks = ceil_div(n, 256);
-      if (blocks > 65536) blocks = 65536;
+      if (blocks > 2048) blocks = 2048;
       k_deg_hist<<<(unsigned)blocks, 256, 0, st>>>(d_rowptr, (uint32_t)n, ix.vcode, ix.vmeta,
                                                    osc.hist);
       WEDGE_LAUNCH_CHECK("k_deg_hist");
