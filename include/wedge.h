@@ -655,7 +655,7 @@ int wedge_closure_join(const uint32_t* d_a, const uint32_t* d_c, uint64_t k,
  * wedge_bin_counts + wedge_sample_close on the same list.
  *
  * In:  h_src[m_in], h_dst[m_in]  host uint32 edge list (pinned memory lets
- *                     the copies overlap); read in 3 + (gather rounds)
+ *                     the copies overlap); read in 2 + (gather rounds)
  *                     passes; must not change during the call.
  *      n, tau, omega, max_bins as wedge_bin_counts; h_k[max_bins],
  *      k_global, seed as wedge_sample_close (graph_id 0); a bin whose p_b
