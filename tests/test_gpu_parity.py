@@ -363,6 +363,30 @@ def test_degenerate_graphs():
     assert r["q"][2].tolist() == [0, 0, 0, 4096] and r["q"][4].tolist() == [0, 0, 0, 4096]
 
 
+def test_bins_degrees_around_255():
+    """Degrees below 255 are ordered by one pass over the row starts, the
+    others sorted as keys: cliques whose vertices have degree 254, 255 and
+    256, stars with 254 to 300 leaves and a sparse background, so that both
+    parts of the centre order meet several times."""
+    rng = np.random.default_rng(255)
+    parts, off = [], 0
+    for size in (255, 256, 257):      # degrees 254, 255, 256
+        e = np.array([(i, j) for i in range(size) for j in range(i + 1, size)], np.uint32)
+        parts.append(e + np.uint32(off))
+        off += size
+    for leaves in (254, 255, 256, 300):
+        e = np.stack([np.full(leaves, off, np.uint32),
+                      np.arange(off + 1, off + 1 + leaves, dtype=np.uint32)], 1)
+        parts.append(e)
+        off += leaves + 1
+    n = off + 20_000
+    bg = rng.integers(off, n, (60_000, 2)).astype(np.uint32)
+    e = np.concatenate(parts + [bg])
+    e = e[rng.permutation(len(e))]
+    r = run_both(e[:, 0], e[:, 1], n, B=24, k=3_000, seed=5)
+    check_all(r)
+
+
 def test_rejected_ids_and_duplicates():
     rng = np.random.default_rng(3)
     n = 500
