@@ -1,7 +1,8 @@
 // Chunked pass over an edge list held in host memory: chunk j is copied on a
 // second stream of the device into one of two buffer pairs while the caller's
 // stream runs the consumer on chunk j - 1 (pinned host memory lets the copies
-// overlap the kernels).
+// overlap the kernels, and is read by a copy kernel rather than the copy
+// engine).
 #pragma once
 
 #include "common.hpp"
@@ -13,6 +14,18 @@ constexpr uint64_t kEdgeChunk = 1ULL << 24;
 // One copy stream per device, created on first use (default priority) and
 // kept until the process ends.
 int copy_stream(hipStream_t* out);
+
+// The device address of host memory [h, h + bytes) when kernels may read it
+// directly: pinned memory (hipHostMalloc, torch's pin_memory) whose one
+// allocation holds the whole range.  Null for anything else (pageable memory
+// goes through hipMemcpyAsync instead).
+const char* host_direct(const void* h, size_t bytes);
+
+// Enqueues on cs the copy of ne edges from host memory read directly
+// (addresses from host_direct) into bs, bd: a kernel that reads over the host
+// link, which moves a chunk faster than the copy engine did.
+int copy_edges_direct(const uint32_t* s, const uint32_t* d, uint32_t* bs, uint32_t* bd,
+                      uint64_t ne, hipStream_t cs);
 
 // The events of one pass; destroyed with the pass, on every return path
 // (an event may be destroyed while work that records it is pending).
@@ -34,6 +47,9 @@ int stream_edges(const uint32_t* h_src, const uint32_t* h_dst, uint64_t m_in, ui
   hipStream_t cs;
   int rc = copy_stream(&cs);
   if (rc) return rc;
+  const size_t bytes = (size_t)m_in * 4;
+  const char* ds = host_direct(h_src, bytes);
+  const char* dd = ds ? host_direct(h_dst, bytes) : nullptr;
   EdgeStreamEvents ev;
   for (hipEvent_t& x : ev.e) WEDGE_HIP_TRY(hipEventCreateWithFlags(&x, hipEventDisableTiming));
   hipEvent_t start = ev.e[0];
@@ -48,8 +64,14 @@ int stream_edges(const uint32_t* h_src, const uint32_t* h_dst, uint64_t m_in, ui
     const uint64_t e0 = j * chunk;
     const uint64_t ne = (m_in - e0) < chunk ? (m_in - e0) : chunk;
     if (j >= 2) WEDGE_HIP_TRY(hipStreamWaitEvent(cs, used[b], 0));
-    WEDGE_HIP_TRY(hipMemcpyAsync(buf[b][0], h_src + e0, ne * 4, hipMemcpyHostToDevice, cs));
-    WEDGE_HIP_TRY(hipMemcpyAsync(buf[b][1], h_dst + e0, ne * 4, hipMemcpyHostToDevice, cs));
+    if (dd) {
+      rc = copy_edges_direct((const uint32_t*)ds + e0, (const uint32_t*)dd + e0, buf[b][0],
+                             buf[b][1], ne, cs);
+      if (rc) return rc;
+    } else {
+      WEDGE_HIP_TRY(hipMemcpyAsync(buf[b][0], h_src + e0, ne * 4, hipMemcpyHostToDevice, cs));
+      WEDGE_HIP_TRY(hipMemcpyAsync(buf[b][1], h_dst + e0, ne * 4, hipMemcpyHostToDevice, cs));
+    }
     WEDGE_HIP_TRY(hipEventRecord(copied[b], cs));
     WEDGE_HIP_TRY(hipStreamWaitEvent(st, copied[b], 0));
     rc = consume((const uint32_t*)buf[b][0], (const uint32_t*)buf[b][1], ne);

@@ -109,6 +109,84 @@ static size_t join_layout(uint64_t k, uint64_t chunk, JoinWorkspace* w, void* ba
 
 constexpr uint64_t kJoinChunk = kEdgeChunk;
 
+const char* host_direct(const void* h, size_t bytes) {
+  if (!h || bytes == 0) return nullptr;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, h) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (a.type != hipMemoryTypeHost || !a.devicePointer) return nullptr;
+  void* start = nullptr;
+  size_t size = 0;
+  if (hipPointerGetAttribute(&start, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR,
+                             (hipDeviceptr_t)h) != hipSuccess ||
+      hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, (hipDeviceptr_t)h) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  const char* p = (const char*)h;
+  if (!start || p < (const char*)start || bytes > size ||
+      (size_t)(p - (const char*)start) > size - bytes)
+    return nullptr;
+  return (const char*)a.devicePointer;
+}
+
+// Four 16-byte words of each array per thread and step when every address is
+// 16-byte aligned (many reads in flight over the host link); words otherwise.
+constexpr int kCopyWG = 256;
+constexpr int kCopyVec = 4;
+__global__ __launch_bounds__(kCopyWG) void k_copy_edges(const uint32_t* __restrict__ s,
+                                                        const uint32_t* __restrict__ d,
+                                                        uint32_t* __restrict__ bs,
+                                                        uint32_t* __restrict__ bd, uint64_t ne) {
+  const uint64_t stride = (uint64_t)gridDim.x * kCopyWG;
+  const uint64_t t = (uint64_t)blockIdx.x * kCopyWG + threadIdx.x;
+  uint64_t i0 = 0;
+  if (((((uintptr_t)s) | ((uintptr_t)d) | ((uintptr_t)bs) | ((uintptr_t)bd)) & 15) == 0) {
+    const uint64_t nq = ne / 4;
+    const uint4* s4 = (const uint4*)s;
+    const uint4* d4 = (const uint4*)d;
+    uint4* bs4 = (uint4*)bs;
+    uint4* bd4 = (uint4*)bd;
+    for (uint64_t q = t; q < nq; q += stride * kCopyVec) {
+      uint4 xs[kCopyVec], xd[kCopyVec];
+#pragma unroll
+      for (int j = 0; j < kCopyVec; ++j) {
+        const uint64_t r = q + (uint64_t)j * stride;
+        if (r < nq) {
+          xs[j] = s4[r];
+          xd[j] = d4[r];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kCopyVec; ++j) {
+        const uint64_t r = q + (uint64_t)j * stride;
+        if (r < nq) {
+          bs4[r] = xs[j];
+          bd4[r] = xd[j];
+        }
+      }
+    }
+    i0 = nq * 4;
+  }
+  for (uint64_t i = i0 + t; i < ne; i += stride) {
+    bs[i] = s[i];
+    bd[i] = d[i];
+  }
+}
+
+int copy_edges_direct(const uint32_t* s, const uint32_t* d, uint32_t* bs, uint32_t* bd,
+                      uint64_t ne, hipStream_t cs) {
+  if (ne == 0) return WEDGE_OK;
+  uint64_t blocks = ceil_div(ne, (uint64_t)kCopyWG * 4 * kCopyVec);
+  if (blocks > 2048) blocks = 2048;
+  k_copy_edges<<<(unsigned)blocks, kCopyWG, 0, cs>>>(s, d, bs, bd, ne);
+  WEDGE_LAUNCH_CHECK("k_copy_edges");
+  return WEDGE_OK;
+}
+
 int copy_stream(hipStream_t* out) {
   static std::mutex mu;
   static hipStream_t streams[64] = {};

@@ -53,10 +53,16 @@ def adjacency_path(src, dst, n, B, k, kg, seed, tau=2, omega=2, dpb=None):
                 dump=so.dump.cpu().numpy().view(np.uint32).reshape(B + 1, dpb, 4))
 
 
-def stream_path(src, dst, n, B, k, kg, seed, dpb, tau=2, omega=2, gather_cap=None, chunk=0):
+def stream_path(src, dst, n, B, k, kg, seed, dpb, tau=2, omega=2, gather_cap=None, chunk=0,
+                pinned=True):
     print(f"[stream] n={n} m_in={len(src)} B={B} k={k} kg={kg} seed={seed} cap={gather_cap} "
-          f"chunk={chunk}", flush=True)
-    out = W.sample_stream(host(src), host(dst), n, np.full(B, k, dtype=np.uint64), kg, seed,
+          f"chunk={chunk} pinned={pinned}", flush=True)
+    if pinned:
+        hs, hd = host(src), host(dst)
+    else:
+        hs, hd = (torch.from_numpy(np.ascontiguousarray(x, dtype=np.uint32).view(np.int32))
+                  for x in (src, dst))
+    out = W.sample_stream(hs, hd, n, np.full(B, k, dtype=np.uint64), kg, seed,
                           tau, omega, B, gather_cap=gather_cap, chunk_edges=chunk,
                           dump_per_bin=dpb)
     torch.cuda.synchronize()
@@ -101,11 +107,14 @@ def test_stream_equals_adjacency_path(case):
         assert st.rounds >= 3
 
 
-def test_stream_equals_oracle_small():
+@pytest.mark.parametrize("pinned", [True, False])
+def test_stream_equals_oracle_small(pinned):
+    """Against the oracle, from pinned host memory (read by the copy kernel)
+    and from pageable memory (copied by hipMemcpyAsync)."""
     n, src, dst = gen.rmat_graph500(11, 8, seed=4)
     a, b = simple_edges(src, dst, n, seed=5)
     B, k, kg, seed = 24, 5000, 5000, 9
-    st = stream_path(a, b, n, B, k, kg, seed, dpb=5000)
+    st = stream_path(a, b, n, B, k, kg, seed, dpb=5000, pinned=pinned)
     og = O.build_graph(a, b, n)
     n_b, p_b = O.bins(og, 2, 2, B)
     assert (st.bins.h_n_b == n_b).all() and (st.bins.h_p_b == p_b).all()
