@@ -133,69 +133,57 @@ const char* host_direct(const void* h, size_t bytes) {
   return (const char*)a.devicePointer;
 }
 
-// Four 16-byte words of each array per thread and step when every address is
-// 16-byte aligned (many reads in flight over the host link); words otherwise.
+// Four 16-byte words per thread and step when both addresses are 16-byte
+// aligned (many reads in flight over the host link); words otherwise.
 constexpr int kCopyWG = 256;
 constexpr int kCopyVec = 4;
-__global__ __launch_bounds__(kCopyWG) void k_copy_edges(const uint32_t* __restrict__ s,
-                                                        const uint32_t* __restrict__ d,
-                                                        uint32_t* __restrict__ bs,
-                                                        uint32_t* __restrict__ bd, uint64_t ne) {
+__global__ __launch_bounds__(kCopyWG) void k_copy_words(const uint32_t* __restrict__ s,
+                                                        uint32_t* __restrict__ b, uint64_t n) {
   const uint64_t stride = (uint64_t)gridDim.x * kCopyWG;
   const uint64_t t = (uint64_t)blockIdx.x * kCopyWG + threadIdx.x;
   uint64_t i0 = 0;
-  if (((((uintptr_t)s) | ((uintptr_t)d) | ((uintptr_t)bs) | ((uintptr_t)bd)) & 15) == 0) {
-    const uint64_t nq = ne / 4;
+  if (((((uintptr_t)s) | ((uintptr_t)b)) & 15) == 0) {
+    const uint64_t nq = n / 4;
     const uint4* s4 = (const uint4*)s;
-    const uint4* d4 = (const uint4*)d;
-    uint4* bs4 = (uint4*)bs;
-    uint4* bd4 = (uint4*)bd;
+    uint4* b4 = (uint4*)b;
     for (uint64_t q = t; q < nq; q += stride * kCopyVec) {
-      uint4 xs[kCopyVec], xd[kCopyVec];
+      uint4 x[kCopyVec];
 #pragma unroll
       for (int j = 0; j < kCopyVec; ++j) {
         const uint64_t r = q + (uint64_t)j * stride;
-        if (r < nq) {
-          xs[j] = s4[r];
-          xd[j] = d4[r];
-        }
+        if (r < nq) x[j] = s4[r];
       }
 #pragma unroll
       for (int j = 0; j < kCopyVec; ++j) {
         const uint64_t r = q + (uint64_t)j * stride;
-        if (r < nq) {
-          bs4[r] = xs[j];
-          bd4[r] = xd[j];
-        }
+        if (r < nq) b4[r] = x[j];
       }
     }
     i0 = nq * 4;
   }
-  for (uint64_t i = i0 + t; i < ne; i += stride) {
-    bs[i] = s[i];
-    bd[i] = d[i];
-  }
+  for (uint64_t i = i0 + t; i < n; i += stride) b[i] = s[i];
 }
 
-int copy_edges_direct(const uint32_t* s, const uint32_t* d, uint32_t* bs, uint32_t* bd,
-                      uint64_t ne, hipStream_t cs) {
-  if (ne == 0) return WEDGE_OK;
-  uint64_t blocks = ceil_div(ne, (uint64_t)kCopyWG * 4 * kCopyVec);
+int copy_words_direct(const uint32_t* s, uint32_t* b, uint64_t n, hipStream_t cs) {
+  if (n == 0) return WEDGE_OK;
+  uint64_t blocks = ceil_div(n, (uint64_t)kCopyWG * 4 * kCopyVec);
   if (blocks > 2048) blocks = 2048;
-  k_copy_edges<<<(unsigned)blocks, kCopyWG, 0, cs>>>(s, d, bs, bd, ne);
-  WEDGE_LAUNCH_CHECK("k_copy_edges");
+  k_copy_words<<<(unsigned)blocks, kCopyWG, 0, cs>>>(s, b, n);
+  WEDGE_LAUNCH_CHECK("k_copy_words");
   return WEDGE_OK;
 }
 
-int copy_stream(hipStream_t* out) {
+int copy_stream(hipStream_t* out, int which) {
   static std::mutex mu;
-  static hipStream_t streams[64] = {};
+  static hipStream_t streams[64][2] = {};
   int dev = 0;
   WEDGE_HIP_TRY(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64) return set_error(WEDGE_ERANGE, "copy_stream: device id");
+  if (dev < 0 || dev >= 64 || which < 0 || which > 1)
+    return set_error(WEDGE_ERANGE, "copy_stream: device id");
   std::lock_guard<std::mutex> lock(mu);
-  if (!streams[dev]) WEDGE_HIP_TRY(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
-  *out = streams[dev];
+  if (!streams[dev][which])
+    WEDGE_HIP_TRY(hipStreamCreateWithFlags(&streams[dev][which], hipStreamNonBlocking));
+  *out = streams[dev][which];
   return WEDGE_OK;
 }
 
