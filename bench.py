@@ -33,6 +33,7 @@ import argparse
 import gc
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -341,6 +342,12 @@ def plain_workload(args, torch, n, src, dst, workload):
                                                          avg["sample_close"])
     alloc = alloc_comparison(args, torch, W, g, bi, hk, kg, k) if args.alloc_seeds > 0 else None
     join = closure_join(args, torch, W, g, bi, hk, kg, src, dst) if args.join else None
+    if args.stream:
+        # the timed steps' workspace is not needed any more; the streamed leg
+        # builds its edge list on the device and needs the room at scale 28
+        ws.buf = None
+        gc.collect()
+        torch.cuda.empty_cache()
     streamed = stream_leg(args, torch, W, g, bi, k, kg, q_step) if args.stream else None
     tri = triangle_sample(args, torch, g, bi, est) if args.triangles > 0 else None
     hashp = None if args.no_hash else hash_probe(args, torch, W, g, bi, hk, kg, q_step,
@@ -605,31 +612,74 @@ def closure_join(args, torch, W, g, bi, hk, kg, src, dst):
     return join
 
 
+def simple_edges_to_host(torch, g, seed):
+    """The graph's simple edge list (each edge once, u < w before a random
+    flip of orientation) in random order, in pinned host memory.  Below 2^31
+    edges the order is a random permutation; above (torch's masked selection
+    and randperm stop there) the rows are taken in slices of at most 2^30
+    entries and edge e goes to position (a e + b) mod m for an a prime to m,
+    which scatters neighbouring edges across the list."""
+    n, m = g.n, g.m
+    dev = g.col.device
+    gen_ = torch.Generator(device=dev)
+    gen_.manual_seed(seed)
+    ha = torch.empty(m, dtype=torch.int32, pin_memory=True)
+    hb = torch.empty(m, dtype=torch.int32, pin_memory=True)
+    if m < (1 << 31):
+        deg = g.rowptr[1:] - g.rowptr[:-1]
+        rows = torch.repeat_interleave(torch.arange(n, dtype=torch.int32, device=dev), deg)
+        col = g.col[: 2 * m]
+        keep = col > rows
+        u, w = rows[keep], col[keep]
+        del rows, col, keep, deg
+        perm = torch.randperm(m, device=dev, generator=gen_)
+        u, w = u[perm], w[perm]
+        del perm
+        flip = torch.rand(m, device=dev, generator=gen_) < 0.5
+        ha.copy_(torch.where(flip, w, u))
+        hb.copy_(torch.where(flip, u, w))
+        return ha, hb
+    mult = 1_000_003
+    while math.gcd(mult, m) != 1:
+        mult += 2
+    shift = int(torch.randint(0, m, (1,), device=dev, generator=gen_).item())
+    A = torch.empty(m, dtype=torch.int32, device=dev)
+    Bv = torch.empty(m, dtype=torch.int32, device=dev)
+    rp = g.rowptr
+    v0, off = 0, 0
+    while v0 < n:
+        lim = torch.tensor([int(rp[v0].item()) + (1 << 30)], dtype=torch.int64, device=dev)
+        v1 = int(torch.searchsorted(rp, lim, right=True).item()) - 1
+        v1 = min(max(v1, v0 + 1), n)
+        r0, r1 = int(rp[v0].item()), int(rp[v1].item())
+        deg = rp[v0 + 1:v1 + 1] - rp[v0:v1]
+        rows = torch.repeat_interleave(torch.arange(v0, v1, dtype=torch.int32, device=dev), deg)
+        col = g.col[r0:r1]
+        keep = col > rows
+        u, w = rows[keep], col[keep]
+        del rows, col, keep, deg
+        cnt = u.numel()
+        pos = (torch.arange(off, off + cnt, dtype=torch.int64, device=dev) * mult + shift) % m
+        flip = torch.rand(cnt, device=dev, generator=gen_) < 0.5
+        A[pos] = torch.where(flip, w, u)
+        Bv[pos] = torch.where(flip, u, w)
+        del u, w, pos, flip
+        off += cnt
+        v0 = v1
+    assert off == m, (off, m)
+    ha.copy_(A)
+    hb.copy_(Bv)
+    del A, Bv
+    return ha, hb
+
+
 def stream_leg(args, torch, W, g, bi, k, kg, q_step):
     """The step's samples by the streamed path: the graph's simple edge list
     (each edge once, random order and orientation) in pinned host memory,
     degrees, draws, gathered rows and the closure join all from passes over
     it, no adjacency on the device; its counts against the step's."""
     n, m = g.n, g.m
-    deg = g.rowptr[1:] - g.rowptr[:-1]
-    rows = torch.repeat_interleave(torch.arange(n, dtype=torch.int32, device=g.col.device), deg)
-    col = g.col[: 2 * m]
-    keep = col > rows
-    u, w = rows[keep], col[keep]
-    del rows, col, keep, deg
-    gen_ = torch.Generator(device=g.col.device)
-    gen_.manual_seed(args.seed)
-    perm = torch.randperm(m, device=g.col.device, generator=gen_)
-    u, w = u[perm], w[perm]
-    del perm
-    flip = torch.rand(m, device=g.col.device, generator=gen_) < 0.5
-    a, b = torch.where(flip, w, u), torch.where(flip, u, w)
-    del u, w, flip
-    ha = torch.empty(m, dtype=torch.int32, pin_memory=True)
-    hb = torch.empty(m, dtype=torch.int32, pin_memory=True)
-    ha.copy_(a)
-    hb.copy_(b)
-    del a, b
+    ha, hb = simple_edges_to_host(torch, g, args.seed)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     B = bi.max_bins
