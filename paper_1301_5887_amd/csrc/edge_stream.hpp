@@ -1,8 +1,9 @@
-// Chunked pass over an edge list held in host memory: chunk j is copied on a
-// second stream of the device into one of two buffer pairs while the caller's
-// stream runs the consumer on chunk j - 1 (pinned host memory lets the copies
-// overlap the kernels, and is read by a copy kernel rather than the copy
-// engine).
+// Chunked pass over an edge list held in host memory: chunk j is copied into
+// one of two buffer pairs on two copy streams of the device while the
+// caller's stream runs the consumer on chunk j - 1.  The destination array
+// goes by the copy engine; the source array, when it is pinned, by a copy
+// kernel that reads it over the host link, so both share the link (pinned
+// memory also lets the copies overlap the kernels).
 #pragma once
 
 #include "common.hpp"
