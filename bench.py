@@ -77,6 +77,16 @@ def sampler_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def csr_hash() -> str:
+    """Hash of the adjacency build's sources, kept with its counter summary
+    (the counts stand for the build only while these files are unchanged)."""
+    h = hashlib.sha256()
+    for name in ("csr.hip", "radix.hip", "radix.hpp"):
+        with open(os.path.join(ROOT, "paper_1301_5887_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def host_info() -> dict:
     """CPU model, memory and core counts of the host the oracle runs on."""
     model = None
@@ -300,6 +310,7 @@ def plain_workload(args, torch, n, src, dst, workload):
 
     roofline = sampler_roofline(args, K, q_step, probes, avg["sample_close"])
     roofline_csr = csr_roofline(n, m_in, m, avg["build_csr"])
+    csr_traffic(args, roofline_csr, m_in, K, avg["build_csr"])
     roofline_bins = bins_roofline(n, avg["bin_counts"])
     # the streaming ceiling (left out of counter runs, whose calibration copy
     # must be the only large copy)
@@ -472,6 +483,32 @@ def bins_roofline(n, t_ms):
             "frac_min": round(least / t / 1e9 / PEAK_HBM_GBS, 5),
             "pass_bytes": ours, "achieved_pass": round(ours / t / 1e9, 2),
             "frac_pass": round(ours / t / 1e9 / PEAK_HBM_GBS, 5)}
+
+
+def csr_traffic(args, rf, m_in, K, t_ms):
+    """HBM bytes of one adjacency build from the stored counter summary (the
+    first digit pass, the later passes, the dedup; the edge histogram's read
+    of the 8 bytes of every input edge is added at its size, as it streams
+    the list once), while the build's sources and the workload match it."""
+    rf["traffic"] = None
+    pf = pmc_file(args.scale) if args.graph == "rmat" else None
+    if not (pf and os.path.exists(pf)):
+        return
+    with open(pf) as f:
+        pmc = json.load(f)
+    if pmc.get("csr_hash") != csr_hash() or pmc.get("workload_K") != K:
+        return
+    grp = pmc.get("groups", {})
+    parts = [grp.get(x, {}) for x in ("k_os_pass_first", "k_os_pass_later", "k_dedup")]
+    if not all("read_bytes" in p and "write_bytes" in p for p in parts):
+        return
+    first, later, dedup = (p["read_bytes"] + p["write_bytes"] for p in parts)
+    traffic = first + (rf["digit_passes"] - 1) * later + dedup + 8 * m_in
+    t = t_ms / 1000.0
+    rf["traffic"] = traffic
+    rf["traffic_GBps"] = round(traffic / t / 1e9, 1)
+    rf["frac_traffic"] = round(traffic / t / 1e9 / PEAK_HBM_GBS, 5)
+    rf["traffic_over_sort_bytes"] = round(traffic / rf["sort_bytes"], 3)
 
 
 def csr_roofline(n, m_in, m, t_ms):
@@ -1023,8 +1060,8 @@ def pmc_summarize(dirs, workload_k: int, copy_gib: float, gather_lines: int, out
         return out
 
     groups = {g: derive(c) for g, c in merged.items()}
-    out = {"sampler_hash": sampler_hash(), "workload_K": workload_k, "groups": groups,
-           "runs": [str(d) for d in dirs]}
+    out = {"sampler_hash": sampler_hash(), "csr_hash": csr_hash(), "workload_K": workload_k,
+           "groups": groups, "runs": [str(d) for d in dirs]}
     cal = groups.get("calibration_copy", {})
     factor = None
     if cal.get("read_bytes"):
