@@ -439,6 +439,9 @@ def sampler_roofline(args, K, qh, probes, t_ms):
             out["traffic"] = traffic
             out["amplification"] = round(traffic / alg_bytes, 2) if traffic else None
             out["traffic_GBps_at_this_launch_time"] = round(traffic / t / 1e9, 1) if traffic else None
+            # the HBM bytes the counters see over this launch time, against the peak
+            out["frac_traffic"] = (round(traffic / t / 1e9 / PEAK_HBM_GBS, 5)
+                                   if traffic else None)
             for key in ("l2_hit_rate", "request_mix", "traffic_by_requests"):
                 if key in pmc:
                     out[key] = pmc[key]
