@@ -98,6 +98,12 @@ __global__ void k_deg_keys(const uint64_t* __restrict__ rowptr, uint32_t n,
   }
 }
 
+// *target = value if *word != 0 (after the work before it on the stream).
+__global__ void k_flag_if_set(const uint64_t* __restrict__ word, uint64_t* __restrict__ target,
+                              uint64_t value) {
+  if (threadIdx.x == 0 && *word != 0) *target = value;
+}
+
 // One graph: degree code and row word per vertex (as k_deg_keys) and the
 // counts of min(degree, kRowsDirect).  Lane group lane / 8 adds to its own
 // copy of the counters (most vertices share a few small degrees).
@@ -358,7 +364,8 @@ struct BinsWorkspace {
   uint64_t* scan_ws;
   uint32_t* first_cls;
   uint64_t* meta;  // one graph: [0] vertices of degree >= kRowsDirect, [1] their first
-                   // position, [2] classes of lower degree
+                   // position, [2] classes of lower degree, [3] 1 if the pass by
+                   // degree gave up waiting between tiles
   void* radix;
 };
 
@@ -417,6 +424,9 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
     }
     if ((rc = onesweep_rows(RowSink{d_rowptr, ix.vlist, ix.vrow, w.keys_a}, n, osc, st)))
       return rc;
+    // the sort below clears the stall count: keep this pass's in meta[3]
+    if ((rc = fill<uint64_t>(w.meta + 3, 1, 0, st))) return rc;
+    if ((rc = os_flag_stalls(osc, w.meta + 3, 1, st))) return rc;
     k_rows_classes<<<1, 256, 0, st>>>(osc.hist, osc.base, cap, ix, w.meta);
     WEDGE_LAUNCH_CHECK("k_rows_classes");
     // vertices of degree >= kRowsDirect: at most 2m / kRowsDirect of them
@@ -474,6 +484,10 @@ int bins_build(const uint64_t* d_rowptr, uint64_t n, uint64_t m_total, const uin
                                                                 G, d_n_b, d_p_b, w.first_cls);
   WEDGE_LAUNCH_CHECK("k_bin_finalize");
   // a sort whose bounded wait gave up leaves overflow = 2^64 - 1
+  if (G == 1 && n > 0) {
+    k_flag_if_set<<<1, 64, 0, st>>>(w.meta + 3, (uint64_t*)&ix.hdr->overflow, ~0ULL);
+    WEDGE_LAUNCH_CHECK("k_flag_if_set");
+  }
   return os_flag_stalls(osc, (uint64_t*)&ix.hdr->overflow, ~0ULL, st);
 }
 
